@@ -1,0 +1,213 @@
+/*
+ * esnufft — type 1 and type 2 nonuniform FFTs on one AMD MI355X (gfx950) GPU
+ * with the "exponential of semicircle" (ES) spreading kernel.
+ *
+ * The transforms approximate, to a requested relative tolerance eps, the
+ * exponential sums of Sec. 1 of Barnett, Magland & af Klinteberg,
+ * "A parallel non-uniform fast Fourier transform library based on an
+ * 'exponential of semicircle' kernel" (arXiv:1808.06736):
+ *
+ *   type 1 (eq. (1)):  f_k = sum_{j=1..M} c_j exp(isign * i k.x_j),  k in I
+ *   type 2 (eq. (2)):  c_j = sum_{k in I} f_k exp(isign * i k.x_j),  j = 1..M
+ *
+ * with d = 1, 2 or 3, mode set I = I_{N1} x ... x I_{Nd},
+ * I_N = {-floor(N/2), ..., -floor(N/2) + N - 1}, points x_j anywhere in
+ * [-3pi, 3pi]^d (the sums are 2pi-periodic in each coordinate), complex c_j, f_k.
+ * No normalisation.  The method (Sec. 3): spread onto an upsampled fine grid
+ * with the ES kernel phi(z) = exp(beta(sqrt(1 - z^2) - 1)) (eq. (ES)), FFT, and
+ * divide by the kernel's Fourier transform (eqs. (pb1), (pk)); type 2 runs the
+ * steps in reverse (Sec. 3.2).
+ *
+ * Memory: every data pointer below is a DEVICE pointer (hipMalloc'd or a
+ * torch CUDA tensor's data_ptr) unless the argument says "host".  The caller
+ * owns x, y, z, c and f; the library reads/writes them only during the call
+ * that receives them.  esn_setpts copies the points, bin-sorted and rescaled,
+ * into plan-owned device memory, so the caller may free or overwrite the
+ * coordinate arrays once it returns.  The plan owns its fine grid, correction
+ * factors, sort arrays, rocFFT plan and work buffer until esn_destroy.
+ *
+ * Layouts: complex data are interleaved (re, im) pairs of float (ESN_SINGLE)
+ * or double (ESN_DOUBLE).  Strengths c are [ntransf][M].  Mode arrays f are
+ * [ntransf][N3][N2][N1] (N1 fastest); within a dimension the modes run in
+ * increasing k from -floor(N/2) (modeord 0) or in FFT order 0,1,..,-1
+ * (modeord 1).  Outputs are overwritten, never accumulated.
+ *
+ * Streams: all work of a plan is enqueued on the hipStream_t given to
+ * esn_makeplan (NULL = the null stream).  Calls return once the work is
+ * enqueued, except where stated; errors found on the host are returned
+ * before anything is enqueued.  One plan must not be used from two host
+ * threads at once.
+ *
+ * Status codes: 0 = success, 1 = warning (computed, but eps is beyond what
+ * the precision supports), >= 2 = error (nothing was computed).
+ */
+#ifndef ESNUFFT_H
+#define ESNUFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- precision codes ---------------------------------------------------- */
+#define ESN_SINGLE 1 /* complex64 data, FP32 spread/interp/FFT */
+#define ESN_DOUBLE 2 /* complex128 data, FP64 everywhere */
+
+/* ---- status codes -------------------------------------------------------- */
+#define ESN_OK 0
+#define ESN_WARN_EPS_TOO_SMALL 1   /* eps < 1e-6 in single or < 1e-15; w clamped */
+#define ESN_ERR_BAD_ARG 2          /* invalid type, dim, sizes, sign, pointer */
+#define ESN_ERR_PTS_OUT_OF_RANGE 3 /* chkbnds: a coordinate outside [-3pi, 3pi] */
+#define ESN_ERR_NAN_PTS 4          /* a coordinate is NaN or infinite */
+#define ESN_ERR_BUDGET 5           /* request exceeds the HBM budget */
+#define ESN_ERR_ALLOC 6            /* device allocation failed */
+#define ESN_ERR_FFT_PLAN 7         /* rocFFT refused the plan */
+#define ESN_ERR_HIP 8              /* a HIP runtime call failed */
+#define ESN_ERR_UNSUPPORTED 9      /* a valid request this build does not do */
+#define ESN_ERR_NO_POINTS 10       /* execute before setpts */
+#define ESN_ERR_QUEUE 11           /* server: unknown ticket or server stopped */
+
+/* ---- options (paper Sec. 2: an opts struct with defaults) ----------------- */
+typedef struct esn_opts {
+  int debug;          /* 1: time each stage with HIP events (esn_get_stats) */
+  int chkbnds;        /* 1: setpts rejects coordinates outside [-3pi, 3pi] */
+  int modeord;        /* 0: increasing k from -floor(N/2); 1: FFT order */
+  double upsampfac;   /* fine grid / modes ratio sigma; only 2.0 is supported */
+  int sort;           /* 1 (default): bin-sort points (Sec. 4.1); 0: keep order */
+  int spread_method;  /* 0 auto; 1 LDS tile per subproblem; 2 global atomics */
+  int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather */
+  int bin[3];         /* bin size in fine-grid cells per dim; 0 = default */
+  int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default */
+  int ntransf_chunk;  /* transforms per fused launch; 0 = as many as fit */
+  int block;          /* threads per workgroup for spread/interp; 0 = 256 */
+} esn_opts;
+
+/* Fill *o with the defaults (debug 0, chkbnds 1, modeord 0, upsampfac 2.0,
+ * sort 1, everything else 0 = automatic). */
+void esn_default_opts(esn_opts* o);
+
+/* ---- parameter choice (host only, no GPU needed) --------------------------- */
+typedef struct esn_params {
+  int w;             /* kernel width in fine-grid cells, eq. (params) */
+  double beta;       /* ES shape parameter 2.30 w, eq. (params) */
+  int nquad;         /* positive Gauss-Legendre nodes p >= 1.5 w + 2 (Sec. 3.1) */
+  int64_t nf[3];     /* fine grid per dim: smallest 2^a 3^b 5^c >= max(2N, 2w) */
+} esn_params;
+
+/* Kernel and grid parameters for tolerance eps (Sec. 3, eq. (params) and
+ * Sec. 3.1): w = ceil(log10(1/eps)) + 1 clamped to [2, 16], beta = 2.30 w,
+ * n_i = smallest 2^a 3^b 5^c >= max(sigma N_i, 2w) (unused dims: 1).
+ * nmodes: host array of 3 (entries beyond dim ignored).
+ * Returns ESN_OK, ESN_WARN_EPS_TOO_SMALL or ESN_ERR_BAD_ARG. */
+int esn_choose_params(double eps, int prec, int dim, const int64_t* nmodes,
+                      double upsampfac, esn_params* out);
+
+/* The p positive nodes (decreasing) and their weights of the 2p-node
+ * Gauss-Legendre rule on [-1, 1], FP64 Newton iteration on P_2p (the rule of
+ * eq. (quad)).  nodes, weights: host arrays of p >= 1.  Host only. */
+int esn_gauss_legendre(int p, double* nodes, double* weights);
+
+/* Host FP64 twin of the GPU correction factors of one dimension:
+ * out[k] = 1 / (w sum_{j<=p} w_j phi(q_j) cos(alpha k q_j)), k = 0..floor(N/2),
+ * alpha = pi w / nf, p = nquad (eqs. (pk1), (quad)).  out: host array of
+ * floor(N/2) + 1 doubles.  Host only; used to check the GPU values. */
+int esn_correction_factors(int w, double beta, int nquad, int64_t nf, int64_t N, double* out);
+
+/* ---- plan interface -------------------------------------------------------- */
+typedef struct esn_plan_s* esn_plan;
+
+/* Make a plan for ntransf transforms of one type that share one point set
+ * (Sec. 2, remark on repeated small problems: a plan stage and multiple
+ * inputs).  type 1 or 2; dim 1..3; nmodes host[3] (N_i >= 1); isign +1/-1;
+ * ntransf >= 1; prec ESN_SINGLE/ESN_DOUBLE; opts may be NULL (defaults);
+ * stream is a hipStream_t or NULL.  Computes the correction factors p_k
+ * (eqs. (pk1), (quad), (pk)) on the GPU in FP64 and builds the rocFFT plan.
+ * Synchronises the stream before returning.  *out is NULL on error. */
+int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntransf,
+                 double eps, int prec, esn_plan* out, const esn_opts* opts,
+                 void* stream);
+
+/* Give the plan M >= 0 points (coordinate arrays x[, y[, z]] of M values,
+ * float if coord_prec == ESN_SINGLE else double; unused dims may be NULL).
+ * Folds each coordinate into [0, 2pi) and rescales it to fine-grid units in
+ * FP64, bin-sorts the points (Sec. 4.1) and builds the subproblem list
+ * (Sec. 4.2).  Synchronises the stream (it reads back the subproblem count
+ * and the bounds/NaN flags).  On ESN_ERR_NAN_PTS or (with chkbnds)
+ * ESN_ERR_PTS_OUT_OF_RANGE the plan is left without points, so a following
+ * esn_execute returns ESN_ERR_NO_POINTS until a successful esn_setpts. */
+int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
+               const void* z);
+
+/* Run the transforms.  type 1: reads c [ntransf][M], writes f
+ * [ntransf][N3][N2][N1] (steps of Sec. 3.1: spread eq. (bl), FFT eq. (dft1),
+ * truncate and correct eq. (pb1)); type 2: reads f, writes c (Sec. 3.2:
+ * amplify and zero-pad, FFT eq. (dft), interpolate eq. (interp)).
+ * Asynchronous on the plan's stream. */
+int esn_execute(esn_plan p, void* c, void* f);
+
+/* The spreading step alone, eq. (bl): grid[t] = sum_j c[t][j] psi~(l h - x_j)
+ * for the plan's points, into a caller buffer of ntransf * n1*n2*n3 complex
+ * values (n1 fastest, fine-grid cell l at l*h).  Type 1 plans only. */
+int esn_spread(esn_plan p, const void* c, void* grid);
+
+/* The interpolation step alone, eq. (interp): c[t][j] = sum_l grid[t][l]
+ * psi~(l h - x_j).  Type 2 plans only. */
+int esn_interp(esn_plan p, const void* grid, void* c);
+
+typedef struct esn_info {
+  int type, dim, isign, ntransf, prec, w, nquad, modeord;
+  double beta, eps;
+  int64_t nmodes[3], nf[3], M;
+  int bin[3], maxsubprob, nsubprob, nbins_nonempty, ntransf_chunk;
+  int spread_method, interp_method, point_code; /* point_code 1: fixed point u32, 2: f64 */
+  int64_t device_bytes;  /* device memory the plan holds */
+} esn_info;
+
+/* Describe a plan (host struct filled). */
+int esn_get_info(esn_plan p, esn_info* out);
+
+typedef struct esn_stats {
+  /* milliseconds of the last setpts / execute, by stage (debug = 1 only) */
+  double t_setpts, t_spread_or_interp, t_fft, t_deconv_or_amplify, t_execute;
+} esn_stats;
+
+/* Copy the plan's GPU-computed correction factors of dimension m (0-based,
+ * floor(N_m/2) + 1 doubles) into the host array out of length len.
+ * Synchronises the plan's stream. */
+int esn_plan_correction(esn_plan p, int m, double* out, int64_t len);
+
+/* Per-stage times of the last calls; requires opts.debug = 1.  Synchronises. */
+int esn_get_stats(esn_plan p, esn_stats* out);
+
+/* Free everything the plan owns (waits for its stream first).  NULL is ok. */
+int esn_destroy(esn_plan p);
+
+/* ---- one-shot calls in the paper's style (Sec. 2: status = finufft1d1(...)) */
+/* Coordinates are device doubles; c and f device complex of precision prec;
+ * opts may be NULL; stream as above.  Each call plans, sets points, executes
+ * and destroys; it returns after the result is complete. */
+int esn_1d1(int64_t M, const double* x, const void* c, int isign, double eps,
+            int64_t N1, void* f, int prec, const esn_opts* opts, void* stream);
+int esn_1d2(int64_t M, const double* x, void* c, int isign, double eps, int64_t N1,
+            const void* f, int prec, const esn_opts* opts, void* stream);
+int esn_2d1(int64_t M, const double* x, const double* y, const void* c, int isign,
+            double eps, int64_t N1, int64_t N2, void* f, int prec,
+            const esn_opts* opts, void* stream);
+int esn_2d2(int64_t M, const double* x, const double* y, void* c, int isign,
+            double eps, int64_t N1, int64_t N2, const void* f, int prec,
+            const esn_opts* opts, void* stream);
+int esn_3d1(int64_t M, const double* x, const double* y, const double* z,
+            const void* c, int isign, double eps, int64_t N1, int64_t N2,
+            int64_t N3, void* f, int prec, const esn_opts* opts, void* stream);
+int esn_3d2(int64_t M, const double* x, const double* y, const double* z, void* c,
+            int isign, double eps, int64_t N1, int64_t N2, int64_t N3,
+            const void* f, int prec, const esn_opts* opts, void* stream);
+
+/* Text for a status code (static string). */
+const char* esn_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESNUFFT_H */

@@ -1,0 +1,392 @@
+"""ctypes binding of libesnufft.so (the C ABI in include/esnufft.h).
+
+Argument marshalling only: every step of the transforms runs in the HIP
+library.  The ``esn_*`` functions mirror the C entry points one to one (device
+pointers are plain integers); ``Plan`` is a thin convenience wrapper that takes
+torch CUDA tensors, passes their ``data_ptr()`` and torch's current stream, and
+raises on error statuses.  There is no CPU fallback: without the built library
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libesnufft.so")
+
+ESN_SINGLE = 1
+ESN_DOUBLE = 2
+
+STATUS = {
+    0: "ESN_OK", 1: "ESN_WARN_EPS_TOO_SMALL", 2: "ESN_ERR_BAD_ARG",
+    3: "ESN_ERR_PTS_OUT_OF_RANGE", 4: "ESN_ERR_NAN_PTS", 5: "ESN_ERR_BUDGET",
+    6: "ESN_ERR_ALLOC", 7: "ESN_ERR_FFT_PLAN", 8: "ESN_ERR_HIP",
+    9: "ESN_ERR_UNSUPPORTED", 10: "ESN_ERR_NO_POINTS", 11: "ESN_ERR_QUEUE",
+}
+for _k, _v in STATUS.items():
+    globals()[_v] = _k
+
+i64 = ctypes.c_int64
+vp = ctypes.c_void_p
+ci = ctypes.c_int
+cd = ctypes.c_double
+
+
+class EsnOpts(ctypes.Structure):
+    _fields_ = [("debug", ci), ("chkbnds", ci), ("modeord", ci), ("upsampfac", cd),
+                ("sort", ci), ("spread_method", ci), ("interp_method", ci),
+                ("bin", ci * 3), ("maxsubprob", ci), ("ntransf_chunk", ci), ("block", ci)]
+
+
+class EsnParams(ctypes.Structure):
+    _fields_ = [("w", ci), ("beta", cd), ("nquad", ci), ("nf", i64 * 3)]
+
+
+class EsnInfo(ctypes.Structure):
+    _fields_ = [("type", ci), ("dim", ci), ("isign", ci), ("ntransf", ci), ("prec", ci),
+                ("w", ci), ("nquad", ci), ("modeord", ci), ("beta", cd), ("eps", cd),
+                ("nmodes", i64 * 3), ("nf", i64 * 3), ("M", i64), ("bin", ci * 3),
+                ("maxsubprob", ci), ("nsubprob", ci), ("nbins_nonempty", ci),
+                ("ntransf_chunk", ci), ("spread_method", ci), ("interp_method", ci),
+                ("point_code", ci), ("device_bytes", i64)]
+
+
+class EsnStats(ctypes.Structure):
+    _fields_ = [("t_setpts", cd), ("t_spread_or_interp", cd), ("t_fft", cd),
+                ("t_deconv_or_amplify", cd), ("t_execute", cd)]
+
+
+class EsnError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({strerror(status)})")
+
+
+_lib = None
+
+# (name, argtypes) of every C entry point; restype int unless noted
+_SIGS = {
+    "esn_default_opts": ([ctypes.POINTER(EsnOpts)], None),
+    "esn_choose_params": ([cd, ci, ci, ctypes.POINTER(i64), cd, ctypes.POINTER(EsnParams)], ci),
+    "esn_makeplan": ([ci, ci, ctypes.POINTER(i64), ci, ci, cd, ci, ctypes.POINTER(vp),
+                      ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_setpts": ([vp, i64, ci, vp, vp, vp], ci),
+    "esn_execute": ([vp, vp, vp], ci),
+    "esn_spread": ([vp, vp, vp], ci),
+    "esn_interp": ([vp, vp, vp], ci),
+    "esn_get_info": ([vp, ctypes.POINTER(EsnInfo)], ci),
+    "esn_get_stats": ([vp, ctypes.POINTER(EsnStats)], ci),
+    "esn_destroy": ([vp], ci),
+    "esn_1d1": ([i64, vp, vp, ci, cd, i64, vp, ci, ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_1d2": ([i64, vp, vp, ci, cd, i64, vp, ci, ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_2d1": ([i64, vp, vp, vp, ci, cd, i64, i64, vp, ci, ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_2d2": ([i64, vp, vp, vp, ci, cd, i64, i64, vp, ci, ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_3d1": ([i64, vp, vp, vp, vp, ci, cd, i64, i64, i64, vp, ci, ctypes.POINTER(EsnOpts),
+                 vp], ci),
+    "esn_3d2": ([i64, vp, vp, vp, vp, ci, cd, i64, i64, i64, vp, ci, ctypes.POINTER(EsnOpts),
+                 vp], ci),
+    "esn_strerror": ([ci], ctypes.c_char_p),
+    "esn_gauss_legendre": ([ci, vp, vp], ci),
+    "esn_correction_factors": ([ci, cd, ci, i64, i64, vp], ci),
+    "esn_plan_correction": ([vp, ci, vp, i64], ci),
+}
+
+
+def lib():
+    """Load libesnufft.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1808_06736_amd.build`")
+        try:
+            # torch ships its own HIP runtime under the same soname; loading torch
+            # first makes this library bind to that one runtime, so torch's
+            # streams and device pointers are valid here.
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().esn_strerror(int(status)).decode()
+    except Exception:          # the library itself failed to load
+        return STATUS.get(status, "unknown")
+
+
+def _i64x3(vals):
+    v = list(vals) + [1] * (3 - len(vals))
+    return (i64 * 3)(*[int(a) for a in v[:3]])
+
+
+# ---- C entry points, same names ------------------------------------------------
+def esn_default_opts() -> EsnOpts:
+    o = EsnOpts()
+    lib().esn_default_opts(ctypes.byref(o))
+    return o
+
+
+def esn_choose_params(eps, prec, dim, nmodes, upsampfac=2.0):
+    out = EsnParams()
+    st = lib().esn_choose_params(float(eps), int(prec), int(dim), _i64x3(nmodes),
+                                 float(upsampfac), ctypes.byref(out))
+    return st, out
+
+
+def esn_makeplan(type_, dim, nmodes, isign, ntransf, eps, prec, opts=None, stream=None):
+    h = vp()
+    st = lib().esn_makeplan(int(type_), int(dim), _i64x3(nmodes), int(isign), int(ntransf),
+                            float(eps), int(prec), ctypes.byref(h),
+                            ctypes.byref(opts) if opts is not None else None, stream)
+    return st, h
+
+
+def esn_setpts(plan, M, coord_prec, x, y=None, z=None):
+    return lib().esn_setpts(plan, int(M), int(coord_prec), x, y, z)
+
+
+def esn_execute(plan, c, f):
+    return lib().esn_execute(plan, c, f)
+
+
+def esn_spread(plan, c, grid):
+    return lib().esn_spread(plan, c, grid)
+
+
+def esn_interp(plan, grid, c):
+    return lib().esn_interp(plan, grid, c)
+
+
+def esn_get_info(plan) -> EsnInfo:
+    info = EsnInfo()
+    st = lib().esn_get_info(plan, ctypes.byref(info))
+    if st:
+        raise EsnError(st, "esn_get_info")
+    return info
+
+
+def esn_get_stats(plan) -> EsnStats:
+    s = EsnStats()
+    st = lib().esn_get_stats(plan, ctypes.byref(s))
+    if st:
+        raise EsnError(st, "esn_get_stats")
+    return s
+
+
+def esn_gauss_legendre(p):
+    """Host arrays (nodes, weights) of the p positive nodes of the 2p-node rule."""
+    import numpy as np
+    q = np.zeros(p)
+    w = np.zeros(p)
+    check(lib().esn_gauss_legendre(int(p), q.ctypes.data, w.ctypes.data), "esn_gauss_legendre")
+    return q, w
+
+
+def esn_correction_factors(w, beta, nquad, nf, N):
+    import numpy as np
+    out = np.zeros(int(N) // 2 + 1)
+    check(lib().esn_correction_factors(int(w), float(beta), int(nquad), int(nf), int(N),
+                                       out.ctypes.data), "esn_correction_factors")
+    return out
+
+
+def esn_plan_correction(plan, m, N_m):
+    import numpy as np
+    out = np.zeros(int(N_m) // 2 + 1)
+    check(lib().esn_plan_correction(plan, int(m), out.ctypes.data, out.shape[0]),
+          "esn_plan_correction")
+    return out
+
+
+def esn_destroy(plan):
+    return lib().esn_destroy(plan)
+
+
+def _oneshot(name, *args):
+    return getattr(lib(), name)(*args)
+
+
+def esn_1d1(M, x, c, isign, eps, N1, f, prec, opts=None, stream=None):
+    return _oneshot("esn_1d1", M, x, c, isign, eps, N1, f, prec, opts, stream)
+
+
+def esn_1d2(M, x, c, isign, eps, N1, f, prec, opts=None, stream=None):
+    return _oneshot("esn_1d2", M, x, c, isign, eps, N1, f, prec, opts, stream)
+
+
+def esn_2d1(M, x, y, c, isign, eps, N1, N2, f, prec, opts=None, stream=None):
+    return _oneshot("esn_2d1", M, x, y, c, isign, eps, N1, N2, f, prec, opts, stream)
+
+
+def esn_2d2(M, x, y, c, isign, eps, N1, N2, f, prec, opts=None, stream=None):
+    return _oneshot("esn_2d2", M, x, y, c, isign, eps, N1, N2, f, prec, opts, stream)
+
+
+def esn_3d1(M, x, y, z, c, isign, eps, N1, N2, N3, f, prec, opts=None, stream=None):
+    return _oneshot("esn_3d1", M, x, y, z, c, isign, eps, N1, N2, N3, f, prec, opts, stream)
+
+
+def esn_3d2(M, x, y, z, c, isign, eps, N1, N2, N3, f, prec, opts=None, stream=None):
+    return _oneshot("esn_3d2", M, x, y, z, c, isign, eps, N1, N2, N3, f, prec, opts, stream)
+
+
+def check(status, where=""):
+    """Raise EsnError for error statuses; warn for status 1."""
+    if status >= 2:
+        raise EsnError(status, where)
+    if status == 1:
+        warnings.warn(f"{where}: {strerror(1)}", RuntimeWarning, stacklevel=3)
+    return status
+
+
+# ---- torch convenience wrapper --------------------------------------------------
+def _stream_handle(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(**kw) -> EsnOpts:
+    o = esn_default_opts()
+    for k, v in kw.items():
+        if k == "bin":
+            for m, b in enumerate(list(v) + [0] * (3 - len(v))):
+                o.bin[m] = int(b)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Plan:
+    """A type 1 or type 2 plan over torch CUDA tensors.
+
+    ``Plan(type_, N, eps, dtype=torch.complex64, isign=None, ntransf=1, **opts)``
+    with N a tuple of 1..3 mode counts (N1 first).  isign defaults to +1 for
+    type 1 and -1 for type 2.  Work is enqueued on torch's current stream.
+    """
+
+    def __init__(self, type_, N, eps, dtype=None, isign=None, ntransf=1, **opts):
+        import torch
+        self.torch = torch
+        self.type = int(type_)
+        self.N = tuple(int(n) for n in N)
+        self.dim = len(self.N)
+        self.dtype = dtype or torch.complex64
+        if self.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.prec = ESN_SINGLE if self.dtype == torch.complex64 else ESN_DOUBLE
+        self.isign = isign if isign is not None else (1 if self.type == 1 else -1)
+        self.ntransf = int(ntransf)
+        self.eps = float(eps)
+        self.opts = make_opts(**opts)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        st, h = esn_makeplan(self.type, self.dim, self.N, self.isign, self.ntransf, self.eps,
+                             self.prec, self.opts, _stream_handle(torch))
+        check(st, "esn_makeplan")
+        self.handle = h
+        self.M = None
+
+    def info(self) -> EsnInfo:
+        return esn_get_info(self.handle)
+
+    def stats(self) -> EsnStats:
+        return esn_get_stats(self.handle)
+
+    def setpts(self, *coords):
+        torch = self.torch
+        if len(coords) != self.dim:
+            raise ValueError(f"need {self.dim} coordinate arrays")
+        M = coords[0].numel()
+        cdt = coords[0].dtype
+        if cdt not in (torch.float32, torch.float64):
+            raise ValueError("coordinates must be float32 or float64")
+        ptrs = []
+        for a in coords:
+            if a.dtype != cdt or a.numel() != M or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("coordinates: same dtype, same length, contiguous, on the GPU")
+            ptrs.append(vp(a.data_ptr()) if M > 0 else None)
+        ptrs += [None] * (3 - len(ptrs))
+        st = esn_setpts(self.handle, M, ESN_SINGLE if cdt == torch.float32 else ESN_DOUBLE,
+                        *ptrs)
+        check(st, "esn_setpts")
+        self.M = M
+        return self
+
+    def _shape_c(self):
+        return (self.ntransf, self.M) if self.ntransf > 1 else (self.M,)
+
+    def _shape_f(self):
+        Nrev = tuple(reversed(self.N))
+        return ((self.ntransf,) + Nrev) if self.ntransf > 1 else Nrev
+
+    def _check(self, t, shape, name):
+        if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: must be a contiguous {self.dtype} CUDA tensor")
+        if t.numel() != int(__import__("math").prod(shape)):
+            raise ValueError(f"{name}: expected {shape} elements, got {tuple(t.shape)}")
+
+    def execute(self, c, f):
+        if self.M is None:
+            raise EsnError(ESN_ERR_NO_POINTS, "execute")
+        self._check(c, self._shape_c(), "c")
+        self._check(f, self._shape_f(), "f")
+        st = esn_execute(self.handle, vp(c.data_ptr()) if c.numel() else None,
+                         vp(f.data_ptr()))
+        check(st, "esn_execute")
+        return c, f
+
+    def type1(self, c, out=None):
+        f = out if out is not None else self.torch.empty(self._shape_f(), dtype=self.dtype,
+                                                         device=self.device)
+        self.execute(c, f)
+        return f
+
+    def type2(self, f, out=None):
+        c = out if out is not None else self.torch.empty(self._shape_c(), dtype=self.dtype,
+                                                         device=self.device)
+        self.execute(c, f)
+        return c
+
+    def fine_grid_shape(self):
+        info = self.info()
+        nf = [int(info.nf[m]) for m in range(self.dim)]
+        return ((self.ntransf,) if self.ntransf > 1 else ()) + tuple(reversed(nf))
+
+    def spread(self, c, grid=None):
+        grid = grid if grid is not None else self.torch.empty(self.fine_grid_shape(),
+                                                              dtype=self.dtype,
+                                                              device=self.device)
+        self._check(c, self._shape_c(), "c")
+        check(esn_spread(self.handle, vp(c.data_ptr()) if c.numel() else None,
+                         vp(grid.data_ptr())), "esn_spread")
+        return grid
+
+    def interp(self, grid, c=None):
+        c = c if c is not None else self.torch.empty(self._shape_c(), dtype=self.dtype,
+                                                      device=self.device)
+        check(esn_interp(self.handle, vp(grid.data_ptr()), vp(c.data_ptr()) if c.numel() else None),
+              "esn_interp")
+        return c
+
+    def close(self):
+        if getattr(self, "handle", None):
+            esn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

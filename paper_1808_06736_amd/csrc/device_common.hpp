@@ -1,0 +1,109 @@
+// Device helpers shared by the spread / interp kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "esn_internal.hpp"
+
+namespace esn {
+
+template <typename T> struct CT;                    // complex type of precision T
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+template <typename T> using cplx_t = typename CT<T>::type;
+
+// A sorted point's coordinate in one dimension, split into the fine-grid cell
+// c = floor(t) (c in [0, n)) and the offset within it, f = t - c in [0, 1).
+template <typename T>
+struct Coord {
+  int cell;
+  T f;
+};
+
+template <typename T>
+__device__ __forceinline__ Coord<T> decode_coord(const void* base, int code, int fbits,
+                                                 int64_t i, int* sh_out, int w) {
+  Coord<T> r;
+  if (code == kPtsFixed32) {
+    uint32_t v = static_cast<const uint32_t*>(base)[i];
+    uint32_t mask = (fbits >= 32) ? 0xffffffffu : ((1u << fbits) - 1u);
+    uint32_t fr = v & mask;
+    r.cell = (int)(fbits >= 32 ? 0u : (v >> fbits));
+    // the fraction fr * 2^-fbits (exact in float when fbits <= 24)
+    if constexpr (sizeof(T) == 4) r.f = ldexpf((float)fr, -fbits);
+    else r.f = ldexp((double)fr, -fbits);
+    // window shift sh (see the window comment below), decided on the exact bits
+    if (w & 1) {
+      uint32_t half = 1u << (fbits - 1);
+      *sh_out = fr > half ? 1 : 0;
+    } else {
+      *sh_out = fr != 0u ? 1 : 0;
+    }
+  } else {
+    double t = static_cast<const double*>(base)[i];
+    double c = floor(t);
+    double f = t - c;                      // exact in FP64
+    r.cell = (int)c;
+    r.f = (T)f;
+    if (w & 1) *sh_out = f > 0.5 ? 1 : 0;
+    else *sh_out = f > 0.0 ? 1 : 0;
+  }
+  return r;
+}
+
+// Window of a point at fine-grid coordinate t = c + f: the w cells
+// l0 .. l0 + w - 1 with l0 = ceil(t - w/2) = c - floor(w/2) + sh, where
+// sh in {0, 1} is decided exactly from f (w even: f > 0; w odd: f > 1/2).
+// When t - w/2 is an integer the left end of the closed support (z = -1) is
+// the first window cell and the right end (z = +1) is left out.
+//
+// ES kernel values at the window, eq. (ES) rescaled by alpha = w h / 2
+// (eqs. (al), (psi1)):  ker[k] = phi((l0 + k - t) / (w/2)),
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)).
+template <int W>
+__device__ __forceinline__ void es_weights_f32(int sh, float f, float beta, float* ker) {
+  // offset of the first window cell from t, in [-W/2, -W/2 + 1]
+  const float off = (float)(sh - W / 2) - f;
+  const float s = 2.0f / (float)W;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    float z = (off + (float)k) * s;
+    float a = fmaxf(1.0f - z * z, 0.0f);
+    ker[k] = __expf(beta * (__fsqrt_rn(a) - 1.0f));
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void es_weights_f64(int sh, double f, double beta, double* ker) {
+  const double off = (double)(sh - W / 2) - f;
+  const double s = 2.0 / (double)W;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    double z = (off + (double)k) * s;
+    double a = fmax(1.0 - z * z, 0.0);
+    ker[k] = exp(beta * (sqrt(a) - 1.0));
+  }
+}
+
+template <int W, typename T>
+__device__ __forceinline__ void es_weights_t(int sh, T f, T beta, T* ker) {
+  if constexpr (sizeof(T) == 4) es_weights_f32<W>(sh, f, beta, ker);
+  else es_weights_f64<W>(sh, f, beta, ker);
+}
+
+// Periodic wrap of an index that lies in [-n, 2n).
+__device__ __forceinline__ int64_t wrap_once(int64_t g, int64_t n) {
+  if (g < 0) g += n;
+  if (g >= n) g -= n;
+  return g;
+}
+
+// Periodic wrap of any index.
+__device__ __forceinline__ int64_t wrap_any(int64_t g, int64_t n) {
+  g %= n;
+  return g < 0 ? g + n : g;
+}
+
+}  // namespace esn

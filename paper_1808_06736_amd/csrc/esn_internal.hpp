@@ -1,0 +1,184 @@
+// Internal declarations of the esnufft library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/esnufft.h"
+
+namespace esn {
+
+constexpr int kMaxW = 16;        // widest kernel supported (eps ~ 1e-15)
+constexpr int kMaxDim = 3;
+
+// ---- host plan math (params.cpp) ----
+bool width_from_eps(double eps, int* w_out);
+int64_t next_smooth235(int64_t n);
+int64_t fine_size(int64_t N, double sigma, int w);
+void gauss_legendre_positive(int p, std::vector<double>* nodes,
+                             std::vector<double>* weights);
+int quad_nodes_for_width(int w);
+
+// Point storage codes: how a sorted point's fine-grid coordinate t in [0, n)
+// is kept per dimension.
+//   kPtsFixed32: unsigned fixed point t * 2^F (F = 32 - ceil(log2 n) fraction
+//                bits), used by single-precision plans on grids up to 8192;
+//   kPtsF64:     the double t itself.
+enum { kPtsFixed32 = 1, kPtsF64 = 2 };
+
+// Everything a spread/interp kernel needs about the geometry and the sorted
+// points.  Passed by value.
+struct GeomArgs {
+  int64_t n[3];          // fine grid per dim (1 for unused dims)
+  int b[3];              // bin size per dim (1 for unused dims)
+  int nb[3];             // bins per dim
+  int fbits[3];          // fixed-point fraction bits per dim
+  int pts_code;          // kPtsFixed32 or kPtsF64
+  double beta;           // ES shape parameter
+  int64_t M;             // number of points
+  int ntr;               // transforms in this launch
+  int64_t cstride;       // elements between transforms in c (= M)
+  int64_t gstride;       // elements between transforms in the grid
+  const void* t[3];      // sorted coordinates per dim
+  const int32_t* perm;   // sorted position -> original point index
+  const int32_t* sub_bin;    // subproblem -> bin
+  const int32_t* sub_start;  // subproblem -> first sorted position
+  const int32_t* sub_len;    // subproblem -> number of points
+};
+
+// ---- kernel launchers (kernels_*.hip) ----
+// All return hipSuccess or the launch error.
+hipError_t launch_fseries(int w, double beta, const double* d_nodes,
+                          const double* d_weights, int nquad, int64_t nf, int64_t N,
+                          double* d_out, hipStream_t s);
+
+hipError_t launch_deconv(int prec, int dim, const int64_t* N, const int64_t* nf,
+                         int modeord, int ntr, const void* grid, int64_t gstride,
+                         void* f, int64_t fstride, const double* const* pf,
+                         hipStream_t s);
+hipError_t launch_amplify(int prec, int dim, const int64_t* N, const int64_t* nf,
+                          int modeord, int ntr, void* grid, int64_t gstride,
+                          const void* f, int64_t fstride, const double* const* pf,
+                          hipStream_t s);
+
+// Sorting / binning (kernels_sort.hip).
+struct SortArgs {
+  int dim;
+  int64_t M;
+  int coord_prec;           // ESN_SINGLE / ESN_DOUBLE
+  const void* x[3];         // caller's coordinates
+  int64_t n[3];
+  int b[3], nb[3], fbits[3];
+  int pts_code;
+  int chkbnds;
+  int32_t* keybin;          // [M]
+  int32_t* slot;            // [M]
+  int32_t* count;           // [nbins]
+  int32_t* start;           // [nbins]
+  int32_t* perm;            // [M]
+  void* t[3];               // [M] each (sorted storage)
+  int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
+};
+hipError_t launch_bin_count(const SortArgs& a, hipStream_t s);
+hipError_t launch_scatter(const SortArgs& a, hipStream_t s);
+hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
+// Exclusive scan of n int32 values (in -> out, may not alias); tmp must hold
+// scan_tmp_elems(n) int32.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n,
+                              int32_t* tmp, hipStream_t s);
+// nsub[b] = ceil(count[b] / maxsub); *nonempty (device) is incremented per nonempty bin.
+hipError_t launch_subprob_count(const int32_t* count, int32_t* nsub, int64_t nbins,
+                                int maxsub, int32_t* nonempty, hipStream_t s);
+hipError_t launch_subprob_fill(const int32_t* count, const int32_t* start,
+                               const int32_t* nsub, const int32_t* subofs,
+                               int64_t nbins, int maxsub, int32_t* sub_bin,
+                               int32_t* sub_start, int32_t* sub_len, hipStream_t s);
+hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
+
+// Spread / interp (kernels_spread.hip, kernels_interp.hip).
+// method 1: LDS tile per subproblem (grid = nsub workgroups);
+// method 2: one thread per point with global atomics / direct gathers.
+hipError_t launch_spread(int method, int prec, int dim, int w, const GeomArgs& g,
+                         int nsub, int block, size_t lds_bytes, const void* c,
+                         void* grid, hipStream_t s);
+hipError_t launch_interp(int method, int prec, int dim, int w, const GeomArgs& g,
+                         int nsub, int block, size_t lds_bytes, const void* grid,
+                         void* c, hipStream_t s);
+// LDS bytes one subproblem tile needs for ntr transforms.
+size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr);
+
+// ---- rocFFT wrapper (fft.cpp) ----
+struct FFTPlan {
+  rocfft_plan plan = nullptr;
+  rocfft_execution_info info = nullptr;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+int fft_make(FFTPlan* p, int dim, const int64_t* nf, int batch, int prec,
+             int sign, hipStream_t s);
+int fft_exec(FFTPlan* p, void* data);
+void fft_destroy(FFTPlan* p);
+
+}  // namespace esn
+
+// The plan object behind esn_plan.
+struct esn_plan_s {
+  int type, dim, isign, ntransf, prec;
+  int64_t N[3], nf[3];
+  double eps;
+  esn_params par;
+  esn_opts opts;
+  hipStream_t stream;
+  int device;
+  int warn;                      // status to return for eps warnings
+
+  // correction factors p_k per dim, FP64, k = 0..floor(N/2)
+  double* d_pf[3] = {nullptr, nullptr, nullptr};
+  // fine grid(s): chunk * nf1 nf2 nf3 complex
+  void* d_grid = nullptr;
+  int chunk = 1;                 // transforms per fused launch
+  esn::FFTPlan fft;
+  esn::FFTPlan fft_tail;         // plan for the last, shorter chunk (if any)
+  int tail = 0;
+
+  // binning geometry
+  int bin[3] = {1, 1, 1};
+  int nb[3] = {1, 1, 1};
+  int64_t nbins = 1;
+  int maxsub = 1024;
+  int spread_method = 1, interp_method = 1;
+  int block = 256;
+  int pts_code = esn::kPtsFixed32;
+  int fbits[3] = {0, 0, 0};
+
+  // points
+  int64_t M = -1;                // -1: no points yet
+  int64_t cap_M = 0;
+  void* d_t[3] = {nullptr, nullptr, nullptr};
+  int32_t* d_perm = nullptr;
+  int32_t* d_keybin = nullptr;
+  int32_t* d_slot = nullptr;
+  int32_t* d_count = nullptr;
+  int32_t* d_start = nullptr;
+  int32_t* d_nsub = nullptr;
+  int32_t* d_subofs = nullptr;
+  int32_t* d_scan_tmp = nullptr;
+  int32_t* d_flags = nullptr;
+  int32_t* d_sub_bin = nullptr;
+  int32_t* d_sub_start = nullptr;
+  int32_t* d_sub_len = nullptr;
+  int64_t cap_sub = 0;
+  int nsub = 0;
+  int nbins_nonempty = 0;
+  int32_t* h_pinned = nullptr;   // small pinned host buffer for read-backs
+
+  // debug timing
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  esn_stats stats{};
+  int64_t device_bytes = 0;
+  std::vector<std::pair<void*, size_t>> allocs;   // live device allocations
+};

@@ -1,0 +1,277 @@
+// Bin sort of the nonuniform points (Sec. 4.1, an "incomplete" histogram
+// sort) and the subproblem list for spreading (Sec. 4.2).
+//
+//   bin_count : fold each coordinate into [0, 2pi), rescale to fine-grid units
+//               t = x n / 2pi (FP64), take the bin of floor(t), and count the
+//               point into its bin; the count before the increment is the
+//               point's slot within the bin.
+//   scan      : exclusive prefix sum of the counts = each bin's first position.
+//   scatter   : place point j at start[bin] + slot, storing its permutation
+//               entry and its rescaled coordinate (no order inside a bin).
+//   subprob   : split each bin into runs of at most maxsub points.
+#include "device_common.hpp"
+
+namespace esn {
+
+constexpr double kInvTwoPi = 0.15915494309189533577;  // 1 / (2 pi)
+constexpr double kThreePi = 9.42477796076937971539;   // 3 pi
+
+// Fold x into [0, 2pi) and rescale to t = x n / 2pi in [0, n), in FP64.
+__device__ __forceinline__ double fold_rescale(double x, int64_t n) {
+  const double dn = (double)n;
+  double t = x * (dn * kInvTwoPi);
+  t -= dn * floor(t / dn);
+  if (t < 0.0) t += dn;
+  if (t >= dn) t -= dn;
+  if (!(t >= 0.0 && t < dn)) t = 0.0;
+  return t;
+}
+
+// Encode t for storage; returns the cell floor(t) that the stored value decodes to.
+__device__ __forceinline__ int encode_t(double t, int64_t n, int code, int fbits,
+                                        uint32_t* q_out, double* t_out) {
+  if (code == kPtsFixed32) {
+    const uint64_t span = (uint64_t)n << fbits;
+    uint64_t q = (uint64_t)llrint(ldexp(t, fbits));
+    if (q >= span) q -= span;
+    *q_out = (uint32_t)q;
+    return (int)(q >> fbits);
+  }
+  *t_out = t;
+  return (int)floor(t);
+}
+
+template <typename CTy>
+__device__ __forceinline__ double load_coord(const void* p, int64_t j) {
+  return (double)static_cast<const CTy*>(p)[j];
+}
+
+template <typename CTy>
+__device__ __forceinline__ int point_bin(const SortArgs& a, int64_t j, int* flag,
+                                         uint32_t* q, double* t) {
+  int bin = 0, mult = 1;
+  for (int m = 0; m < a.dim; m++) {
+    const double x = load_coord<CTy>(a.x[m], j);
+    if (!isfinite(x)) *flag |= 1;
+    else if (a.chkbnds && fabs(x) > kThreePi) *flag |= 2;
+    const double tt = isfinite(x) ? fold_rescale(x, a.n[m]) : 0.0;
+    const int cell = encode_t(tt, a.n[m], a.pts_code, a.fbits[m], &q[m], &t[m]);
+    bin += mult * (cell / a.b[m]);
+    mult *= a.nb[m];
+  }
+  return bin;
+}
+
+template <typename CTy>
+__global__ void bin_count_kernel(const SortArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.M) return;
+  int flag = 0;
+  uint32_t q[3];
+  double t[3];
+  const int bin = point_bin<CTy>(a, j, &flag, q, t);
+  if (flag) atomicOr(a.flags, flag);
+  a.keybin[j] = bin;
+  a.slot[j] = atomicAdd(&a.count[bin], 1);
+}
+
+template <typename CTy>
+__global__ void scatter_kernel(const SortArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.M) return;
+  int flag = 0;
+  uint32_t q[3];
+  double t[3];
+  point_bin<CTy>(a, j, &flag, q, t);
+  const int64_t pos = (int64_t)a.start[a.keybin[j]] + a.slot[j];
+  a.perm[pos] = (int32_t)j;
+  for (int m = 0; m < a.dim; m++) {
+    if (a.pts_code == kPtsFixed32) static_cast<uint32_t*>(a.t[m])[pos] = q[m];
+    else static_cast<double*>(a.t[m])[pos] = t[m];
+  }
+}
+
+template <typename CTy>
+__global__ void encode_unsorted_kernel(const SortArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.M) return;
+  int flag = 0;
+  uint32_t q[3];
+  double t[3];
+  point_bin<CTy>(a, j, &flag, q, t);
+  if (flag) atomicOr(a.flags, flag);
+  a.perm[j] = (int32_t)j;
+  for (int m = 0; m < a.dim; m++) {
+    if (a.pts_code == kPtsFixed32) static_cast<uint32_t*>(a.t[m])[j] = q[m];
+    else static_cast<double*>(a.t[m])[j] = t[m];
+  }
+}
+
+static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_bin_count(const SortArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.coord_prec == ESN_SINGLE)
+    hipLaunchKernelGGL(bin_count_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(bin_count_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const SortArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.coord_prec == ESN_SINGLE)
+    hipLaunchKernelGGL(scatter_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(scatter_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.coord_prec == ESN_SINGLE)
+    hipLaunchKernelGGL(encode_unsorted_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(encode_unsorted_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- exclusive scan of int32 (three phases, recursive over block sums) ----
+constexpr int kScanBS = 256;           // threads per block
+constexpr int kScanIPT = 4;            // items per thread
+constexpr int kScanTile = kScanBS * kScanIPT;
+
+// Inclusive scan of one value per thread across the block; returns the
+// thread's inclusive prefix, *total gets the block sum.
+__device__ __forceinline__ int32_t block_inclusive_scan(int32_t v, int32_t* sh, int32_t* total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBS; off <<= 1) {
+    int32_t add = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  int32_t r = sh[tid];
+  *total = sh[kScanBS - 1];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kScanBS)
+scan_sums_kernel(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ sums) {
+  __shared__ int32_t sh[kScanBS];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+  int32_t s = 0;
+  for (int i = 0; i < kScanIPT; i++)
+    if (base + i < n) s += in[base + i];
+  int32_t total;
+  block_inclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBS)
+scan_apply_kernel(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n,
+                  const int32_t* __restrict__ offsets) {
+  __shared__ int32_t sh[kScanBS];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanIPT;
+  int32_t v[kScanIPT];
+  int32_t s = 0;
+  for (int i = 0; i < kScanIPT; i++) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int32_t total;
+  int32_t incl = block_inclusive_scan(s, sh, &total);
+  int32_t run = incl - s + (offsets ? offsets[blockIdx.x] : 0);
+  for (int i = 0; i < kScanIPT; i++) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= 1) return 0;
+  return 2 * nb + scan_tmp_elems(nb);
+}
+
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(kScanBS), 0, s, in, out, n,
+                       (const int32_t*)nullptr);
+    return hipGetLastError();
+  }
+  int32_t* sums = tmp;
+  int32_t* offs = tmp + nb;
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(kScanBS), 0, s, in, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = exclusive_scan_i32(sums, offs, nb, tmp + 2 * nb, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kScanBS), 0, s, in, out, n,
+                     (const int32_t*)offs);
+  return hipGetLastError();
+}
+
+// ---- subproblems ----
+__global__ void subprob_count_kernel(const int32_t* __restrict__ count, int32_t* __restrict__ nsub,
+                                     int64_t nbins, int maxsub, int32_t* nonempty) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  const int cnt = count[b];
+  nsub[b] = (cnt + maxsub - 1) / maxsub;
+  if (cnt > 0) atomicAdd(nonempty, 1);
+}
+
+__global__ void subprob_fill_kernel(const int32_t* __restrict__ count,
+                                    const int32_t* __restrict__ start,
+                                    const int32_t* __restrict__ nsub,
+                                    const int32_t* __restrict__ subofs, int64_t nbins,
+                                    int maxsub, int32_t* __restrict__ sub_bin,
+                                    int32_t* __restrict__ sub_start,
+                                    int32_t* __restrict__ sub_len) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  const int ns = nsub[b];
+  const int o = subofs[b];
+  const int cnt = count[b];
+  for (int k = 0; k < ns; k++) {
+    sub_bin[o + k] = (int32_t)b;
+    sub_start[o + k] = start[b] + k * maxsub;
+    sub_len[o + k] = min(maxsub, cnt - k * maxsub);
+  }
+}
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+hipError_t launch_subprob_count(const int32_t* count, int32_t* nsub, int64_t nbins, int maxsub,
+                                int32_t* nonempty, hipStream_t s) {
+  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, count,
+                     nsub, nbins, maxsub, nonempty);
+  return hipGetLastError();
+}
+
+hipError_t launch_subprob_fill(const int32_t* count, const int32_t* start, const int32_t* nsub,
+                               const int32_t* subofs, int64_t nbins, int maxsub,
+                               int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, count,
+                     start, nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace esn

@@ -1,0 +1,650 @@
+// Plan object and the C ABI (include/esnufft.h): makeplan / setpts / execute /
+// destroy, the spread-only and interp-only steps, and the one-shot calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "esn_internal.hpp"
+
+using namespace esn;
+
+namespace {
+
+constexpr size_t kLdsBudgetCap = 64 * 1024;   // bytes of LDS one tile may use
+constexpr int64_t kMaxPoints = 2147483647LL;  // int32 permutation indices
+
+size_t csize(int prec) { return prec == ESN_DOUBLE ? 2 * sizeof(double) : 2 * sizeof(float); }
+
+int64_t nf_total(const esn_plan_s* p) { return p->nf[0] * p->nf[1] * p->nf[2]; }
+int64_t n_total(const esn_plan_s* p) { return p->N[0] * p->N[1] * p->N[2]; }
+
+size_t lds_budget(int device) {
+  static int cached_dev = -1;
+  static size_t cached = 0;
+  if (cached_dev != device) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+            hipSuccess ||
+        v <= 0)
+      v = 64 * 1024;
+    cached = (size_t)v;
+    cached_dev = device;
+  }
+  return std::min(cached, kLdsBudgetCap);
+}
+
+int ceil_log2(int64_t n) {
+  int k = 0;
+  while (((int64_t)1 << k) < n) k++;
+  return k;
+}
+
+// Device allocations of a plan, with their sizes kept for accounting.
+int dalloc(esn_plan_s* p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return ESN_ERR_ALLOC;
+  }
+  p->allocs.emplace_back(*ptr, bytes);
+  p->device_bytes += (int64_t)bytes;
+  return ESN_OK;
+}
+
+void dfree(esn_plan_s* p, void** ptr) {
+  if (*ptr) {
+    for (size_t i = 0; i < p->allocs.size(); i++) {
+      if (p->allocs[i].first == *ptr) {
+        p->device_bytes -= (int64_t)p->allocs[i].second;
+        p->allocs.erase(p->allocs.begin() + i);
+        break;
+      }
+    }
+    (void)hipFree(*ptr);
+  }
+  *ptr = nullptr;
+}
+
+#define ESN_HIP(call)                         \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return ESN_ERR_HIP; \
+  } while (0)
+
+#define ESN_TRY(call)               \
+  do {                              \
+    int s_ = (call);                \
+    if (s_ >= 2) return s_;         \
+  } while (0)
+
+void default_bins(int dim, int* b) {
+  if (dim == 1) { b[0] = 1024; b[1] = 1; b[2] = 1; }
+  else if (dim == 2) { b[0] = 32; b[1] = 32; b[2] = 1; }
+  else { b[0] = 8; b[1] = 8; b[2] = 8; }
+}
+
+GeomArgs make_geom(const esn_plan_s* p, int ntr) {
+  GeomArgs g;
+  for (int m = 0; m < 3; m++) {
+    g.n[m] = p->nf[m];
+    g.b[m] = p->bin[m];
+    g.nb[m] = p->nb[m];
+    g.fbits[m] = p->fbits[m];
+    g.t[m] = p->d_t[m];
+  }
+  g.pts_code = p->pts_code;
+  g.beta = p->par.beta;
+  g.M = p->M;
+  g.ntr = ntr;
+  g.cstride = p->M;
+  g.gstride = nf_total(p);
+  g.perm = p->d_perm;
+  g.sub_bin = p->d_sub_bin;
+  g.sub_start = p->d_sub_start;
+  g.sub_len = p->d_sub_len;
+  return g;
+}
+
+void free_points(esn_plan_s* p) {
+  for (int m = 0; m < 3; m++) dfree(p, &p->d_t[m]);
+  dfree(p, (void**)&p->d_perm);
+  dfree(p, (void**)&p->d_keybin);
+  dfree(p, (void**)&p->d_slot);
+  p->cap_M = 0;
+}
+
+void free_subs(esn_plan_s* p) {
+  dfree(p, (void**)&p->d_sub_bin);
+  dfree(p, (void**)&p->d_sub_start);
+  dfree(p, (void**)&p->d_sub_len);
+  p->cap_sub = 0;
+}
+
+void destroy_all(esn_plan_s* p) {
+  (void)hipStreamSynchronize(p->stream);
+  free_points(p);
+  free_subs(p);
+  for (int m = 0; m < 3; m++) dfree(p, (void**)&p->d_pf[m]);
+  dfree(p, &p->d_grid);
+  dfree(p, (void**)&p->d_count);
+  dfree(p, (void**)&p->d_start);
+  dfree(p, (void**)&p->d_nsub);
+  dfree(p, (void**)&p->d_subofs);
+  dfree(p, (void**)&p->d_scan_tmp);
+  dfree(p, (void**)&p->d_flags);
+  if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+  p->h_pinned = nullptr;
+  fft_destroy(&p->fft);
+  fft_destroy(&p->fft_tail);
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" void esn_default_opts(esn_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->debug = 0;
+  o->chkbnds = 1;
+  o->modeord = 0;
+  o->upsampfac = 2.0;
+  o->sort = 1;
+}
+
+extern "C" const char* esn_strerror(int s) {
+  switch (s) {
+    case ESN_OK: return "success";
+    case ESN_WARN_EPS_TOO_SMALL: return "warning: tolerance beyond what the precision supports";
+    case ESN_ERR_BAD_ARG: return "invalid argument";
+    case ESN_ERR_PTS_OUT_OF_RANGE: return "a point coordinate lies outside [-3pi, 3pi]";
+    case ESN_ERR_NAN_PTS: return "a point coordinate is NaN or infinite";
+    case ESN_ERR_BUDGET: return "request exceeds the device memory budget";
+    case ESN_ERR_ALLOC: return "device memory allocation failed";
+    case ESN_ERR_FFT_PLAN: return "rocFFT plan or execution failed";
+    case ESN_ERR_HIP: return "HIP runtime error";
+    case ESN_ERR_UNSUPPORTED: return "unsupported request";
+    case ESN_ERR_NO_POINTS: return "no points set (call esn_setpts first)";
+    case ESN_ERR_QUEUE: return "unknown ticket or server stopped";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntransf,
+                            double eps, int prec, esn_plan* out, const esn_opts* opts,
+                            void* stream) {
+  if (!out) return ESN_ERR_BAD_ARG;
+  *out = nullptr;
+  if (type == 3) return ESN_ERR_UNSUPPORTED;
+  if ((type != 1 && type != 2) || dim < 1 || dim > 3 || !nmodes || ntransf < 1 ||
+      (isign != 1 && isign != -1))
+    return ESN_ERR_BAD_ARG;
+  esn_opts o;
+  if (opts) o = *opts;
+  else esn_default_opts(&o);
+  if (o.modeord != 0 && o.modeord != 1) return ESN_ERR_BAD_ARG;
+  esn_params par;
+  int st = esn_choose_params(eps, prec, dim, nmodes, o.upsampfac, &par);
+  if (st >= 2) return st;
+  for (int m = 0; m < dim; m++)
+    if (nmodes[m] > (int64_t)1 << 30 || par.nf[m] > (int64_t)1 << 31) return ESN_ERR_BAD_ARG;
+  if (o.bin[0] < 0 || o.bin[1] < 0 || o.bin[2] < 0 || o.maxsubprob < 0 ||
+      o.ntransf_chunk < 0 || o.block < 0 || o.block > 1024 ||
+      (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 2 ||
+      o.interp_method < 0 || o.interp_method > 2)
+    return ESN_ERR_BAD_ARG;
+
+  esn_plan_s* p = new (std::nothrow) esn_plan_s();
+  if (!p) return ESN_ERR_ALLOC;
+  p->type = type;
+  p->dim = dim;
+  p->isign = isign;
+  p->ntransf = ntransf;
+  p->prec = prec;
+  p->eps = eps;
+  p->par = par;
+  p->opts = o;
+  p->warn = st;
+  p->stream = (hipStream_t)stream;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return ESN_ERR_HIP;
+  }
+  for (int m = 0; m < 3; m++) {
+    p->N[m] = m < dim ? nmodes[m] : 1;
+    p->nf[m] = par.nf[m];
+  }
+  const int w = par.w;
+
+  // ---- point storage ----
+  bool fixed = prec == ESN_SINGLE;
+  for (int m = 0; m < dim; m++)
+    if (p->nf[m] > 8192) fixed = false;
+  p->pts_code = fixed ? kPtsFixed32 : kPtsF64;
+  for (int m = 0; m < 3; m++) p->fbits[m] = m < dim ? 32 - ceil_log2(p->nf[m]) : 24;
+
+  // ---- bins, subproblems, methods, chunk ----
+  default_bins(dim, p->bin);
+  for (int m = 0; m < dim; m++) {
+    if (o.bin[m] > 0) p->bin[m] = o.bin[m];
+    p->bin[m] = (int)std::min<int64_t>(p->bin[m], p->nf[m]);
+  }
+  const size_t budget = lds_budget(p->device);
+  bool user_bins = o.bin[0] > 0 || o.bin[1] > 0 || o.bin[2] > 0;
+  while (!user_bins && tile_lds_bytes(prec, dim, w, p->bin, 1) > budget) {
+    int mx = 0;
+    for (int m = 1; m < dim; m++)
+      if (p->bin[m] > p->bin[mx]) mx = m;
+    if (p->bin[mx] <= 1) break;
+    p->bin[mx] /= 2;
+  }
+  for (int m = 0; m < 3; m++) {
+    if (m >= dim) p->bin[m] = 1;
+    p->nb[m] = (int)((p->nf[m] + p->bin[m] - 1) / p->bin[m]);
+  }
+  p->nbins = (int64_t)p->nb[0] * p->nb[1] * p->nb[2];
+  if (p->nbins > (int64_t)1 << 30) {
+    delete p;
+    return ESN_ERR_BAD_ARG;
+  }
+  p->maxsub = o.maxsubprob > 0 ? o.maxsubprob : 1024;
+  p->block = o.block > 0 ? o.block : 256;
+  const bool tile_fits = tile_lds_bytes(prec, dim, w, p->bin, 1) <= budget;
+  p->spread_method = o.spread_method ? o.spread_method : (tile_fits ? 1 : 2);
+  p->interp_method = o.interp_method ? o.interp_method : (tile_fits ? 1 : 2);
+  if (!o.sort) p->spread_method = p->interp_method = 2;
+  if (!tile_fits) {
+    if (p->spread_method == 1 || p->interp_method == 1) {
+      delete p;
+      return ESN_ERR_BAD_ARG;   // requested LDS method cannot hold one tile
+    }
+  }
+  const bool uses_lds = (type == 1 && p->spread_method == 1) || (type == 2 && p->interp_method == 1);
+  int chunk = o.ntransf_chunk > 0 ? o.ntransf_chunk : ntransf;
+  if (uses_lds) {
+    size_t one = tile_lds_bytes(prec, dim, w, p->bin, 1);
+    int lim = (int)std::max<size_t>(1, budget / one);
+    if (o.ntransf_chunk <= 0) chunk = std::min(chunk, lim);
+    else if (tile_lds_bytes(prec, dim, w, p->bin, std::min(chunk, ntransf)) > budget) {
+      delete p;
+      return ESN_ERR_BAD_ARG;
+    }
+  }
+  // keep the fused grids within 16 GiB
+  const size_t gbytes = (size_t)nf_total(p) * csize(prec);
+  int memlim = (int)std::max<size_t>(1, ((size_t)16 << 30) / std::max<size_t>(gbytes, 1));
+  chunk = std::max(1, std::min({chunk, ntransf, memlim}));
+  p->chunk = chunk;
+  p->tail = ntransf % chunk;
+
+  int rc = ESN_OK;
+  hipStream_t s = p->stream;
+  auto fail = [&](int code) {
+    destroy_all(p);
+    delete p;
+    return code;
+  };
+
+  // ---- correction factors p(k) per dim (FP64 quadrature on the GPU) ----
+  {
+    std::vector<double> nodes, weights;
+    gauss_legendre_positive(par.nquad, &nodes, &weights);
+    double* d_q = nullptr;
+    if (dalloc(p, (void**)&d_q, sizeof(double) * 2 * par.nquad) != ESN_OK) return fail(ESN_ERR_ALLOC);
+    std::vector<double> qw(nodes);
+    qw.insert(qw.end(), weights.begin(), weights.end());
+    if (hipMemcpyAsync(d_q, qw.data(), sizeof(double) * qw.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+      return fail(ESN_ERR_HIP);
+    for (int m = 0; m < 3; m++) {
+      int64_t K = p->N[m] / 2 + 1;
+      if (dalloc(p, (void**)&p->d_pf[m], sizeof(double) * K) != ESN_OK) return fail(ESN_ERR_ALLOC);
+      if (m < dim) {
+        if (launch_fseries(w, par.beta, d_q, d_q + par.nquad, par.nquad, p->nf[m], p->N[m],
+                           p->d_pf[m], s) != hipSuccess)
+          return fail(ESN_ERR_HIP);
+      } else {
+        const double one = 1.0;
+        if (hipMemcpyAsync(p->d_pf[m], &one, sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+          return fail(ESN_ERR_HIP);
+      }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(ESN_ERR_HIP);
+    dfree(p, (void**)&d_q);
+  }
+
+  // ---- fine grid and FFT plans ----
+  if (dalloc(p, &p->d_grid, gbytes * chunk) != ESN_OK) return fail(ESN_ERR_ALLOC);
+  rc = fft_make(&p->fft, dim, p->nf, chunk, prec, isign, s);
+  if (rc != ESN_OK) return fail(rc);
+  if (p->tail) {
+    rc = fft_make(&p->fft_tail, dim, p->nf, p->tail, prec, isign, s);
+    if (rc != ESN_OK) return fail(rc);
+  }
+  p->device_bytes += (int64_t)(p->fft.work_bytes + p->fft_tail.work_bytes);
+
+  // ---- per-bin arrays ----
+  if (dalloc(p, (void**)&p->d_count, 4 * p->nbins) || dalloc(p, (void**)&p->d_start, 4 * p->nbins) ||
+      dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
+      dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(p->nbins) + 1)) ||
+      dalloc(p, (void**)&p->d_flags, 4 * 4))
+    return fail(ESN_ERR_ALLOC);
+  if (hipHostMalloc((void**)&p->h_pinned, 4 * 8, hipHostMallocDefault) != hipSuccess)
+    return fail(ESN_ERR_ALLOC);
+  if (o.debug) {
+    for (auto& e : p->ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(ESN_ERR_HIP);
+  }
+  *out = p;
+  return p->warn;
+}
+
+extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
+                          const void* z) {
+  if (!p || M < 0 || M > kMaxPoints) return ESN_ERR_BAD_ARG;
+  if (coord_prec != ESN_SINGLE && coord_prec != ESN_DOUBLE) return ESN_ERR_BAD_ARG;
+  const void* xs[3] = {x, y, z};
+  if (M > 0)
+    for (int m = 0; m < p->dim; m++)
+      if (!xs[m]) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  hipStream_t s = p->stream;
+  p->M = -1;
+  if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+  if (M > p->cap_M) {
+    free_points(p);
+    size_t el = p->pts_code == kPtsF64 ? sizeof(double) : sizeof(uint32_t);
+    for (int m = 0; m < p->dim; m++)
+      if (dalloc(p, &p->d_t[m], M * el)) return ESN_ERR_ALLOC;
+    if (dalloc(p, (void**)&p->d_perm, 4 * M) || dalloc(p, (void**)&p->d_keybin, 4 * M) ||
+        dalloc(p, (void**)&p->d_slot, 4 * M))
+      return ESN_ERR_ALLOC;
+    p->cap_M = M;
+  }
+  SortArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.dim = p->dim;
+  a.M = M;
+  a.coord_prec = coord_prec;
+  for (int m = 0; m < 3; m++) {
+    a.x[m] = m < p->dim ? xs[m] : nullptr;
+    a.n[m] = p->nf[m];
+    a.b[m] = p->bin[m];
+    a.nb[m] = p->nb[m];
+    a.fbits[m] = p->fbits[m];
+    a.t[m] = p->d_t[m];
+  }
+  a.pts_code = p->pts_code;
+  a.chkbnds = p->opts.chkbnds;
+  a.keybin = p->d_keybin;
+  a.slot = p->d_slot;
+  a.count = p->d_count;
+  a.start = p->d_start;
+  a.perm = p->d_perm;
+  a.flags = p->d_flags;
+  ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
+  int nsub = 0;
+  if (p->opts.sort) {
+    ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * p->nbins, s));
+    ESN_HIP(launch_bin_count(a, s));
+    ESN_HIP(exclusive_scan_i32(p->d_count, p->d_start, p->nbins, p->d_scan_tmp, s));
+    ESN_HIP(launch_scatter(a, s));
+    ESN_HIP(launch_subprob_count(p->d_count, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
+    ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
+    ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipMemcpyAsync(p->h_pinned + 2, p->d_subofs + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipMemcpyAsync(p->h_pinned + 3, p->d_nsub + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipStreamSynchronize(s));
+    nsub = p->h_pinned[2] + p->h_pinned[3];
+  } else {
+    ESN_HIP(launch_encode_unsorted(a, s));
+    ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipStreamSynchronize(s));
+  }
+  const int flags = p->h_pinned[0];
+  if (flags & 1) return ESN_ERR_NAN_PTS;
+  if (flags & 2) return ESN_ERR_PTS_OUT_OF_RANGE;
+  p->nbins_nonempty = p->opts.sort ? p->h_pinned[1] : 0;
+  if (p->opts.sort) {
+    if (nsub > p->cap_sub) {
+      free_subs(p);
+      if (dalloc(p, (void**)&p->d_sub_bin, 4 * (size_t)nsub) ||
+          dalloc(p, (void**)&p->d_sub_start, 4 * (size_t)nsub) ||
+          dalloc(p, (void**)&p->d_sub_len, 4 * (size_t)nsub))
+        return ESN_ERR_ALLOC;
+      p->cap_sub = nsub;
+    }
+    ESN_HIP(launch_subprob_fill(p->d_count, p->d_start, p->d_nsub, p->d_subofs, p->nbins,
+                                p->maxsub, p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
+  }
+  p->nsub = nsub;
+  p->M = M;
+  if (p->opts.debug) {
+    ESN_HIP(hipEventRecord(p->ev[1], s));
+    ESN_HIP(hipEventSynchronize(p->ev[1]));
+    float ms = 0;
+    ESN_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->stats.t_setpts = ms;
+  }
+  return ESN_OK;
+}
+
+static int run_spread(esn_plan_s* p, int ntr, const void* c, void* grid) {
+  GeomArgs g = make_geom(p, ntr);
+  size_t lds = p->spread_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
+  ESN_HIP(launch_spread(p->spread_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds,
+                        c, grid, p->stream));
+  return ESN_OK;
+}
+
+static int run_interp(esn_plan_s* p, int ntr, const void* grid, void* c) {
+  GeomArgs g = make_geom(p, ntr);
+  size_t lds = p->interp_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
+  ESN_HIP(launch_interp(p->interp_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds,
+                        grid, c, p->stream));
+  return ESN_OK;
+}
+
+extern "C" int esn_execute(esn_plan p, void* c, void* f) {
+  if (!p) return ESN_ERR_BAD_ARG;
+  if (p->M < 0) return ESN_ERR_NO_POINTS;
+  if ((p->M > 0 && !c) || !f) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  hipStream_t s = p->stream;
+  const size_t cs = csize(p->prec);
+  const int64_t G = nf_total(p), Nt = n_total(p);
+  const double* pf[3] = {p->d_pf[0], p->d_pf[1], p->d_pf[2]};
+  double t_a = 0, t_fft = 0, t_b = 0;
+  if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[5], s));
+  for (int c0 = 0; c0 < p->ntransf; c0 += p->chunk) {
+    const int ntr = std::min(p->chunk, p->ntransf - c0);
+    FFTPlan* fp = ntr == p->chunk ? &p->fft : &p->fft_tail;
+    char* cc = static_cast<char*>(c) + (size_t)c0 * p->M * cs;
+    char* ff = static_cast<char*>(f) + (size_t)c0 * Nt * cs;
+    if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+    if (p->type == 1) {
+      ESN_HIP(hipMemsetAsync(p->d_grid, 0, (size_t)ntr * G * cs, s));
+      ESN_TRY(run_spread(p, ntr, cc, p->d_grid));
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
+      ESN_TRY(fft_exec(fp, p->d_grid));
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[2], s));
+      ESN_HIP(launch_deconv(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
+                            Nt, pf, s));
+    } else {
+      ESN_HIP(launch_amplify(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
+                             Nt, pf, s));
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
+      ESN_TRY(fft_exec(fp, p->d_grid));
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[2], s));
+      ESN_TRY(run_interp(p, ntr, p->d_grid, cc));
+    }
+    if (p->opts.debug) {
+      ESN_HIP(hipEventRecord(p->ev[3], s));
+      ESN_HIP(hipEventSynchronize(p->ev[3]));
+      float a = 0, b = 0, d = 0;
+      ESN_HIP(hipEventElapsedTime(&a, p->ev[0], p->ev[1]));
+      ESN_HIP(hipEventElapsedTime(&b, p->ev[1], p->ev[2]));
+      ESN_HIP(hipEventElapsedTime(&d, p->ev[2], p->ev[3]));
+      t_a += a; t_fft += b; t_b += d;
+    }
+  }
+  if (p->opts.debug) {
+    ESN_HIP(hipEventRecord(p->ev[4], s));
+    ESN_HIP(hipEventSynchronize(p->ev[4]));
+    float tot = 0;
+    ESN_HIP(hipEventElapsedTime(&tot, p->ev[5], p->ev[4]));
+    if (p->type == 1) {
+      p->stats.t_spread_or_interp = t_a;   // memset + spread
+      p->stats.t_deconv_or_amplify = t_b;
+    } else {
+      p->stats.t_deconv_or_amplify = t_a;
+      p->stats.t_spread_or_interp = t_b;
+    }
+    p->stats.t_fft = t_fft;
+    p->stats.t_execute = tot;
+  }
+  return p->warn;
+}
+
+extern "C" int esn_spread(esn_plan p, const void* c, void* grid) {
+  if (!p || p->type != 1 || !grid) return ESN_ERR_BAD_ARG;
+  if (p->M < 0) return ESN_ERR_NO_POINTS;
+  if (p->M > 0 && !c) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  const size_t cs = csize(p->prec);
+  const int64_t G = nf_total(p);
+  ESN_HIP(hipMemsetAsync(grid, 0, (size_t)p->ntransf * G * cs, p->stream));
+  for (int c0 = 0; c0 < p->ntransf; c0 += p->chunk) {
+    const int ntr = std::min(p->chunk, p->ntransf - c0);
+    ESN_TRY(run_spread(p, ntr, static_cast<const char*>(c) + (size_t)c0 * p->M * cs,
+                       static_cast<char*>(grid) + (size_t)c0 * G * cs));
+  }
+  return ESN_OK;
+}
+
+extern "C" int esn_interp(esn_plan p, const void* grid, void* c) {
+  if (!p || p->type != 2 || !grid) return ESN_ERR_BAD_ARG;
+  if (p->M < 0) return ESN_ERR_NO_POINTS;
+  if (p->M > 0 && !c) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  const size_t cs = csize(p->prec);
+  const int64_t G = nf_total(p);
+  for (int c0 = 0; c0 < p->ntransf; c0 += p->chunk) {
+    const int ntr = std::min(p->chunk, p->ntransf - c0);
+    ESN_TRY(run_interp(p, ntr, static_cast<const char*>(grid) + (size_t)c0 * G * cs,
+                       static_cast<char*>(c) + (size_t)c0 * p->M * cs));
+  }
+  return ESN_OK;
+}
+
+extern "C" int esn_get_info(esn_plan p, esn_info* o) {
+  if (!p || !o) return ESN_ERR_BAD_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->type = p->type;
+  o->dim = p->dim;
+  o->isign = p->isign;
+  o->ntransf = p->ntransf;
+  o->prec = p->prec;
+  o->w = p->par.w;
+  o->nquad = p->par.nquad;
+  o->modeord = p->opts.modeord;
+  o->beta = p->par.beta;
+  o->eps = p->eps;
+  for (int m = 0; m < 3; m++) {
+    o->nmodes[m] = p->N[m];
+    o->nf[m] = p->nf[m];
+    o->bin[m] = p->bin[m];
+  }
+  o->M = p->M;
+  o->maxsubprob = p->maxsub;
+  o->nsubprob = p->nsub;
+  o->nbins_nonempty = p->nbins_nonempty;
+  o->ntransf_chunk = p->chunk;
+  o->spread_method = p->spread_method;
+  o->interp_method = p->interp_method;
+  o->point_code = p->pts_code;
+  o->device_bytes = p->device_bytes;
+  return ESN_OK;
+}
+
+extern "C" int esn_plan_correction(esn_plan p, int m, double* out, int64_t len) {
+  if (!p || !out || m < 0 || m >= p->dim || len != p->N[m] / 2 + 1) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  ESN_HIP(hipMemcpyAsync(out, p->d_pf[m], sizeof(double) * len, hipMemcpyDeviceToHost, p->stream));
+  ESN_HIP(hipStreamSynchronize(p->stream));
+  return ESN_OK;
+}
+
+extern "C" int esn_get_stats(esn_plan p, esn_stats* o) {
+  if (!p || !o) return ESN_ERR_BAD_ARG;
+  if (!p->opts.debug) return ESN_ERR_BAD_ARG;
+  *o = p->stats;
+  return ESN_OK;
+}
+
+extern "C" int esn_destroy(esn_plan p) {
+  if (!p) return ESN_OK;
+  (void)hipSetDevice(p->device);
+  destroy_all(p);
+  delete p;
+  return ESN_OK;
+}
+
+// ---- one-shot calls ----
+static int oneshot(int type, int dim, int64_t M, const double* x, const double* y,
+                   const double* z, void* c, int isign, double eps, const int64_t* N, void* f,
+                   int prec, const esn_opts* opts, void* stream) {
+  esn_plan p = nullptr;
+  int st = esn_makeplan(type, dim, N, isign, 1, eps, prec, &p, opts, stream);
+  if (st >= 2) return st;
+  int warn = st;
+  st = esn_setpts(p, M, ESN_DOUBLE, x, y, z);
+  if (st == ESN_OK) st = esn_execute(p, c, f);
+  if (st < 2 && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = ESN_ERR_HIP;
+  esn_destroy(p);
+  if (st >= 2) return st;
+  return st ? st : warn;
+}
+
+extern "C" int esn_1d1(int64_t M, const double* x, const void* c, int isign, double eps,
+                       int64_t N1, void* f, int prec, const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, 1, 1};
+  return oneshot(1, 1, M, x, nullptr, nullptr, const_cast<void*>(c), isign, eps, N, f, prec, opts,
+                 stream);
+}
+extern "C" int esn_1d2(int64_t M, const double* x, void* c, int isign, double eps, int64_t N1,
+                       const void* f, int prec, const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, 1, 1};
+  return oneshot(2, 1, M, x, nullptr, nullptr, c, isign, eps, N, const_cast<void*>(f), prec, opts,
+                 stream);
+}
+extern "C" int esn_2d1(int64_t M, const double* x, const double* y, const void* c, int isign,
+                       double eps, int64_t N1, int64_t N2, void* f, int prec,
+                       const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, N2, 1};
+  return oneshot(1, 2, M, x, y, nullptr, const_cast<void*>(c), isign, eps, N, f, prec, opts,
+                 stream);
+}
+extern "C" int esn_2d2(int64_t M, const double* x, const double* y, void* c, int isign,
+                       double eps, int64_t N1, int64_t N2, const void* f, int prec,
+                       const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, N2, 1};
+  return oneshot(2, 2, M, x, y, nullptr, c, isign, eps, N, const_cast<void*>(f), prec, opts,
+                 stream);
+}
+extern "C" int esn_3d1(int64_t M, const double* x, const double* y, const double* z,
+                       const void* c, int isign, double eps, int64_t N1, int64_t N2, int64_t N3,
+                       void* f, int prec, const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, N2, N3};
+  return oneshot(1, 3, M, x, y, z, const_cast<void*>(c), isign, eps, N, f, prec, opts, stream);
+}
+extern "C" int esn_3d2(int64_t M, const double* x, const double* y, const double* z, void* c,
+                       int isign, double eps, int64_t N1, int64_t N2, int64_t N3,
+                       const void* f, int prec, const esn_opts* opts, void* stream) {
+  int64_t N[3] = {N1, N2, N3};
+  return oneshot(2, 3, M, x, y, z, c, isign, eps, N, const_cast<void*>(f), prec, opts, stream);
+}

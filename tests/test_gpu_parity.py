@@ -1,0 +1,84 @@
+"""GPU parity of the HIP path with the FP64 oracle (relative l2 error, Sec. 4.2).
+
+Bar: rel. l2 error <= 10 eps on every case (eps = requested tolerance).  Inputs
+are seeded (paper_1808_06736_amd.inputs); the oracle gets exactly the values
+the GPU gets, upcast to FP64.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1808_06736_amd import inputs as I
+from tests.gpu_helpers import coord_np, run_type1, run_type2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-9)])
+def test_single_point_at_origin_gives_ones(dim, prec, eps):
+    N = (12, 9, 7)[:dim]
+    coords = coord_np([np.zeros(1)] * dim, prec)
+    c = np.ones(1, dtype=np.complex64 if prec == "f32" else np.complex128)
+    f, _ = run_type1(coords, c, N, eps, prec)
+    assert f.shape == tuple(reversed(N))
+    assert np.max(np.abs(f - 1.0)) < 10 * eps
+
+
+def test_small_1d_type1_full():
+    """1D type 1, M = 10^4 iid uniform points, N = 1000, eps = 1e-6, FP64: full output."""
+    w = I.WORKLOADS["1d_t1_small"]
+    coords = w.coords()
+    c = w.strengths()
+    f, info = run_type1(coords, c, (1000,), w.eps, "f64")
+    assert info.w == 7
+    ref = O.type1(coords, c, +1, N=(1000,))
+    err = O.rel_l2(f, ref)
+    print(f"1d t1 rel l2 = {err:.3e}")
+    assert err <= 10 * w.eps
+
+
+CASES = [
+    # dim, N, M, points, prec, eps
+    (1, (257,), 5001, "uniform", "f64", 1e-9),
+    (1, (100,), 3000, "wrapped_gaussian", "f32", 1e-4),
+    (2, (40, 33), 20011, "uniform", "f32", 1e-5),
+    (2, (31, 64), 20011, "wrapped_gaussian", "f64", 1e-10),
+    (3, (16, 13, 20), 30007, "uniform", "f32", 1e-6),
+    (3, (24, 24, 24), 30007, "wrapped_gaussian", "f32", 1e-4),
+    (3, (11, 16, 9), 20011, "wrapped_gaussian", "f64", 1e-9),
+]
+
+
+def _inputs(dim, N, M, points, prec, seed):
+    dt = np.float32 if prec == "f32" else np.float64
+    if points == "uniform":
+        coords = I.uniform_points(M, dim, seed, dt)
+    else:
+        coords = I.wrapped_gaussian_points(M, dim, seed, 0.3, dt)
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    c = I.complex_normal(M, seed + 1, cdt)
+    f = I.complex_normal(tuple(reversed(N)), seed + 2, cdt)
+    return coords, c, f
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in CASES])
+def test_small_type1_full(case):
+    dim, N, M, points, prec, eps = case
+    coords, c, _ = _inputs(dim, N, M, points, prec, 100 + dim)
+    f, _ = run_type1(coords, c, N, eps, prec)
+    ref = O.type1(coords, c, +1, N=N)
+    err = O.rel_l2(f, ref)
+    print(f"type1 {case}: {err:.3e}")
+    assert err <= 10 * eps
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in CASES])
+def test_small_type2_full(case):
+    dim, N, M, points, prec, eps = case
+    coords, _, f = _inputs(dim, N, M, points, prec, 200 + dim)
+    c, _ = run_type2(coords, f, N, eps, prec)
+    ref = O.type2(coords, f, -1)
+    err = O.rel_l2(c, ref)
+    print(f"type2 {case}: {err:.3e}")
+    assert err <= 10 * eps
