@@ -1,0 +1,267 @@
+"""Throughput benchmark of the NUFFT hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the whole hot path over the workload's points: for each
+transform type in the workload, set the points (FP64 fold + bin sort +
+subproblems) and execute (spread / FFT / deconvolve for type 1; amplify / FFT /
+interpolate for type 2).  Plans (kernel parameters, the FP64 quadrature of the
+kernel's Fourier transform, rocFFT plans) are made once before timing, as the
+paper times only calls after planning (Sec. 5).  All inputs are resident in
+HBM before the timed region.  ``value`` = NU points processed per second
+(M * ntransf per transform type, summed) over the timed steps.
+
+One JSON line is printed.  Besides the contract fields it carries
+* ``roofline``: the dominant kernel's algorithmic work per launch divided by
+  its mean duration, timed with HIP events on the kernel's own stream inside
+  the timed region (the library's debug stage events);
+* ``cpu_baseline``: the FP64 oracle (direct sums) timed on a bounded sample of
+  the same workload on the host cores, scaled to the metric's unit;
+* ``parity``: the GPU output's relative l2 error on that oracle sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1808_06736_amd import inputs as I  # noqa: E402
+
+METRIC = "NU points/sec, 3D type1/2 at ε=1e-6; served p50/p99 latency vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="3d_clustered", choices=sorted(I.WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="modes per dim (type 1) in the oracle sample; 0 = default")
+    return ap.parse_args()
+
+
+def algorithmic_work(w, dim, M, ntr, nf, prec, kind):
+    """Algorithmic bytes and flops of one spread or interp launch.
+
+    Per point: d sorted coordinates (4 B fixed point or 8 B) + one complex
+    strength per transform; per fine-grid cell: one complex write (spread) or
+    nothing counted (interp reads only the cells the points touch, which the
+    per-point figure already bounds).  Flops: 4 w^d per point per transform (a
+    real weight times a complex value, accumulated) + the separable weights
+    (w^(d-1) + ... products, ignored).
+    """
+    cb = 8 if prec == "f32" else 16
+    coord_b = 4 if prec == "f32" else 8
+    per_point = dim * coord_b + ntr * cb
+    grid = math.prod(nf) * ntr * cb if kind == "spread" else 0
+    bytes_ = M * per_point + grid
+    flops = 4.0 * (w ** dim) * M * ntr
+    return bytes_, flops
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1808_06736_amd import binding as B
+
+    wl = I.WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    dim, M, ntr = wl.dim, wl.M, wl.ntransf
+    N = wl.N[:dim]
+    prec = wl.prec
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+
+    coords_np = wl.coords()
+    coords = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in coords_np]
+    c_np = wl.strengths()
+    f_np = wl.coefficients()
+    c_in = torch.from_numpy(c_np).cuda()
+    f_in = torch.from_numpy(f_np).cuda()
+
+    plans = {}
+    outs = {}
+    for t in wl.types:
+        plans[t] = B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1)
+        plans[t].setpts(*coords)
+        if t == 1:
+            outs[t] = torch.empty_like(f_in)
+        else:
+            outs[t] = torch.empty_like(c_in)
+    torch.cuda.synchronize()
+
+    def step(record=None):
+        for t in wl.types:
+            p = plans[t]
+            p.setpts(*coords)
+            st_set = p.stats().t_setpts
+            if t == 1:
+                p.execute(c_in, outs[1])
+            else:
+                p.execute(outs[2], f_in)
+            if record is not None:
+                s = p.stats()
+                record.append((t, st_set, s.t_spread_or_interp, s.t_fft,
+                               s.t_deconv_or_amplify, s.t_execute))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    pts_per_step = M * ntr * len(wl.types)
+    value = pts_per_step / (elapsed / args.steps)
+
+    # per-type stage means (ms)
+    stages = {}
+    for t in wl.types:
+        r = np.array([x[1:] for x in rec if x[0] == t])
+        stages[f"type{t}"] = {
+            "setpts_ms": float(r[:, 0].mean()),
+            ("spread_ms" if t == 1 else "interp_ms"): float(r[:, 1].mean()),
+            "fft_ms": float(r[:, 2].mean()),
+            ("deconv_ms" if t == 1 else "amplify_ms"): float(r[:, 3].mean()),
+            "execute_ms": float(r[:, 4].mean()),
+            "exec_pts_per_s": M * ntr / (r[:, 4].mean() * 1e-3),
+        }
+
+    # dominant kernel: the slower of spread / interp
+    info = {t: plans[t].info() for t in wl.types}
+    kern_t = {t: stages[f"type{t}"]["spread_ms" if t == 1 else "interp_ms"] for t in wl.types}
+    tdom = max(kern_t, key=kern_t.get)
+    inf = info[tdom]
+    nf = [int(inf.nf[m]) for m in range(dim)]
+    kind = "spread" if tdom == 1 else "interp"
+    bytes_, flops = algorithmic_work(inf.w, dim, M, ntr, nf, prec, kind)
+    dur_s = kern_t[tdom] * 1e-3
+    peak_alu = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
+    intensity = flops / bytes_
+    ridge = peak_alu * 1e12 / (HBM_PEAK_GBS * 1e9)
+    kname = {1: "spread_lds_kernel", 2: "interp_lds_kernel"}[tdom]
+    if intensity >= ridge:
+        roof = {"bound": "alu", "achieved": flops / dur_s / 1e12, "peak": peak_alu,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_ / dur_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"{kname}<D={dim},W={inf.w},{'float' if prec == 'f32' else 'double'}>"
+    roof["algorithmic_bytes"] = bytes_
+    roof["algorithmic_flops"] = flops
+    roof["mean_launch_ms"] = kern_t[tdom]
+    roof["hbm_frac"] = bytes_ / dur_s / 1e9 / HBM_PEAK_GBS
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "NU pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "dim": dim, "N": list(N), "M": M, "ntransf": ntr,
+                   "eps": wl.eps, "points": wl.points, "types": list(wl.types),
+                   "w": int(inf.w), "nf": nf,
+                   "step": "per type: setpts (fold+sort+subproblems) + execute"},
+        "stages": stages,
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
+                                                          outs, args.cpu_sample)
+    for p in plans.values():
+        p.close()
+    print(json.dumps(out))
+
+
+def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
+    """Time the FP64 oracle on a bounded sample and scale to NU pts/s of a full step.
+
+    type 1: a seeded product set of S modes per dim (incl. min, 0, max) for all M
+    points -> extrapolated to all N modes.  type 2: 1024 seeded points (incl.
+    the extreme ones) over all N modes -> extrapolated to all M points.  For
+    batched workloads only the first transform is timed and the time scaled
+    by ntransf.
+    """
+    import torch
+    from oracle import oracle as O
+    threads = O.default_threads()
+    dim, M, ntr = wl.dim, wl.M, wl.ntransf
+    N = wl.N[:dim]
+    Ntot = math.prod(N)
+    S = cpu_sample or {1: 200, 2: 24, 3: 10}[dim]
+    t_full = 0.0
+    parts = []
+    parity = {}
+    if 1 in wl.types:
+        modes = [I.sample_modes(n, S, seed=31 + m) for m, n in enumerate(N)]
+        c0 = c_np[0] if ntr > 1 else c_np
+        t0 = time.perf_counter()
+        ref = O.type1(coords, c0, +1, modes=modes, nthreads=threads)
+        dt = time.perf_counter() - t0
+        nsamp = math.prod(len(m) for m in modes)
+        t_full += dt * (Ntot / nsamp) * ntr
+        parts.append(f"type 1: {nsamp} modes x {M} points ({dt:.1f} s)")
+        fg = outs[1].cpu().numpy()
+        fg = fg[0] if ntr > 1 else fg
+        idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
+        parity["type1_rel_l2"] = O.rel_l2(fg[idx], ref)
+    if 2 in wl.types:
+        sel = I.sample_points(coords, 1024, seed=37)
+        f0 = f_np[0] if ntr > 1 else f_np
+        t0 = time.perf_counter()
+        ref = O.type2([a[sel] for a in coords], f0, -1, nthreads=threads)
+        dt = time.perf_counter() - t0
+        t_full += dt * (M / len(sel)) * ntr
+        parts.append(f"type 2: {len(sel)} points x {Ntot} modes ({dt:.1f} s)")
+        cg = outs[2].cpu().numpy()
+        cg = cg[0] if ntr > 1 else cg
+        parity["type2_rel_l2"] = O.rel_l2(cg[sel], ref)
+    parity["bar"] = 10 * wl.eps
+    value = M * ntr * len(wl.types) / t_full
+    return ({"value": value, "unit": "NU pts/s", "cores": threads, "kind": "oracle",
+             "sample": "; ".join(parts) + "; scaled to all outputs of one step",
+             "cpu": _cpu_model()}, parity)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

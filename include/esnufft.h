@@ -75,7 +75,9 @@ typedef struct esn_opts {
   int modeord;        /* 0: increasing k from -floor(N/2); 1: FFT order */
   double upsampfac;   /* fine grid / modes ratio sigma; only 2.0 is supported */
   int sort;           /* 1 (default): bin-sort points (Sec. 4.1); 0: keep order */
-  int spread_method;  /* 0 auto; 1 LDS tile per subproblem; 2 global atomics */
+  int spread_method;  /* 0 auto; 1 LDS tile per subproblem; 2 global atomics;
+                         3 dense columns on the matrix cores (3D, single, w <= 7)
+                         plus LDS tiles for the rest */
   int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather */
   int bin[3];         /* bin size in fine-grid cells per dim; 0 = default */
   int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default */
@@ -162,6 +164,7 @@ typedef struct esn_info {
   int bin[3], maxsubprob, nsubprob, nbins_nonempty, ntransf_chunk;
   int spread_method, interp_method, point_code; /* point_code 1: fixed point u32, 2: f64 */
   int64_t device_bytes;  /* device memory the plan holds */
+  int ndense_units;      /* work units of the dense-column spreading path */
 } esn_info;
 
 /* Describe a plan (host struct filled). */

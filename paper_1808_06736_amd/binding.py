@@ -50,7 +50,7 @@ class EsnInfo(ctypes.Structure):
                 ("nmodes", i64 * 3), ("nf", i64 * 3), ("M", i64), ("bin", ci * 3),
                 ("maxsubprob", ci), ("nsubprob", ci), ("nbins_nonempty", ci),
                 ("ntransf_chunk", ci), ("spread_method", ci), ("interp_method", ci),
-                ("point_code", ci), ("device_bytes", i64)]
+                ("point_code", ci), ("device_bytes", i64), ("ndense_units", ci)]
 
 
 class EsnStats(ctypes.Structure):

@@ -65,6 +65,12 @@ hipError_t launch_amplify(int prec, int dim, const int64_t* N, const int64_t* nf
                           hipStream_t s);
 
 // Sorting / binning (kernels_sort.hip).
+//
+// Points are counted per fine-grid cell.  Cells are numbered bin-major: the
+// key of a cell is bin * cpb + local, cpb = b0 b1 b2 cells per bin, with the
+// local index z-fastest in 3D (local = lz + b2 (lx + b0 ly)), so that the
+// cells of one (x, y) column of a bin are consecutive keys and
+// column = key / b2.  In 2D local = lx + b0 ly, in 1D local = lx.
 struct SortArgs {
   int dim;
   int64_t M;
@@ -74,10 +80,14 @@ struct SortArgs {
   int b[3], nb[3], fbits[3];
   int pts_code;
   int chkbnds;
-  int32_t* keybin;          // [M]
-  int32_t* slot;            // [M]
-  int32_t* count;           // [nbins]
-  int32_t* start;           // [nbins]
+  int32_t* key;             // [M] cell key of each point
+  int32_t* slot;            // [M] rank of the point within its cell
+  int32_t* count;           // [ncells + 1] points per cell
+  const int32_t* sstart;    // [ncells + 1] first sorted position of a cell (sparse part)
+  const int32_t* dstart;    // [ncells + 1] same for cells of dense columns, relative to
+                            //   the end of the sparse part (nullptr: no dense part)
+  const int32_t* dcount;    // [ncells + 1] points per cell of dense columns (or nullptr)
+  int64_t ncells;
   int32_t* perm;            // [M]
   void* t[3];               // [M] each (sorted storage)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
@@ -90,13 +100,28 @@ hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n,
                               int32_t* tmp, hipStream_t s);
-// nsub[b] = ceil(count[b] / maxsub); *nonempty (device) is incremented per nonempty bin.
-hipError_t launch_subprob_count(const int32_t* count, int32_t* nsub, int64_t nbins,
-                                int maxsub, int32_t* nonempty, hipStream_t s);
-hipError_t launch_subprob_fill(const int32_t* count, const int32_t* start,
-                               const int32_t* nsub, const int32_t* subofs,
-                               int64_t nbins, int maxsub, int32_t* sub_bin,
-                               int32_t* sub_start, int32_t* sub_len, hipStream_t s);
+// 3D column classification: a column (b2 consecutive cells) is dense when it
+// holds at least min_dense points.  Writes the per-cell counts split into
+// scount (sparse columns) and dcount (dense columns), and the number of dense
+// work units per column, ucount[col] = ceil(points / max_unit) (0 if sparse).
+hipError_t launch_classify_columns(const int32_t* count, int64_t ncols, int b2, int min_dense,
+                                   int max_unit, int32_t* scount, int32_t* dcount,
+                                   int32_t* ucount, hipStream_t s);
+// Per bin: nsub[b] = ceil(points / maxsub) from the sparse starts; *nonempty
+// (device) is incremented per nonempty bin.
+hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub,
+                                int64_t nbins, int maxsub, int32_t* nonempty, hipStream_t s);
+hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t* nsub,
+                               const int32_t* subofs, int64_t nbins, int maxsub,
+                               int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
+                               hipStream_t s);
+// Dense units: column col with ucount[col] > 0 is cut into ucount[col] runs of
+// its sorted points; unit_col / unit_p0 / unit_p1 at ustart[col] + k.
+// Positions are absolute (the sparse total sstart[ncells] is added).
+hipError_t launch_units_fill(const int32_t* ucount, const int32_t* ustart,
+                             const int32_t* dstart, const int32_t* sstart, int64_t ncells,
+                             int64_t ncols, int b2, int32_t* unit_col, int32_t* unit_p0,
+                             int32_t* unit_p1, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // Spread / interp (kernels_spread.hip, kernels_interp.hip).
@@ -108,8 +133,22 @@ hipError_t launch_spread(int method, int prec, int dim, int w, const GeomArgs& g
 hipError_t launch_interp(int method, int prec, int dim, int w, const GeomArgs& g,
                          int nsub, int block, size_t lds_bytes, const void* grid,
                          void* c, hipStream_t s);
-// LDS bytes one subproblem tile needs for ntr transforms.
-size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr);
+// Dense 3D columns: MFMA spreading (kernels_dense.hip).  FP32, w <= 7, ntr 1.
+struct DenseArgs {
+  const int32_t* unit_col;
+  const int32_t* unit_p0;
+  const int32_t* unit_p1;
+  const int32_t* dstart;     // dense cell starts (relative to the sparse total)
+  const int32_t* sstart;     // sstart[ncells] = sparse total
+  int64_t ncells;
+};
+hipError_t launch_spread_dense(int w, const GeomArgs& g, const DenseArgs& d, int nunits,
+                               const void* c, void* grid, hipStream_t s);
+size_t dense_lds_bytes(int w, const int* b);
+
+// LDS bytes one subproblem tile needs for ntr transforms (with the spreading
+// kernel's per-point staging when staging is true).
+size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr, bool staging = true);
 
 // ---- rocFFT wrapper (fft.cpp) ----
 struct FFTPlan {
@@ -160,10 +199,24 @@ struct esn_plan_s {
   int64_t cap_M = 0;
   void* d_t[3] = {nullptr, nullptr, nullptr};
   int32_t* d_perm = nullptr;
-  int32_t* d_keybin = nullptr;
+  int32_t* d_key = nullptr;
   int32_t* d_slot = nullptr;
-  int32_t* d_count = nullptr;
-  int32_t* d_start = nullptr;
+  int64_t ncells = 0;            // bins * cells per bin
+  int32_t* d_count = nullptr;    // [ncells + 1]
+  int32_t* d_sstart = nullptr;   // [ncells + 1]
+  int32_t* d_scount = nullptr;   // [ncells + 1] (dense-capable plans)
+  int32_t* d_dcount = nullptr;   // [ncells + 1]
+  int32_t* d_dstart = nullptr;   // [ncells + 1]
+  int32_t* d_ucount = nullptr;   // [ncols + 1]
+  int32_t* d_ustart = nullptr;   // [ncols + 1]
+  int32_t* d_unit_col = nullptr;
+  int32_t* d_unit_p0 = nullptr;
+  int32_t* d_unit_p1 = nullptr;
+  int64_t cap_units = 0;
+  int nunits = 0;
+  int dense = 0;                 // dense-column MFMA spreading enabled
+  int min_dense = 64;            // points per column for the dense path
+  int max_unit = 2048;           // points per dense work unit
   int32_t* d_nsub = nullptr;
   int32_t* d_subofs = nullptr;
   int32_t* d_scan_tmp = nullptr;

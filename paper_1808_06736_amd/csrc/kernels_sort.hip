@@ -1,14 +1,17 @@
-// Bin sort of the nonuniform points (Sec. 4.1, an "incomplete" histogram
-// sort) and the subproblem list for spreading (Sec. 4.2).
+// Bin sort of the nonuniform points (Sec. 4.1, a histogram sort without any
+// ordering inside a cell) and the work lists for spreading (Sec. 4.2).
 //
 //   bin_count : fold each coordinate into [0, 2pi), rescale to fine-grid units
-//               t = x n / 2pi (FP64), take the bin of floor(t), and count the
-//               point into its bin; the count before the increment is the
-//               point's slot within the bin.
-//   scan      : exclusive prefix sum of the counts = each bin's first position.
-//   scatter   : place point j at start[bin] + slot, storing its permutation
-//               entry and its rescaled coordinate (no order inside a bin).
-//   subprob   : split each bin into runs of at most maxsub points.
+//               t = x n / 2pi (FP64), take the cell floor(t) and count the
+//               point into it; the count before the increment is the point's
+//               slot within the cell.  Cells are numbered bin-major, so every
+//               bin (and, in 3D, every column of a bin) is a run of keys.
+//   classify  : (3D, dense path) split columns into dense and sparse ones.
+//   scan      : exclusive prefix sums of the counts = first position of a cell.
+//   scatter   : place point j at start[cell] + slot, storing its permutation
+//               entry and its rescaled coordinate.
+//   subprob   : split each bin's sparse points into runs of at most maxsub.
+//   units     : split each dense column into runs of at most max_unit points.
 #include "device_common.hpp"
 
 namespace esn {
@@ -46,20 +49,26 @@ __device__ __forceinline__ double load_coord(const void* p, int64_t j) {
   return (double)static_cast<const CTy*>(p)[j];
 }
 
+// Cell key of point j (see SortArgs); also returns the encoded coordinates.
 template <typename CTy>
-__device__ __forceinline__ int point_bin(const SortArgs& a, int64_t j, int* flag,
-                                         uint32_t* q, double* t) {
-  int bin = 0, mult = 1;
+__device__ __forceinline__ int point_key(const SortArgs& a, int64_t j, int* flag, uint32_t* q,
+                                         double* t) {
+  int cell[3] = {0, 0, 0};
   for (int m = 0; m < a.dim; m++) {
     const double x = load_coord<CTy>(a.x[m], j);
     if (!isfinite(x)) *flag |= 1;
     else if (a.chkbnds && fabs(x) > kThreePi) *flag |= 2;
     const double tt = isfinite(x) ? fold_rescale(x, a.n[m]) : 0.0;
-    const int cell = encode_t(tt, a.n[m], a.pts_code, a.fbits[m], &q[m], &t[m]);
-    bin += mult * (cell / a.b[m]);
-    mult *= a.nb[m];
+    cell[m] = encode_t(tt, a.n[m], a.pts_code, a.fbits[m], &q[m], &t[m]);
   }
-  return bin;
+  const int bx = cell[0] / a.b[0], by = cell[1] / a.b[1], bz = cell[2] / a.b[2];
+  const int lx = cell[0] - bx * a.b[0], ly = cell[1] - by * a.b[1], lz = cell[2] - bz * a.b[2];
+  const int bin = bx + a.nb[0] * (by + a.nb[1] * bz);
+  const int cpb = a.b[0] * a.b[1] * a.b[2];
+  int local;
+  if (a.dim == 3) local = lz + a.b[2] * (lx + a.b[0] * ly);
+  else local = lx + a.b[0] * ly;
+  return bin * cpb + local;
 }
 
 template <typename CTy>
@@ -69,10 +78,10 @@ __global__ void bin_count_kernel(const SortArgs a) {
   int flag = 0;
   uint32_t q[3];
   double t[3];
-  const int bin = point_bin<CTy>(a, j, &flag, q, t);
+  const int key = point_key<CTy>(a, j, &flag, q, t);
   if (flag) atomicOr(a.flags, flag);
-  a.keybin[j] = bin;
-  a.slot[j] = atomicAdd(&a.count[bin], 1);
+  a.key[j] = key;
+  a.slot[j] = atomicAdd(&a.count[key], 1);
 }
 
 template <typename CTy>
@@ -82,8 +91,12 @@ __global__ void scatter_kernel(const SortArgs a) {
   int flag = 0;
   uint32_t q[3];
   double t[3];
-  point_bin<CTy>(a, j, &flag, q, t);
-  const int64_t pos = (int64_t)a.start[a.keybin[j]] + a.slot[j];
+  point_key<CTy>(a, j, &flag, q, t);
+  const int key = a.key[j];
+  int64_t pos;
+  if (a.dcount && a.dcount[key] > 0) pos = (int64_t)a.sstart[a.ncells] + a.dstart[key];
+  else pos = a.sstart[key];
+  pos += a.slot[j];
   a.perm[pos] = (int32_t)j;
   for (int m = 0; m < a.dim; m++) {
     if (a.pts_code == kPtsFixed32) static_cast<uint32_t*>(a.t[m])[pos] = q[m];
@@ -98,7 +111,7 @@ __global__ void encode_unsorted_kernel(const SortArgs a) {
   int flag = 0;
   uint32_t q[3];
   double t[3];
-  point_bin<CTy>(a, j, &flag, q, t);
+  point_key<CTy>(a, j, &flag, q, t);
   if (flag) atomicOr(a.flags, flag);
   a.perm[j] = (int32_t)j;
   for (int m = 0; m < a.dim; m++) {
@@ -218,18 +231,34 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_
   return hipGetLastError();
 }
 
-// ---- subproblems ----
-__global__ void subprob_count_kernel(const int32_t* __restrict__ count, int32_t* __restrict__ nsub,
-                                     int64_t nbins, int maxsub, int32_t* nonempty) {
+// ---- column classification, subproblems, dense units ----
+__global__ void classify_kernel(const int32_t* __restrict__ count, int64_t ncols, int b2,
+                                int min_dense, int max_unit, int32_t* __restrict__ scount,
+                                int32_t* __restrict__ dcount, int32_t* __restrict__ ucount) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  int tot = 0;
+  for (int z = 0; z < b2; z++) tot += count[col * b2 + z];
+  const bool dense = tot >= min_dense;
+  for (int z = 0; z < b2; z++) {
+    const int v = count[col * b2 + z];
+    scount[col * b2 + z] = dense ? 0 : v;
+    dcount[col * b2 + z] = dense ? v : 0;
+  }
+  ucount[col] = dense ? (tot + max_unit - 1) / max_unit : 0;
+}
+
+__global__ void subprob_count_kernel(const int32_t* __restrict__ sstart, int64_t cpb,
+                                     int32_t* __restrict__ nsub, int64_t nbins, int maxsub,
+                                     int32_t* nonempty) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
-  const int cnt = count[b];
+  const int cnt = sstart[(b + 1) * cpb] - sstart[b * cpb];
   nsub[b] = (cnt + maxsub - 1) / maxsub;
   if (cnt > 0) atomicAdd(nonempty, 1);
 }
 
-__global__ void subprob_fill_kernel(const int32_t* __restrict__ count,
-                                    const int32_t* __restrict__ start,
+__global__ void subprob_fill_kernel(const int32_t* __restrict__ sstart, int64_t cpb,
                                     const int32_t* __restrict__ nsub,
                                     const int32_t* __restrict__ subofs, int64_t nbins,
                                     int maxsub, int32_t* __restrict__ sub_bin,
@@ -239,11 +268,34 @@ __global__ void subprob_fill_kernel(const int32_t* __restrict__ count,
   if (b >= nbins) return;
   const int ns = nsub[b];
   const int o = subofs[b];
-  const int cnt = count[b];
+  const int st = sstart[b * cpb];
+  const int cnt = sstart[(b + 1) * cpb] - st;
   for (int k = 0; k < ns; k++) {
     sub_bin[o + k] = (int32_t)b;
-    sub_start[o + k] = start[b] + k * maxsub;
+    sub_start[o + k] = st + k * maxsub;
     sub_len[o + k] = min(maxsub, cnt - k * maxsub);
+  }
+}
+
+__global__ void units_fill_kernel(const int32_t* __restrict__ ucount,
+                                  const int32_t* __restrict__ ustart,
+                                  const int32_t* __restrict__ dstart,
+                                  const int32_t* __restrict__ sstart, int64_t ncells,
+                                  int64_t ncols, int b2, int32_t* __restrict__ unit_col,
+                                  int32_t* __restrict__ unit_p0, int32_t* __restrict__ unit_p1) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  const int nu = ucount[col];
+  if (nu == 0) return;
+  const int base = sstart[ncells];
+  const int p0 = base + dstart[col * b2];
+  const int p1 = base + dstart[(col + 1) * b2];
+  const int per = (p1 - p0 + nu - 1) / nu;
+  const int o = ustart[col];
+  for (int k = 0; k < nu; k++) {
+    unit_col[o + k] = (int32_t)col;
+    unit_p0[o + k] = p0 + k * per;
+    unit_p1[o + k] = min(p1, p0 + (k + 1) * per);
   }
 }
 
@@ -252,19 +304,36 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
   if (i < n) p[i] = (int32_t)i;
 }
 
-hipError_t launch_subprob_count(const int32_t* count, int32_t* nsub, int64_t nbins, int maxsub,
-                                int32_t* nonempty, hipStream_t s) {
-  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, count,
-                     nsub, nbins, maxsub, nonempty);
+hipError_t launch_classify_columns(const int32_t* count, int64_t ncols, int b2, int min_dense,
+                                   int max_unit, int32_t* scount, int32_t* dcount,
+                                   int32_t* ucount, hipStream_t s) {
+  hipLaunchKernelGGL(classify_kernel, dim3(nblocks(ncols, 256)), dim3(256), 0, s, count, ncols,
+                     b2, min_dense, max_unit, scount, dcount, ucount);
   return hipGetLastError();
 }
 
-hipError_t launch_subprob_fill(const int32_t* count, const int32_t* start, const int32_t* nsub,
+hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub, int64_t nbins,
+                                int maxsub, int32_t* nonempty, hipStream_t s) {
+  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, sstart,
+                     cpb, nsub, nbins, maxsub, nonempty);
+  return hipGetLastError();
+}
+
+hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t* nsub,
                                const int32_t* subofs, int64_t nbins, int maxsub,
                                int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
                                hipStream_t s) {
-  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, count,
-                     start, nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
+  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, sstart,
+                     cpb, nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_units_fill(const int32_t* ucount, const int32_t* ustart, const int32_t* dstart,
+                             const int32_t* sstart, int64_t ncells, int64_t ncols, int b2,
+                             int32_t* unit_col, int32_t* unit_p0, int32_t* unit_p1,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(units_fill_kernel, dim3(nblocks(ncols, 256)), dim3(256), 0, s, ucount,
+                     ustart, dstart, sstart, ncells, ncols, b2, unit_col, unit_p0, unit_p1);
   return hipGetLastError();
 }
 

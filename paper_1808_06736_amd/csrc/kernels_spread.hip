@@ -1,11 +1,11 @@
 // Spreading, eq. (bl):  b_l = sum_j c_j psi~(l h - x_j)  on the fine grid.
 //
-// spread_lds: one workgroup per subproblem (Sec. 4.2).  A subproblem is a run
-// of at most maxsub bin-sorted points of one bin.  The workgroup spreads them
-// into a tile in LDS covering the bin plus a halo (bin + w cells per dim, so no
-// index wrapping is needed while spreading), then adds the tile to the fine
-// grid with periodic wrapping.  Different subproblems may overlap on the fine
-// grid, so the add-back uses global atomics; only cells that received a
+// spread_lds: one wave per subproblem (Sec. 4.2).  A subproblem is a run of at
+// most maxsub bin-sorted points of one bin.  The wave spreads them into a tile
+// in LDS covering the bin plus a halo (bin + w cells per dim, so no index
+// wrapping is needed while spreading), then adds the tile to the fine grid
+// with periodic wrapping.  Different subproblems may overlap on the fine grid,
+// so the add-back uses global atomics; only cells that received a
 // contribution are added.
 //
 // spread_gm: one thread per (sorted or unsorted) point, adding its w^d
@@ -14,11 +14,23 @@
 
 namespace esn {
 
+// Per-point staging of one batch of 64 points, kept in LDS after the tile.
 template <int D, int W, typename T>
-__global__ void __launch_bounds__(1024)
+struct Staging {
+  T ker[64][D][W];   // separable kernel values per dim
+  int loc[64][D];    // window start inside the tile per dim
+};
+
+// One wave (64 lanes) per subproblem.  The wave owns its LDS tile, so no
+// atomics are needed inside it: the lanes take the points of the subproblem
+// one after another, and for each point every lane updates a different set of
+// tile cells (d = 3: lane -> one (x, y) of the w x w footprint and its w cells
+// along z; d = 2: lane -> one cell; d = 1: lane -> one cell).  Kernel values are
+// computed once per point, a lane per point, in batches of 64.
+template <int D, int W, typename T>
+__global__ void __launch_bounds__(64)
 spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restrict__ grid) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
   const int sidx = blockIdx.x;
   const int bin = g.sub_bin[sidx];
   const int start = g.sub_start[sidx];
@@ -32,57 +44,86 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
   const int T2 = D >= 3 ? g.b[2] + W : 1;
   const int tc = T0 * T1 * T2;
   const int ntr = g.ntr;
-  for (int i = threadIdx.x; i < 2 * tc * ntr; i += blockDim.x) tile[i] = (T)0;
-  __syncthreads();
-
+  cplx_t<T>* tile = reinterpret_cast<cplx_t<T>*>(smem_raw);
+  Staging<D, W, T>* st = reinterpret_cast<Staging<D, W, T>*>(tile + (size_t)tc * ntr);
+  // strengths of the batch, [64][ntr], 16-byte aligned; offsets are taken
+  // inside the LDS array so the compiler keeps LDS (not flat) accesses
+  const size_t stc_off =
+      ((size_t)tc * ntr * sizeof(cplx_t<T>) + sizeof(Staging<D, W, T>) + 15) & ~(size_t)15;
+  cplx_t<T>* stc = reinterpret_cast<cplx_t<T>*>(smem_raw + stc_off);
+  const int lane = threadIdx.x;
+  {
+    cplx_t<T> z;
+    z.x = 0;
+    z.y = 0;
+    for (int i = lane; i < tc * ntr; i += 64) tile[i] = z;
+  }
   const T beta = (T)g.beta;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    const int64_t j = (int64_t)start + i;
-    T ker[D][W];
-    int L[3] = {0, 0, 0};
+  for (int b0 = 0; b0 < len; b0 += 64) {
+    const int nb = min(64, len - b0);
+    __syncthreads();
+    if (lane < nb) {
+      const int64_t j = (int64_t)start + b0 + lane;
 #pragma unroll
-    for (int m = 0; m < D; m++) {
-      int sh;
-      Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
-      L[m] = cd.cell - bi[m] * g.b[m] + sh;   // window start inside the tile
-      es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
+      for (int m = 0; m < D; m++) {
+        int sh;
+        Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
+        st->loc[lane][m] = cd.cell - bi[m] * g.b[m] + sh;
+        es_weights_t<W, T>(sh, cd.f, beta, st->ker[lane][m]);
+      }
+      const int64_t orig = g.perm[j];
+      for (int tr = 0; tr < ntr; tr++) stc[lane * ntr + tr] = c[tr * g.cstride + orig];
     }
-    const int64_t orig = g.perm[j];
-    for (int tr = 0; tr < ntr; tr++) {
-      const cplx_t<T> cv = c[tr * g.cstride + orig];
-      T* tl = tile + 2 * tr * tc;
+    __syncthreads();
+    for (int q = 0; q < nb; q++) {
       if constexpr (D == 1) {
-#pragma unroll
-        for (int k0 = 0; k0 < W; k0++) {
-          const int q = 2 * (L[0] + k0);
-          atomicAdd(&tl[q], ker[0][k0] * cv.x);
-          atomicAdd(&tl[q + 1], ker[0][k0] * cv.y);
+        if (lane < W) {
+          const int idx = st->loc[q][0] + lane;
+          const T k0 = st->ker[q][0][lane];
+          for (int tr = 0; tr < ntr; tr++) {
+            const cplx_t<T> cv = stc[q * ntr + tr];
+            cplx_t<T> v = tile[tr * tc + idx];
+            v.x += k0 * cv.x;
+            v.y += k0 * cv.y;
+            tile[tr * tc + idx] = v;
+          }
         }
       } else if constexpr (D == 2) {
-#pragma unroll
-        for (int k1 = 0; k1 < W; k1++) {
-          const T cr = ker[1][k1] * cv.x, ci = ker[1][k1] * cv.y;
-          const int base = (L[1] + k1) * T0 + L[0];
-#pragma unroll
-          for (int k0 = 0; k0 < W; k0++) {
-            const int q = 2 * (base + k0);
-            atomicAdd(&tl[q], ker[0][k0] * cr);
-            atomicAdd(&tl[q + 1], ker[0][k0] * ci);
+        for (int xy = lane; xy < W * W; xy += 64) {
+          const int lx = xy % W, ly = xy / W;
+          const int idx = (st->loc[q][1] + ly) * T0 + st->loc[q][0] + lx;
+          const T kxy = st->ker[q][0][lx] * st->ker[q][1][ly];
+          for (int tr = 0; tr < ntr; tr++) {
+            const cplx_t<T> cv = stc[q * ntr + tr];
+            cplx_t<T> v = tile[tr * tc + idx];
+            v.x += kxy * cv.x;
+            v.y += kxy * cv.y;
+            tile[tr * tc + idx] = v;
           }
         }
       } else {
-        for (int k2 = 0; k2 < W; k2++) {
+        T kz[W];
 #pragma unroll
-          for (int k1 = 0; k1 < W; k1++) {
-            const T w12 = ker[2][k2] * ker[1][k1];
-            const T cr = w12 * cv.x, ci = w12 * cv.y;
-            const int base = ((L[2] + k2) * T1 + (L[1] + k1)) * T0 + L[0];
+        for (int k = 0; k < W; k++) kz[k] = st->ker[q][2][k];
+        const int plane = T0 * T1;
+        for (int xy = lane; xy < W * W; xy += 64) {
+          const int lx = xy % W, ly = xy / W;
+          const int base = (st->loc[q][2] * T1 + st->loc[q][1] + ly) * T0 + st->loc[q][0] + lx;
+          const T kxy = st->ker[q][0][lx] * st->ker[q][1][ly];
+          for (int tr = 0; tr < ntr; tr++) {
+            const cplx_t<T> cv = stc[q * ntr + tr];
+            const T cr = kxy * cv.x, ci = kxy * cv.y;
+            cplx_t<T>* tl = tile + tr * tc + base;
+            cplx_t<T> v[W];
 #pragma unroll
-            for (int k0 = 0; k0 < W; k0++) {
-              const int q = 2 * (base + k0);
-              atomicAdd(&tl[q], ker[0][k0] * cr);
-              atomicAdd(&tl[q + 1], ker[0][k0] * ci);
+            for (int k = 0; k < W; k++) v[k] = tl[k * plane];
+#pragma unroll
+            for (int k = 0; k < W; k++) {
+              v[k].x += kz[k] * cr;
+              v[k].y += kz[k] * ci;
             }
+#pragma unroll
+            for (int k = 0; k < W; k++) tl[k * plane] = v[k];
           }
         }
       }
@@ -90,11 +131,12 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
   }
   __syncthreads();
 
-  // add the tile back into the periodic fine grid
+  // add the tile back into the periodic fine grid (consecutive lanes take
+  // consecutive cells along x)
   const int64_t o0 = (int64_t)bi[0] * g.b[0] - W / 2;
   const int64_t o1 = D >= 2 ? (int64_t)bi[1] * g.b[1] - W / 2 : 0;
   const int64_t o2 = D >= 3 ? (int64_t)bi[2] * g.b[2] - W / 2 : 0;
-  for (int i = threadIdx.x; i < tc; i += blockDim.x) {
+  for (int i = lane; i < tc; i += 64) {
     const int i0 = i % T0;
     const int r = i / T0;
     const int i1 = r % T1;
@@ -104,12 +146,11 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
     const int64_t g2 = D >= 3 ? wrap_any(o2 + i2, g.n[2]) : 0;
     const int64_t gi = g0 + g.n[0] * (g1 + g.n[1] * g2);
     for (int tr = 0; tr < ntr; tr++) {
-      const T vr = tile[2 * (tr * tc + i)];
-      const T vi = tile[2 * (tr * tc + i) + 1];
-      if (vr != (T)0 || vi != (T)0) {
+      const cplx_t<T> v = tile[tr * tc + i];
+      if (v.x != (T)0 || v.y != (T)0) {
         T* dst = grid + 2 * (tr * g.gstride + gi);
-        atomicAdd(dst, vr);
-        atomicAdd(dst + 1, vi);
+        atomicAdd(dst, v.x);
+        atomicAdd(dst + 1, v.y);
       }
     }
   }
@@ -158,12 +199,17 @@ spread_gm_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restric
   }
 }
 
-size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr) {
+size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr, bool staging) {
   size_t cells = (size_t)(b[0] + w);
   if (dim >= 2) cells *= (size_t)(b[1] + w);
   if (dim >= 3) cells *= (size_t)(b[2] + w);
   size_t el = prec == ESN_DOUBLE ? sizeof(double) : sizeof(float);
-  return cells * 2 * el * (size_t)ntr;
+  size_t bytes = cells * 2 * el * (size_t)ntr;
+  // spreading also stages a batch of 64 points: kernel values, window starts
+  // and strengths (the latter 16-byte aligned)
+  if (staging)
+    bytes += 64 * ((size_t)dim * w * el + (size_t)dim * sizeof(int)) + 16 + 64 * 2 * el * ntr;
+  return bytes;
 }
 
 template <int D, int W, typename T>
@@ -171,7 +217,7 @@ static hipError_t spread_dispatch_t(int method, const GeomArgs& g, int nsub, int
                                     size_t lds, const void* c, void* grid, hipStream_t s) {
   if (method == 1) {
     if (nsub <= 0) return hipSuccess;
-    hipLaunchKernelGGL((spread_lds_kernel<D, W, T>), dim3(nsub), dim3(block), lds, s, g,
+    hipLaunchKernelGGL((spread_lds_kernel<D, W, T>), dim3(nsub), dim3(64), lds, s, g,
                        static_cast<const cplx_t<T>*>(c), static_cast<T*>(grid));
   } else {
     if (g.M <= 0) return hipSuccess;

@@ -112,7 +112,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
 void free_points(esn_plan_s* p) {
   for (int m = 0; m < 3; m++) dfree(p, &p->d_t[m]);
   dfree(p, (void**)&p->d_perm);
-  dfree(p, (void**)&p->d_keybin);
+  dfree(p, (void**)&p->d_key);
   dfree(p, (void**)&p->d_slot);
   p->cap_M = 0;
 }
@@ -124,14 +124,27 @@ void free_subs(esn_plan_s* p) {
   p->cap_sub = 0;
 }
 
+void free_units(esn_plan_s* p) {
+  dfree(p, (void**)&p->d_unit_col);
+  dfree(p, (void**)&p->d_unit_p0);
+  dfree(p, (void**)&p->d_unit_p1);
+  p->cap_units = 0;
+}
+
 void destroy_all(esn_plan_s* p) {
   (void)hipStreamSynchronize(p->stream);
   free_points(p);
   free_subs(p);
+  free_units(p);
   for (int m = 0; m < 3; m++) dfree(p, (void**)&p->d_pf[m]);
   dfree(p, &p->d_grid);
   dfree(p, (void**)&p->d_count);
-  dfree(p, (void**)&p->d_start);
+  dfree(p, (void**)&p->d_sstart);
+  dfree(p, (void**)&p->d_scount);
+  dfree(p, (void**)&p->d_dcount);
+  dfree(p, (void**)&p->d_dstart);
+  dfree(p, (void**)&p->d_ucount);
+  dfree(p, (void**)&p->d_ustart);
   dfree(p, (void**)&p->d_nsub);
   dfree(p, (void**)&p->d_subofs);
   dfree(p, (void**)&p->d_scan_tmp);
@@ -194,7 +207,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     if (nmodes[m] > (int64_t)1 << 30 || par.nf[m] > (int64_t)1 << 31) return ESN_ERR_BAD_ARG;
   if (o.bin[0] < 0 || o.bin[1] < 0 || o.bin[2] < 0 || o.maxsubprob < 0 ||
       o.ntransf_chunk < 0 || o.block < 0 || o.block > 1024 ||
-      (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 2 ||
+      (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 3 ||
       o.interp_method < 0 || o.interp_method > 2)
     return ESN_ERR_BAD_ARG;
 
@@ -254,7 +267,15 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   p->maxsub = o.maxsubprob > 0 ? o.maxsubprob : 1024;
   p->block = o.block > 0 ? o.block : 256;
   const bool tile_fits = tile_lds_bytes(prec, dim, w, p->bin, 1) <= budget;
-  p->spread_method = o.spread_method ? o.spread_method : (tile_fits ? 1 : 2);
+  // dense-column MFMA spreading: 3D single precision, w <= 7, one transform
+  // per launch; method 3 asks for it, method 0 takes it when possible
+  const bool dense_ok = type == 1 && dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
+                        tile_fits && dense_lds_bytes(w, p->bin) <= budget;
+  p->spread_method = o.spread_method ? o.spread_method : (tile_fits ? (dense_ok ? 3 : 1) : 2);
+  if (p->spread_method == 3 && !dense_ok) {
+    delete p;
+    return ESN_ERR_BAD_ARG;
+  }
   p->interp_method = o.interp_method ? o.interp_method : (tile_fits ? 1 : 2);
   if (!o.sort) p->spread_method = p->interp_method = 2;
   if (!tile_fits) {
@@ -263,8 +284,10 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
       return ESN_ERR_BAD_ARG;   // requested LDS method cannot hold one tile
     }
   }
-  const bool uses_lds = (type == 1 && p->spread_method == 1) || (type == 2 && p->interp_method == 1);
+  const bool uses_lds = (type == 1 && (p->spread_method == 1 || p->spread_method == 3)) ||
+                        (type == 2 && p->interp_method == 1);
   int chunk = o.ntransf_chunk > 0 ? o.ntransf_chunk : ntransf;
+  if (type == 1 && p->spread_method == 3) chunk = 1;
   if (uses_lds) {
     size_t one = tile_lds_bytes(prec, dim, w, p->bin, 1);
     int lim = (int)std::max<size_t>(1, budget / one);
@@ -280,6 +303,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   chunk = std::max(1, std::min({chunk, ntransf, memlim}));
   p->chunk = chunk;
   p->tail = ntransf % chunk;
+  p->dense = type == 1 && p->spread_method == 3;
 
   int rc = ESN_OK;
   hipStream_t s = p->stream;
@@ -327,12 +351,28 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   }
   p->device_bytes += (int64_t)(p->fft.work_bytes + p->fft_tail.work_bytes);
 
-  // ---- per-bin arrays ----
-  if (dalloc(p, (void**)&p->d_count, 4 * p->nbins) || dalloc(p, (void**)&p->d_start, 4 * p->nbins) ||
-      dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
-      dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(p->nbins) + 1)) ||
-      dalloc(p, (void**)&p->d_flags, 4 * 4))
-    return fail(ESN_ERR_ALLOC);
+  // ---- per-cell / per-bin arrays ----
+  {
+    const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
+    p->ncells = p->nbins * cpb;
+    if (p->ncells + 1 > (int64_t)1 << 31) return fail(ESN_ERR_BAD_ARG);
+    const int64_t ncols = p->nbins * p->bin[0] * p->bin[1];
+    const int64_t nscan = std::max({p->ncells + 1, ncols + 1, p->nbins});
+    if (dalloc(p, (void**)&p->d_count, 4 * (p->ncells + 1)) ||
+        dalloc(p, (void**)&p->d_sstart, 4 * (p->ncells + 1)) ||
+        dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
+        dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(nscan) + 1)) ||
+        dalloc(p, (void**)&p->d_flags, 4 * 4))
+      return fail(ESN_ERR_ALLOC);
+    if (p->dense) {
+      if (dalloc(p, (void**)&p->d_scount, 4 * (p->ncells + 1)) ||
+          dalloc(p, (void**)&p->d_dcount, 4 * (p->ncells + 1)) ||
+          dalloc(p, (void**)&p->d_dstart, 4 * (p->ncells + 1)) ||
+          dalloc(p, (void**)&p->d_ucount, 4 * (ncols + 1)) ||
+          dalloc(p, (void**)&p->d_ustart, 4 * (ncols + 1)))
+        return fail(ESN_ERR_ALLOC);
+    }
+  }
   if (hipHostMalloc((void**)&p->h_pinned, 4 * 8, hipHostMallocDefault) != hipSuccess)
     return fail(ESN_ERR_ALLOC);
   if (o.debug) {
@@ -360,7 +400,7 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     size_t el = p->pts_code == kPtsF64 ? sizeof(double) : sizeof(uint32_t);
     for (int m = 0; m < p->dim; m++)
       if (dalloc(p, &p->d_t[m], M * el)) return ESN_ERR_ALLOC;
-    if (dalloc(p, (void**)&p->d_perm, 4 * M) || dalloc(p, (void**)&p->d_keybin, 4 * M) ||
+    if (dalloc(p, (void**)&p->d_perm, 4 * M) || dalloc(p, (void**)&p->d_key, 4 * M) ||
         dalloc(p, (void**)&p->d_slot, 4 * M))
       return ESN_ERR_ALLOC;
     p->cap_M = M;
@@ -380,26 +420,45 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   }
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
-  a.keybin = p->d_keybin;
+  a.key = p->d_key;
   a.slot = p->d_slot;
   a.count = p->d_count;
-  a.start = p->d_start;
+  a.sstart = p->d_sstart;
+  a.dstart = p->dense ? p->d_dstart : nullptr;
+  a.dcount = p->dense ? p->d_dcount : nullptr;
+  a.ncells = p->ncells;
   a.perm = p->d_perm;
   a.flags = p->d_flags;
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
-  int nsub = 0;
+  int nsub = 0, nunits = 0;
+  const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
+  const int64_t ncols = p->nbins * p->bin[0] * p->bin[1];
   if (p->opts.sort) {
-    ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * p->nbins, s));
+    ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * (p->ncells + 1), s));
     ESN_HIP(launch_bin_count(a, s));
-    ESN_HIP(exclusive_scan_i32(p->d_count, p->d_start, p->nbins, p->d_scan_tmp, s));
+    if (p->dense) {
+      ESN_HIP(launch_classify_columns(p->d_count, ncols, p->bin[2], p->min_dense, p->max_unit,
+                                      p->d_scount, p->d_dcount, p->d_ucount, s));
+      ESN_HIP(hipMemsetAsync(p->d_scount + p->ncells, 0, 4, s));
+      ESN_HIP(hipMemsetAsync(p->d_dcount + p->ncells, 0, 4, s));
+      ESN_HIP(hipMemsetAsync(p->d_ucount + ncols, 0, 4, s));
+      ESN_HIP(exclusive_scan_i32(p->d_scount, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
+      ESN_HIP(exclusive_scan_i32(p->d_dcount, p->d_dstart, p->ncells + 1, p->d_scan_tmp, s));
+      ESN_HIP(exclusive_scan_i32(p->d_ucount, p->d_ustart, ncols + 1, p->d_scan_tmp, s));
+    } else {
+      ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
+    }
     ESN_HIP(launch_scatter(a, s));
-    ESN_HIP(launch_subprob_count(p->d_count, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
+    ESN_HIP(launch_subprob_count(p->d_sstart, cpb, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
     ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned + 2, p->d_subofs + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned + 3, p->d_nsub + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
+    if (p->dense)
+      ESN_HIP(hipMemcpyAsync(p->h_pinned + 4, p->d_ustart + ncols, 4, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipStreamSynchronize(s));
     nsub = p->h_pinned[2] + p->h_pinned[3];
+    nunits = p->dense ? p->h_pinned[4] : 0;
   } else {
     ESN_HIP(launch_encode_unsorted(a, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
@@ -418,9 +477,22 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
         return ESN_ERR_ALLOC;
       p->cap_sub = nsub;
     }
-    ESN_HIP(launch_subprob_fill(p->d_count, p->d_start, p->d_nsub, p->d_subofs, p->nbins,
-                                p->maxsub, p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
+    ESN_HIP(launch_subprob_fill(p->d_sstart, cpb, p->d_nsub, p->d_subofs, p->nbins, p->maxsub,
+                                p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
+    if (p->dense) {
+      if (nunits > p->cap_units) {
+        free_units(p);
+        if (dalloc(p, (void**)&p->d_unit_col, 4 * (size_t)nunits) ||
+            dalloc(p, (void**)&p->d_unit_p0, 4 * (size_t)nunits) ||
+            dalloc(p, (void**)&p->d_unit_p1, 4 * (size_t)nunits))
+          return ESN_ERR_ALLOC;
+        p->cap_units = nunits;
+      }
+      ESN_HIP(launch_units_fill(p->d_ucount, p->d_ustart, p->d_dstart, p->d_sstart, p->ncells,
+                                ncols, p->bin[2], p->d_unit_col, p->d_unit_p0, p->d_unit_p1, s));
+    }
   }
+  p->nunits = nunits;
   p->nsub = nsub;
   p->M = M;
   if (p->opts.debug) {
@@ -435,15 +507,26 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
 
 static int run_spread(esn_plan_s* p, int ntr, const void* c, void* grid) {
   GeomArgs g = make_geom(p, ntr);
-  size_t lds = p->spread_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
-  ESN_HIP(launch_spread(p->spread_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds,
-                        c, grid, p->stream));
+  const int method = p->spread_method == 3 ? 1 : p->spread_method;
+  size_t lds = method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
+  ESN_HIP(launch_spread(method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds, c, grid,
+                        p->stream));
+  if (p->spread_method == 3) {
+    DenseArgs d;
+    d.unit_col = p->d_unit_col;
+    d.unit_p0 = p->d_unit_p0;
+    d.unit_p1 = p->d_unit_p1;
+    d.dstart = p->d_dstart;
+    d.sstart = p->d_sstart;
+    d.ncells = p->ncells;
+    ESN_HIP(launch_spread_dense(p->par.w, g, d, p->nunits, c, grid, p->stream));
+  }
   return ESN_OK;
 }
 
 static int run_interp(esn_plan_s* p, int ntr, const void* grid, void* c) {
   GeomArgs g = make_geom(p, ntr);
-  size_t lds = p->interp_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
+  size_t lds = p->interp_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr, false) : 0;
   ESN_HIP(launch_interp(p->interp_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds,
                         grid, c, p->stream));
   return ESN_OK;
@@ -465,9 +548,9 @@ extern "C" int esn_execute(esn_plan p, void* c, void* f) {
     FFTPlan* fp = ntr == p->chunk ? &p->fft : &p->fft_tail;
     char* cc = static_cast<char*>(c) + (size_t)c0 * p->M * cs;
     char* ff = static_cast<char*>(f) + (size_t)c0 * Nt * cs;
-    if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
     if (p->type == 1) {
       ESN_HIP(hipMemsetAsync(p->d_grid, 0, (size_t)ntr * G * cs, s));
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
       ESN_TRY(run_spread(p, ntr, cc, p->d_grid));
       if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
       ESN_TRY(fft_exec(fp, p->d_grid));
@@ -475,6 +558,7 @@ extern "C" int esn_execute(esn_plan p, void* c, void* f) {
       ESN_HIP(launch_deconv(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
                             Nt, pf, s));
     } else {
+      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
       ESN_HIP(launch_amplify(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
                              Nt, pf, s));
       if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
@@ -498,7 +582,7 @@ extern "C" int esn_execute(esn_plan p, void* c, void* f) {
     float tot = 0;
     ESN_HIP(hipEventElapsedTime(&tot, p->ev[5], p->ev[4]));
     if (p->type == 1) {
-      p->stats.t_spread_or_interp = t_a;   // memset + spread
+      p->stats.t_spread_or_interp = t_a;   // spread kernel(s) only
       p->stats.t_deconv_or_amplify = t_b;
     } else {
       p->stats.t_deconv_or_amplify = t_a;
@@ -568,6 +652,7 @@ extern "C" int esn_get_info(esn_plan p, esn_info* o) {
   o->interp_method = p->interp_method;
   o->point_code = p->pts_code;
   o->device_bytes = p->device_bytes;
+  o->ndense_units = p->nunits;
   return ESN_OK;
 }
 

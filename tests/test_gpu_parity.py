@@ -82,3 +82,34 @@ def test_small_type2_full(case):
     err = O.rel_l2(c, ref)
     print(f"type2 {case}: {err:.3e}")
     assert err <= 10 * eps
+
+
+METHOD_CASES = [
+    # dim, N, M, points, prec, eps
+    (3, (16, 13, 20), 30007, "uniform", "f32", 1e-6),
+    (3, (24, 20, 28), 300007, "wrapped_gaussian", "f32", 1e-6),
+    (3, (12, 12, 12), 200003, "wrapped_gaussian", "f32", 1e-3),
+    (2, (40, 33), 50011, "wrapped_gaussian", "f64", 1e-9),
+]
+
+
+@pytest.mark.parametrize("case", METHOD_CASES,
+                         ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in METHOD_CASES])
+def test_spread_methods_agree(case):
+    """Every spreading method (LDS tiles, global atomics, dense columns on the
+    matrix cores) meets the bar, and they agree with each other to rounding."""
+    dim, N, M, points, prec, eps = case
+    coords, c, _ = _inputs(dim, N, M, points, prec, 300 + dim)
+    ref = O.type1(coords, c, +1, N=N)
+    outs = {}
+    methods = [1, 2, 3] if (dim == 3 and prec == "f32" and eps >= 1e-6) else [1, 2]
+    for m in methods:
+        f, info = run_type1(coords, c, N, eps, prec, spread_method=m)
+        err = O.rel_l2(f, ref)
+        print(f"method {m}: rel l2 {err:.3e}, dense units {info.ndense_units}")
+        assert err <= 10 * eps
+        if m == 3 and points == "wrapped_gaussian":
+            assert info.ndense_units > 0
+        outs[m] = f
+    for m in methods[1:]:
+        assert O.rel_l2(outs[m], outs[methods[0]]) < (1e-5 if prec == "f32" else 1e-12)
