@@ -76,11 +76,12 @@ typedef struct esn_opts {
   double upsampfac;   /* fine grid / modes ratio sigma; only 2.0 is supported */
   int sort;           /* 1 (default): bin-sort points (Sec. 4.1); 0: keep order */
   int spread_method;  /* 0 auto; 1 LDS tile per subproblem; 2 global atomics;
-                         3 dense columns on the matrix cores (3D, single, w <= 7)
-                         plus LDS tiles for the rest */
-  int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather */
+                         3 matrix cores (3D, single precision, w <= 7) */
+  int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather;
+                         3 matrix cores (3D, single precision, w <= 7) */
   int bin[3];         /* bin size in fine-grid cells per dim; 0 = default */
-  int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default */
+  int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default
+                         (2048 on the matrix cores, 1024 otherwise) */
   int ntransf_chunk;  /* transforms per fused launch; 0 = as many as fit */
   int block;          /* threads per workgroup for spread/interp; 0 = 256 */
 } esn_opts;
@@ -164,7 +165,7 @@ typedef struct esn_info {
   int bin[3], maxsubprob, nsubprob, nbins_nonempty, ntransf_chunk;
   int spread_method, interp_method, point_code; /* point_code 1: fixed point u32, 2: f64 */
   int64_t device_bytes;  /* device memory the plan holds */
-  int ndense_units;      /* work units of the dense-column spreading path */
+  int ndense_units;      /* subproblems run on the matrix cores (method 3) */
 } esn_info;
 
 /* Describe a plan (host struct filled). */

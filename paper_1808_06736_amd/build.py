@@ -30,7 +30,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 SOURCES = ["params.cpp", "fft.cpp", "plan.cpp",
            "kernels_sort.hip", "kernels_deconv.hip", "kernels_spread.hip",
-           "kernels_interp.hip", "kernels_dense.hip"]
+           "kernels_interp.hip", "kernels_mfma.hip"]
 
 
 def _compile(src: str) -> str:

@@ -22,35 +22,38 @@ struct Coord {
   T f;
 };
 
+// Coordinate m of sorted point i from its record.
 template <typename T>
-__device__ __forceinline__ Coord<T> decode_coord(const void* base, int code, int fbits,
-                                                 int64_t i, int* sh_out, int w) {
+__device__ __forceinline__ Coord<T> decode_coord(const unsigned char* pts, int code, int fbits,
+                                                 int64_t i, int m, int* sh_out, int w) {
   Coord<T> r;
   if (code == kPtsFixed32) {
-    uint32_t v = static_cast<const uint32_t*>(base)[i];
-    uint32_t mask = (fbits >= 32) ? 0xffffffffu : ((1u << fbits) - 1u);
-    uint32_t fr = v & mask;
+    const uint32_t v = reinterpret_cast<const uint32_t*>(pts + i * 16)[m];
+    const uint32_t mask = (fbits >= 32) ? 0xffffffffu : ((1u << fbits) - 1u);
+    const uint32_t fr = v & mask;
     r.cell = (int)(fbits >= 32 ? 0u : (v >> fbits));
     // the fraction fr * 2^-fbits (exact in float when fbits <= 24)
     if constexpr (sizeof(T) == 4) r.f = ldexpf((float)fr, -fbits);
     else r.f = ldexp((double)fr, -fbits);
     // window shift sh (see the window comment below), decided on the exact bits
-    if (w & 1) {
-      uint32_t half = 1u << (fbits - 1);
-      *sh_out = fr > half ? 1 : 0;
-    } else {
-      *sh_out = fr != 0u ? 1 : 0;
-    }
+    if (w & 1) *sh_out = fr > (1u << (fbits - 1)) ? 1 : 0;
+    else *sh_out = fr != 0u ? 1 : 0;
   } else {
-    double t = static_cast<const double*>(base)[i];
-    double c = floor(t);
-    double f = t - c;                      // exact in FP64
+    const double t = reinterpret_cast<const double*>(pts + i * 32)[m];
+    const double c = floor(t);
+    const double f = t - c;                      // exact in FP64
     r.cell = (int)c;
     r.f = (T)f;
     if (w & 1) *sh_out = f > 0.5 ? 1 : 0;
     else *sh_out = f > 0.0 ? 1 : 0;
   }
   return r;
+}
+
+// Original index of sorted point i.
+__device__ __forceinline__ int64_t point_perm(const unsigned char* pts, int code, int64_t i) {
+  return code == kPtsFixed32 ? reinterpret_cast<const int32_t*>(pts + i * 16)[3]
+                             : reinterpret_cast<const int32_t*>(pts + i * 32)[6];
 }
 
 // Window of a point at fine-grid coordinate t = c + f: the w cells

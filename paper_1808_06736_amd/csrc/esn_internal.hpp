@@ -22,12 +22,16 @@ void gauss_legendre_positive(int p, std::vector<double>* nodes,
                              std::vector<double>* weights);
 int quad_nodes_for_width(int w);
 
-// Point storage codes: how a sorted point's fine-grid coordinate t in [0, n)
-// is kept per dimension.
-//   kPtsFixed32: unsigned fixed point t * 2^F (F = 32 - ceil(log2 n) fraction
-//                bits), used by single-precision plans on grids up to 8192;
-//   kPtsF64:     the double t itself.
+// Point storage codes: how a sorted point's fine-grid coordinates t in [0, n)
+// are kept.  Each sorted point is one record holding its coordinates and its
+// original index (the permutation entry):
+//   kPtsFixed32: 16 bytes {uint32 q[3], int32 perm}, q = t * 2^F unsigned fixed
+//                point (F = 32 - ceil(log2 n) fraction bits), used by
+//                single-precision plans on grids up to 8192;
+//   kPtsF64:     32 bytes {double t[3], int32 perm, pad}.
+// Unused dimensions hold 0.
 enum { kPtsFixed32 = 1, kPtsF64 = 2 };
+inline int pts_record_bytes(int code) { return code == kPtsFixed32 ? 16 : 32; }
 
 // Everything a spread/interp kernel needs about the geometry and the sorted
 // points.  Passed by value.
@@ -42,8 +46,7 @@ struct GeomArgs {
   int ntr;               // transforms in this launch
   int64_t cstride;       // elements between transforms in c (= M)
   int64_t gstride;       // elements between transforms in the grid
-  const void* t[3];      // sorted coordinates per dim
-  const int32_t* perm;   // sorted position -> original point index
+  const unsigned char* pts;  // sorted point records (see kPtsFixed32 / kPtsF64)
   const int32_t* sub_bin;    // subproblem -> bin
   const int32_t* sub_start;  // subproblem -> first sorted position
   const int32_t* sub_len;    // subproblem -> number of points
@@ -83,13 +86,9 @@ struct SortArgs {
   int32_t* key;             // [M] cell key of each point
   int32_t* slot;            // [M] rank of the point within its cell
   int32_t* count;           // [ncells + 1] points per cell
-  const int32_t* sstart;    // [ncells + 1] first sorted position of a cell (sparse part)
-  const int32_t* dstart;    // [ncells + 1] same for cells of dense columns, relative to
-                            //   the end of the sparse part (nullptr: no dense part)
-  const int32_t* dcount;    // [ncells + 1] points per cell of dense columns (or nullptr)
+  const int32_t* sstart;    // [ncells + 1] first sorted position of a cell
   int64_t ncells;
-  int32_t* perm;            // [M]
-  void* t[3];               // [M] each (sorted storage)
+  unsigned char* pts;       // [M] sorted point records
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
 };
 hipError_t launch_bin_count(const SortArgs& a, hipStream_t s);
@@ -100,14 +99,7 @@ hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n,
                               int32_t* tmp, hipStream_t s);
-// 3D column classification: a column (b2 consecutive cells) is dense when it
-// holds at least min_dense points.  Writes the per-cell counts split into
-// scount (sparse columns) and dcount (dense columns), and the number of dense
-// work units per column, ucount[col] = ceil(points / max_unit) (0 if sparse).
-hipError_t launch_classify_columns(const int32_t* count, int64_t ncols, int b2, int min_dense,
-                                   int max_unit, int32_t* scount, int32_t* dcount,
-                                   int32_t* ucount, hipStream_t s);
-// Per bin: nsub[b] = ceil(points / maxsub) from the sparse starts; *nonempty
+// Per bin: nsub[b] = ceil(points / maxsub) from the cell starts; *nonempty
 // (device) is incremented per nonempty bin.
 hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub,
                                 int64_t nbins, int maxsub, int32_t* nonempty, hipStream_t s);
@@ -115,13 +107,6 @@ hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t
                                const int32_t* subofs, int64_t nbins, int maxsub,
                                int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
                                hipStream_t s);
-// Dense units: column col with ucount[col] > 0 is cut into ucount[col] runs of
-// its sorted points; unit_col / unit_p0 / unit_p1 at ustart[col] + k.
-// Positions are absolute (the sparse total sstart[ncells] is added).
-hipError_t launch_units_fill(const int32_t* ucount, const int32_t* ustart,
-                             const int32_t* dstart, const int32_t* sstart, int64_t ncells,
-                             int64_t ncols, int b2, int32_t* unit_col, int32_t* unit_p0,
-                             int32_t* unit_p1, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // Spread / interp (kernels_spread.hip, kernels_interp.hip).
@@ -133,18 +118,15 @@ hipError_t launch_spread(int method, int prec, int dim, int w, const GeomArgs& g
 hipError_t launch_interp(int method, int prec, int dim, int w, const GeomArgs& g,
                          int nsub, int block, size_t lds_bytes, const void* grid,
                          void* c, hipStream_t s);
-// Dense 3D columns: MFMA spreading (kernels_dense.hip).  FP32, w <= 7, ntr 1.
-struct DenseArgs {
-  const int32_t* unit_col;
-  const int32_t* unit_p0;
-  const int32_t* unit_p1;
-  const int32_t* dstart;     // dense cell starts (relative to the sparse total)
-  const int32_t* sstart;     // sstart[ncells] = sparse total
-  int64_t ncells;
-};
-hipError_t launch_spread_dense(int w, const GeomArgs& g, const DenseArgs& d, int nunits,
-                               const void* c, void* grid, hipStream_t s);
-size_t dense_lds_bytes(int w, const int* b);
+// Matrix-core spreading / interpolation (kernels_mfma.hip): 3D, single
+// precision, w <= 7, fixed-point coordinates, one transform per launch; one
+// wave per subproblem.
+hipError_t launch_spread_mfma(int w, const GeomArgs& g, int nsub, const void* c, void* grid,
+                              hipStream_t s);
+hipError_t launch_interp_mfma(int w, const GeomArgs& g, int nsub, const void* grid, void* c,
+                              hipStream_t s);
+size_t mfma_spread_lds_bytes(int w, const int* b);
+size_t mfma_interp_lds_bytes(const int* b);
 
 // LDS bytes one subproblem tile needs for ntr transforms (with the spreading
 // kernel's per-point staging when staging is true).
@@ -197,26 +179,12 @@ struct esn_plan_s {
   // points
   int64_t M = -1;                // -1: no points yet
   int64_t cap_M = 0;
-  void* d_t[3] = {nullptr, nullptr, nullptr};
-  int32_t* d_perm = nullptr;
+  unsigned char* d_pts = nullptr;   // [M] sorted point records
   int32_t* d_key = nullptr;
   int32_t* d_slot = nullptr;
   int64_t ncells = 0;            // bins * cells per bin
   int32_t* d_count = nullptr;    // [ncells + 1]
   int32_t* d_sstart = nullptr;   // [ncells + 1]
-  int32_t* d_scount = nullptr;   // [ncells + 1] (dense-capable plans)
-  int32_t* d_dcount = nullptr;   // [ncells + 1]
-  int32_t* d_dstart = nullptr;   // [ncells + 1]
-  int32_t* d_ucount = nullptr;   // [ncols + 1]
-  int32_t* d_ustart = nullptr;   // [ncols + 1]
-  int32_t* d_unit_col = nullptr;
-  int32_t* d_unit_p0 = nullptr;
-  int32_t* d_unit_p1 = nullptr;
-  int64_t cap_units = 0;
-  int nunits = 0;
-  int dense = 0;                 // dense-column MFMA spreading enabled
-  int min_dense = 64;            // points per column for the dense path
-  int max_unit = 2048;           // points per dense work unit
   int32_t* d_nsub = nullptr;
   int32_t* d_subofs = nullptr;
   int32_t* d_scan_tmp = nullptr;

@@ -55,11 +55,11 @@ interp_lds_kernel(const GeomArgs g, const T* __restrict__ grid, cplx_t<T>* __res
 #pragma unroll
     for (int m = 0; m < D; m++) {
       int sh;
-      Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
+      Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
       L[m] = cd.cell - bi[m] * g.b[m] + sh;
       es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
     }
-    const int64_t orig = g.perm[j];
+    const int64_t orig = point_perm(g.pts, g.pts_code, j);
     for (int tr = 0; tr < ntr; tr++) {
       const cplx_t<T>* tl = tile + tr * tc;
       T ar = 0, ai = 0;
@@ -121,14 +121,14 @@ interp_gm_kernel(const GeomArgs g, const T* __restrict__ grid, cplx_t<T>* __rest
 #pragma unroll
   for (int m = 0; m < D; m++) {
     int sh;
-    Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
+    Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
     l0[m] = (int64_t)cd.cell - W / 2 + sh;
     es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
   }
   int64_t idx0[W];
 #pragma unroll
   for (int k = 0; k < W; k++) idx0[k] = wrap_once(l0[0] + k, g.n[0]);
-  const int64_t orig = g.perm[j];
+  const int64_t orig = point_perm(g.pts, g.pts_code, j);
   const cplx_t<T>* gridc = reinterpret_cast<const cplx_t<T>*>(grid);
   for (int tr = 0; tr < g.ntr; tr++) {
     const cplx_t<T>* gt = gridc + tr * g.gstride;

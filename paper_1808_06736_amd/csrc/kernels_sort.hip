@@ -6,12 +6,10 @@
 //               point into it; the count before the increment is the point's
 //               slot within the cell.  Cells are numbered bin-major, so every
 //               bin (and, in 3D, every column of a bin) is a run of keys.
-//   classify  : (3D, dense path) split columns into dense and sparse ones.
 //   scan      : exclusive prefix sums of the counts = first position of a cell.
 //   scatter   : place point j at start[cell] + slot, storing its permutation
 //               entry and its rescaled coordinate.
-//   subprob   : split each bin's sparse points into runs of at most maxsub.
-//   units     : split each dense column into runs of at most max_unit points.
+//   subprob   : split each bin's points into runs of at most maxsub.
 #include "device_common.hpp"
 
 namespace esn {
@@ -23,7 +21,7 @@ constexpr double kThreePi = 9.42477796076937971539;   // 3 pi
 __device__ __forceinline__ double fold_rescale(double x, int64_t n) {
   const double dn = (double)n;
   double t = x * (dn * kInvTwoPi);
-  t -= dn * floor(t / dn);
+  t -= dn * floor(t * (1.0 / dn));   // a rounding slip here is fixed below
   if (t < 0.0) t += dn;
   if (t >= dn) t -= dn;
   if (!(t >= 0.0 && t < dn)) t = 0.0;
@@ -71,6 +69,27 @@ __device__ __forceinline__ int point_key(const SortArgs& a, int64_t j, int* flag
   return bin * cpb + local;
 }
 
+// Store sorted point pos: coordinates (unused dims 0) and original index j,
+// as one 16-byte or two 16-byte vector stores.
+__device__ __forceinline__ void write_record(const SortArgs& a, int64_t pos, const uint32_t* q,
+                                             const double* t, int64_t j) {
+  if (a.pts_code == kPtsFixed32) {
+    uint4 r;
+    r.x = q[0];
+    r.y = a.dim >= 2 ? q[1] : 0u;
+    r.z = a.dim >= 3 ? q[2] : 0u;
+    r.w = (uint32_t)j;
+    reinterpret_cast<uint4*>(a.pts)[pos] = r;
+  } else {
+    double2* d = reinterpret_cast<double2*>(a.pts + pos * 32);
+    d[0] = make_double2(t[0], a.dim >= 2 ? t[1] : 0.0);
+    double2 hi;
+    hi.x = a.dim >= 3 ? t[2] : 0.0;
+    hi.y = __longlong_as_double((long long)(uint32_t)j);   // perm in the low 32 bits
+    d[1] = hi;
+  }
+}
+
 template <typename CTy>
 __global__ void bin_count_kernel(const SortArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -93,15 +112,8 @@ __global__ void scatter_kernel(const SortArgs a) {
   double t[3];
   point_key<CTy>(a, j, &flag, q, t);
   const int key = a.key[j];
-  int64_t pos;
-  if (a.dcount && a.dcount[key] > 0) pos = (int64_t)a.sstart[a.ncells] + a.dstart[key];
-  else pos = a.sstart[key];
-  pos += a.slot[j];
-  a.perm[pos] = (int32_t)j;
-  for (int m = 0; m < a.dim; m++) {
-    if (a.pts_code == kPtsFixed32) static_cast<uint32_t*>(a.t[m])[pos] = q[m];
-    else static_cast<double*>(a.t[m])[pos] = t[m];
-  }
+  const int64_t pos = (int64_t)a.sstart[key] + a.slot[j];
+  write_record(a, pos, q, t, j);
 }
 
 template <typename CTy>
@@ -113,11 +125,7 @@ __global__ void encode_unsorted_kernel(const SortArgs a) {
   double t[3];
   point_key<CTy>(a, j, &flag, q, t);
   if (flag) atomicOr(a.flags, flag);
-  a.perm[j] = (int32_t)j;
-  for (int m = 0; m < a.dim; m++) {
-    if (a.pts_code == kPtsFixed32) static_cast<uint32_t*>(a.t[m])[j] = q[m];
-    else static_cast<double*>(a.t[m])[j] = t[m];
-  }
+  write_record(a, j, q, t, j);
 }
 
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -231,23 +239,7 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_
   return hipGetLastError();
 }
 
-// ---- column classification, subproblems, dense units ----
-__global__ void classify_kernel(const int32_t* __restrict__ count, int64_t ncols, int b2,
-                                int min_dense, int max_unit, int32_t* __restrict__ scount,
-                                int32_t* __restrict__ dcount, int32_t* __restrict__ ucount) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  int tot = 0;
-  for (int z = 0; z < b2; z++) tot += count[col * b2 + z];
-  const bool dense = tot >= min_dense;
-  for (int z = 0; z < b2; z++) {
-    const int v = count[col * b2 + z];
-    scount[col * b2 + z] = dense ? 0 : v;
-    dcount[col * b2 + z] = dense ? v : 0;
-  }
-  ucount[col] = dense ? (tot + max_unit - 1) / max_unit : 0;
-}
-
+// ---- subproblems ----
 __global__ void subprob_count_kernel(const int32_t* __restrict__ sstart, int64_t cpb,
                                      int32_t* __restrict__ nsub, int64_t nbins, int maxsub,
                                      int32_t* nonempty) {
@@ -277,39 +269,9 @@ __global__ void subprob_fill_kernel(const int32_t* __restrict__ sstart, int64_t 
   }
 }
 
-__global__ void units_fill_kernel(const int32_t* __restrict__ ucount,
-                                  const int32_t* __restrict__ ustart,
-                                  const int32_t* __restrict__ dstart,
-                                  const int32_t* __restrict__ sstart, int64_t ncells,
-                                  int64_t ncols, int b2, int32_t* __restrict__ unit_col,
-                                  int32_t* __restrict__ unit_p0, int32_t* __restrict__ unit_p1) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  const int nu = ucount[col];
-  if (nu == 0) return;
-  const int base = sstart[ncells];
-  const int p0 = base + dstart[col * b2];
-  const int p1 = base + dstart[(col + 1) * b2];
-  const int per = (p1 - p0 + nu - 1) / nu;
-  const int o = ustart[col];
-  for (int k = 0; k < nu; k++) {
-    unit_col[o + k] = (int32_t)col;
-    unit_p0[o + k] = p0 + k * per;
-    unit_p1[o + k] = min(p1, p0 + (k + 1) * per);
-  }
-}
-
 __global__ void iota_kernel(int32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
-}
-
-hipError_t launch_classify_columns(const int32_t* count, int64_t ncols, int b2, int min_dense,
-                                   int max_unit, int32_t* scount, int32_t* dcount,
-                                   int32_t* ucount, hipStream_t s) {
-  hipLaunchKernelGGL(classify_kernel, dim3(nblocks(ncols, 256)), dim3(256), 0, s, count, ncols,
-                     b2, min_dense, max_unit, scount, dcount, ucount);
-  return hipGetLastError();
 }
 
 hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub, int64_t nbins,
@@ -325,15 +287,6 @@ hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t
                                hipStream_t s) {
   hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, sstart,
                      cpb, nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
-  return hipGetLastError();
-}
-
-hipError_t launch_units_fill(const int32_t* ucount, const int32_t* ustart, const int32_t* dstart,
-                             const int32_t* sstart, int64_t ncells, int64_t ncols, int b2,
-                             int32_t* unit_col, int32_t* unit_p0, int32_t* unit_p1,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(units_fill_kernel, dim3(nblocks(ncols, 256)), dim3(256), 0, s, ucount,
-                     ustart, dstart, sstart, ncells, ncols, b2, unit_col, unit_p0, unit_p1);
   return hipGetLastError();
 }
 

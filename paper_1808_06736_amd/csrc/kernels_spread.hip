@@ -67,11 +67,11 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
 #pragma unroll
       for (int m = 0; m < D; m++) {
         int sh;
-        Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
+        Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
         st->loc[lane][m] = cd.cell - bi[m] * g.b[m] + sh;
         es_weights_t<W, T>(sh, cd.f, beta, st->ker[lane][m]);
       }
-      const int64_t orig = g.perm[j];
+      const int64_t orig = point_perm(g.pts, g.pts_code, j);
       for (int tr = 0; tr < ntr; tr++) stc[lane * ntr + tr] = c[tr * g.cstride + orig];
     }
     __syncthreads();
@@ -167,14 +167,14 @@ spread_gm_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restric
 #pragma unroll
   for (int m = 0; m < D; m++) {
     int sh;
-    Coord<T> cd = decode_coord<T>(g.t[m], g.pts_code, g.fbits[m], j, &sh, W);
+    Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
     l0[m] = (int64_t)cd.cell - W / 2 + sh;   // in [-W/2, n)
     es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
   }
   int64_t idx0[W];
 #pragma unroll
   for (int k = 0; k < W; k++) idx0[k] = wrap_once(l0[0] + k, g.n[0]);
-  const int64_t orig = g.perm[j];
+  const int64_t orig = point_perm(g.pts, g.pts_code, j);
   for (int tr = 0; tr < g.ntr; tr++) {
     const cplx_t<T> cv = c[tr * g.cstride + orig];
     T* gt = grid + 2 * tr * g.gstride;

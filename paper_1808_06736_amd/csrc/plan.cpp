@@ -94,7 +94,6 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
     g.b[m] = p->bin[m];
     g.nb[m] = p->nb[m];
     g.fbits[m] = p->fbits[m];
-    g.t[m] = p->d_t[m];
   }
   g.pts_code = p->pts_code;
   g.beta = p->par.beta;
@@ -102,7 +101,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
   g.ntr = ntr;
   g.cstride = p->M;
   g.gstride = nf_total(p);
-  g.perm = p->d_perm;
+  g.pts = p->d_pts;
   g.sub_bin = p->d_sub_bin;
   g.sub_start = p->d_sub_start;
   g.sub_len = p->d_sub_len;
@@ -110,8 +109,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
 }
 
 void free_points(esn_plan_s* p) {
-  for (int m = 0; m < 3; m++) dfree(p, &p->d_t[m]);
-  dfree(p, (void**)&p->d_perm);
+  dfree(p, (void**)&p->d_pts);
   dfree(p, (void**)&p->d_key);
   dfree(p, (void**)&p->d_slot);
   p->cap_M = 0;
@@ -124,27 +122,16 @@ void free_subs(esn_plan_s* p) {
   p->cap_sub = 0;
 }
 
-void free_units(esn_plan_s* p) {
-  dfree(p, (void**)&p->d_unit_col);
-  dfree(p, (void**)&p->d_unit_p0);
-  dfree(p, (void**)&p->d_unit_p1);
-  p->cap_units = 0;
-}
+
 
 void destroy_all(esn_plan_s* p) {
   (void)hipStreamSynchronize(p->stream);
   free_points(p);
   free_subs(p);
-  free_units(p);
   for (int m = 0; m < 3; m++) dfree(p, (void**)&p->d_pf[m]);
   dfree(p, &p->d_grid);
   dfree(p, (void**)&p->d_count);
   dfree(p, (void**)&p->d_sstart);
-  dfree(p, (void**)&p->d_scount);
-  dfree(p, (void**)&p->d_dcount);
-  dfree(p, (void**)&p->d_dstart);
-  dfree(p, (void**)&p->d_ucount);
-  dfree(p, (void**)&p->d_ustart);
   dfree(p, (void**)&p->d_nsub);
   dfree(p, (void**)&p->d_subofs);
   dfree(p, (void**)&p->d_scan_tmp);
@@ -208,7 +195,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   if (o.bin[0] < 0 || o.bin[1] < 0 || o.bin[2] < 0 || o.maxsubprob < 0 ||
       o.ntransf_chunk < 0 || o.block < 0 || o.block > 1024 ||
       (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 3 ||
-      o.interp_method < 0 || o.interp_method > 2)
+      o.interp_method < 0 || o.interp_method > 3)
     return ESN_ERR_BAD_ARG;
 
   esn_plan_s* p = new (std::nothrow) esn_plan_s();
@@ -242,6 +229,16 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
 
   // ---- bins, subproblems, methods, chunk ----
   default_bins(dim, p->bin);
+  // the matrix-core kernels (3D single precision, w <= 7) work best on small
+  // bins: 2 x 2 columns of 8 cells
+  const bool mfma_candidate = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
+                              o.spread_method != 1 && o.spread_method != 2 &&
+                              o.interp_method != 1 && o.interp_method != 2;
+  if (mfma_candidate) {
+    p->bin[0] = 2;
+    p->bin[1] = 2;
+    p->bin[2] = 8;
+  }
   for (int m = 0; m < dim; m++) {
     if (o.bin[m] > 0) p->bin[m] = o.bin[m];
     p->bin[m] = (int)std::min<int64_t>(p->bin[m], p->nf[m]);
@@ -267,16 +264,20 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   p->maxsub = o.maxsubprob > 0 ? o.maxsubprob : 1024;
   p->block = o.block > 0 ? o.block : 256;
   const bool tile_fits = tile_lds_bytes(prec, dim, w, p->bin, 1) <= budget;
-  // dense-column MFMA spreading: 3D single precision, w <= 7, one transform
-  // per launch; method 3 asks for it, method 0 takes it when possible
-  const bool dense_ok = type == 1 && dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
-                        tile_fits && dense_lds_bytes(w, p->bin) <= budget;
-  p->spread_method = o.spread_method ? o.spread_method : (tile_fits ? (dense_ok ? 3 : 1) : 2);
-  if (p->spread_method == 3 && !dense_ok) {
+  // matrix-core spreading / interpolation: 3D single precision, w <= 7,
+  // fixed-point coordinates, one transform per launch (method 3)
+  const bool mfma_ok = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
+                       p->pts_code == kPtsFixed32 &&
+                       mfma_spread_lds_bytes(w, p->bin) <= budget &&
+                       mfma_interp_lds_bytes(p->bin) <= budget;
+  p->spread_method = o.spread_method ? o.spread_method : (mfma_ok ? 3 : (tile_fits ? 1 : 2));
+  p->interp_method = o.interp_method ? o.interp_method : (mfma_ok ? 3 : (tile_fits ? 1 : 2));
+  if ((p->spread_method == 3 || p->interp_method == 3) && !mfma_ok) {
     delete p;
     return ESN_ERR_BAD_ARG;
   }
-  p->interp_method = o.interp_method ? o.interp_method : (tile_fits ? 1 : 2);
+  const bool mfma = (type == 1 && p->spread_method == 3) || (type == 2 && p->interp_method == 3);
+  if (mfma && o.maxsubprob <= 0) p->maxsub = 2048;
   if (!o.sort) p->spread_method = p->interp_method = 2;
   if (!tile_fits) {
     if (p->spread_method == 1 || p->interp_method == 1) {
@@ -285,9 +286,9 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     }
   }
   const bool uses_lds = (type == 1 && (p->spread_method == 1 || p->spread_method == 3)) ||
-                        (type == 2 && p->interp_method == 1);
+                        (type == 2 && (p->interp_method == 1 || p->interp_method == 3));
   int chunk = o.ntransf_chunk > 0 ? o.ntransf_chunk : ntransf;
-  if (type == 1 && p->spread_method == 3) chunk = 1;
+  if (mfma) chunk = 1;
   if (uses_lds) {
     size_t one = tile_lds_bytes(prec, dim, w, p->bin, 1);
     int lim = (int)std::max<size_t>(1, budget / one);
@@ -303,7 +304,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   chunk = std::max(1, std::min({chunk, ntransf, memlim}));
   p->chunk = chunk;
   p->tail = ntransf % chunk;
-  p->dense = type == 1 && p->spread_method == 3;
+
 
   int rc = ESN_OK;
   hipStream_t s = p->stream;
@@ -356,22 +357,13 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
     p->ncells = p->nbins * cpb;
     if (p->ncells + 1 > (int64_t)1 << 31) return fail(ESN_ERR_BAD_ARG);
-    const int64_t ncols = p->nbins * p->bin[0] * p->bin[1];
-    const int64_t nscan = std::max({p->ncells + 1, ncols + 1, p->nbins});
+    const int64_t nscan = std::max(p->ncells + 1, p->nbins);
     if (dalloc(p, (void**)&p->d_count, 4 * (p->ncells + 1)) ||
         dalloc(p, (void**)&p->d_sstart, 4 * (p->ncells + 1)) ||
         dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
         dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(nscan) + 1)) ||
         dalloc(p, (void**)&p->d_flags, 4 * 4))
       return fail(ESN_ERR_ALLOC);
-    if (p->dense) {
-      if (dalloc(p, (void**)&p->d_scount, 4 * (p->ncells + 1)) ||
-          dalloc(p, (void**)&p->d_dcount, 4 * (p->ncells + 1)) ||
-          dalloc(p, (void**)&p->d_dstart, 4 * (p->ncells + 1)) ||
-          dalloc(p, (void**)&p->d_ucount, 4 * (ncols + 1)) ||
-          dalloc(p, (void**)&p->d_ustart, 4 * (ncols + 1)))
-        return fail(ESN_ERR_ALLOC);
-    }
   }
   if (hipHostMalloc((void**)&p->h_pinned, 4 * 8, hipHostMallocDefault) != hipSuccess)
     return fail(ESN_ERR_ALLOC);
@@ -397,11 +389,8 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
   if (M > p->cap_M) {
     free_points(p);
-    size_t el = p->pts_code == kPtsF64 ? sizeof(double) : sizeof(uint32_t);
-    for (int m = 0; m < p->dim; m++)
-      if (dalloc(p, &p->d_t[m], M * el)) return ESN_ERR_ALLOC;
-    if (dalloc(p, (void**)&p->d_perm, 4 * M) || dalloc(p, (void**)&p->d_key, 4 * M) ||
-        dalloc(p, (void**)&p->d_slot, 4 * M))
+    if (dalloc(p, (void**)&p->d_pts, (size_t)pts_record_bytes(p->pts_code) * M) ||
+        dalloc(p, (void**)&p->d_key, 4 * M) || dalloc(p, (void**)&p->d_slot, 4 * M))
       return ESN_ERR_ALLOC;
     p->cap_M = M;
   }
@@ -416,7 +405,6 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     a.b[m] = p->bin[m];
     a.nb[m] = p->nb[m];
     a.fbits[m] = p->fbits[m];
-    a.t[m] = p->d_t[m];
   }
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
@@ -424,41 +412,24 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   a.slot = p->d_slot;
   a.count = p->d_count;
   a.sstart = p->d_sstart;
-  a.dstart = p->dense ? p->d_dstart : nullptr;
-  a.dcount = p->dense ? p->d_dcount : nullptr;
   a.ncells = p->ncells;
-  a.perm = p->d_perm;
+  a.pts = p->d_pts;
   a.flags = p->d_flags;
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
-  int nsub = 0, nunits = 0;
+  int nsub = 0;
   const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
-  const int64_t ncols = p->nbins * p->bin[0] * p->bin[1];
   if (p->opts.sort) {
     ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * (p->ncells + 1), s));
     ESN_HIP(launch_bin_count(a, s));
-    if (p->dense) {
-      ESN_HIP(launch_classify_columns(p->d_count, ncols, p->bin[2], p->min_dense, p->max_unit,
-                                      p->d_scount, p->d_dcount, p->d_ucount, s));
-      ESN_HIP(hipMemsetAsync(p->d_scount + p->ncells, 0, 4, s));
-      ESN_HIP(hipMemsetAsync(p->d_dcount + p->ncells, 0, 4, s));
-      ESN_HIP(hipMemsetAsync(p->d_ucount + ncols, 0, 4, s));
-      ESN_HIP(exclusive_scan_i32(p->d_scount, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
-      ESN_HIP(exclusive_scan_i32(p->d_dcount, p->d_dstart, p->ncells + 1, p->d_scan_tmp, s));
-      ESN_HIP(exclusive_scan_i32(p->d_ucount, p->d_ustart, ncols + 1, p->d_scan_tmp, s));
-    } else {
-      ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
-    }
+    ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
     ESN_HIP(launch_scatter(a, s));
     ESN_HIP(launch_subprob_count(p->d_sstart, cpb, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
     ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned + 2, p->d_subofs + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned + 3, p->d_nsub + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
-    if (p->dense)
-      ESN_HIP(hipMemcpyAsync(p->h_pinned + 4, p->d_ustart + ncols, 4, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipStreamSynchronize(s));
     nsub = p->h_pinned[2] + p->h_pinned[3];
-    nunits = p->dense ? p->h_pinned[4] : 0;
   } else {
     ESN_HIP(launch_encode_unsorted(a, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
@@ -479,20 +450,7 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     }
     ESN_HIP(launch_subprob_fill(p->d_sstart, cpb, p->d_nsub, p->d_subofs, p->nbins, p->maxsub,
                                 p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
-    if (p->dense) {
-      if (nunits > p->cap_units) {
-        free_units(p);
-        if (dalloc(p, (void**)&p->d_unit_col, 4 * (size_t)nunits) ||
-            dalloc(p, (void**)&p->d_unit_p0, 4 * (size_t)nunits) ||
-            dalloc(p, (void**)&p->d_unit_p1, 4 * (size_t)nunits))
-          return ESN_ERR_ALLOC;
-        p->cap_units = nunits;
-      }
-      ESN_HIP(launch_units_fill(p->d_ucount, p->d_ustart, p->d_dstart, p->d_sstart, p->ncells,
-                                ncols, p->bin[2], p->d_unit_col, p->d_unit_p0, p->d_unit_p1, s));
-    }
   }
-  p->nunits = nunits;
   p->nsub = nsub;
   p->M = M;
   if (p->opts.debug) {
@@ -507,28 +465,25 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
 
 static int run_spread(esn_plan_s* p, int ntr, const void* c, void* grid) {
   GeomArgs g = make_geom(p, ntr);
-  const int method = p->spread_method == 3 ? 1 : p->spread_method;
-  size_t lds = method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
-  ESN_HIP(launch_spread(method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds, c, grid,
-                        p->stream));
   if (p->spread_method == 3) {
-    DenseArgs d;
-    d.unit_col = p->d_unit_col;
-    d.unit_p0 = p->d_unit_p0;
-    d.unit_p1 = p->d_unit_p1;
-    d.dstart = p->d_dstart;
-    d.sstart = p->d_sstart;
-    d.ncells = p->ncells;
-    ESN_HIP(launch_spread_dense(p->par.w, g, d, p->nunits, c, grid, p->stream));
+    ESN_HIP(launch_spread_mfma(p->par.w, g, p->nsub, c, grid, p->stream));
+    return ESN_OK;
   }
+  size_t lds = p->spread_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
+  ESN_HIP(launch_spread(p->spread_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds, c,
+                        grid, p->stream));
   return ESN_OK;
 }
 
 static int run_interp(esn_plan_s* p, int ntr, const void* grid, void* c) {
   GeomArgs g = make_geom(p, ntr);
+  if (p->interp_method == 3) {
+    ESN_HIP(launch_interp_mfma(p->par.w, g, p->nsub, grid, c, p->stream));
+    return ESN_OK;
+  }
   size_t lds = p->interp_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr, false) : 0;
-  ESN_HIP(launch_interp(p->interp_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds,
-                        grid, c, p->stream));
+  ESN_HIP(launch_interp(p->interp_method, p->prec, p->dim, p->par.w, g, p->nsub, p->block, lds, grid,
+                        c, p->stream));
   return ESN_OK;
 }
 
@@ -652,7 +607,8 @@ extern "C" int esn_get_info(esn_plan p, esn_info* o) {
   o->interp_method = p->interp_method;
   o->point_code = p->pts_code;
   o->device_bytes = p->device_bytes;
-  o->ndense_units = p->nunits;
+  o->ndense_units = ((p->type == 1 && p->spread_method == 3) ||
+                     (p->type == 2 && p->interp_method == 3)) ? p->nsub : 0;
   return ESN_OK;
 }
 

@@ -113,3 +113,25 @@ def test_spread_methods_agree(case):
         outs[m] = f
     for m in methods[1:]:
         assert O.rel_l2(outs[m], outs[methods[0]]) < (1e-5 if prec == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("case", METHOD_CASES,
+                         ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in METHOD_CASES])
+def test_interp_methods_agree(case):
+    """Every interpolation method (LDS tiles, direct gathers, dense columns on
+    the matrix cores) meets the bar, and they agree with each other to rounding."""
+    dim, N, M, points, prec, eps = case
+    coords, _, f = _inputs(dim, N, M, points, prec, 400 + dim)
+    ref = O.type2(coords, f, -1)
+    outs = {}
+    methods = [1, 2, 3] if (dim == 3 and prec == "f32" and eps >= 1e-6) else [1, 2]
+    for m in methods:
+        cc, info = run_type2(coords, f, N, eps, prec, interp_method=m)
+        err = O.rel_l2(cc, ref)
+        print(f"interp method {m}: rel l2 {err:.3e}, dense units {info.ndense_units}")
+        assert err <= 10 * eps
+        if m == 3 and points == "wrapped_gaussian":
+            assert info.ndense_units > 0
+        outs[m] = cc
+    for m in methods[1:]:
+        assert O.rel_l2(outs[m], outs[methods[0]]) < (1e-5 if prec == "f32" else 1e-12)
