@@ -51,6 +51,12 @@ def parse():
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="modes per dim (type 1) in the oracle sample; 0 = default")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), the "
+                         "reference for scaling HBM byte counters")
+    ap.add_argument("--traffic", default="",
+                    help="JSON with measured HBM bytes per launch of the dominant "
+                         "kernel ({\"kernel\": ..., \"bytes\": ...}) for roofline.traffic")
     return ap.parse_args()
 
 
@@ -73,8 +79,42 @@ def algorithmic_work(w, dim, M, ntr, nf, prec, kind):
     return bytes_, flops
 
 
+def measured_traffic(path, kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE scaled
+    by a plain copy), from profiles/traffic_<workload>.json; None when missing or
+    when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = path or os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if tr.get("kernel") != kernel or tr.get("workload") != workload:
+        return None
+    src = os.path.join(ROOT, tr.get("source_file", ""))
+    if not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != tr.get("source_sha256_16"):
+        return None
+    return tr["bytes"]
+
+
+def copy_calibration(mib):
+    """A plain copy of a known size: each launch reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes_read": n * 4, "bytes_written": n * 4}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(this build has no multi-GPU path)", file=sys.stderr)
@@ -159,16 +199,23 @@ def main():
     peak_alu = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
     intensity = flops / bytes_
     ridge = peak_alu * 1e12 / (HBM_PEAK_GBS * 1e9)
-    kname = {1: "spread_lds_kernel", 2: "interp_lds_kernel"}[tdom]
+    method = inf.spread_method if tdom == 1 else inf.interp_method
+    kname = {(1, 3): "spread_mfma_kernel", (2, 3): "interp_mfma_kernel",
+             (1, 1): "spread_lds_kernel", (2, 1): "interp_lds_kernel",
+             (1, 2): "spread_gm_kernel", (2, 2): "interp_gm_kernel"}[(tdom, method)]
     if intensity >= ridge:
-        roof = {"bound": "alu", "achieved": flops / dur_s / 1e12, "peak": peak_alu,
-                "unit": "TFLOP/s"}
+        # arithmetic-bound: on the matrix cores (method 3) against the dense
+        # MFMA peak of the precision, otherwise against the vector ALU peak
+        roof = {"bound": "mfma" if method == 3 else "alu",
+                "achieved": flops / dur_s / 1e12, "peak": peak_alu, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / dur_s / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = f"{kname}<D={dim},W={inf.w},{'float' if prec == 'f32' else 'double'}>"
+    roof["kernel"] = (f"{kname}<{inf.w}>" if method == 3 else
+                      f"{kname}<{dim},{inf.w},{'float' if prec == 'f32' else 'double'}>")
+    roof["traffic"] = measured_traffic(args.traffic, roof["kernel"], wl.name)
     roof["algorithmic_bytes"] = bytes_
     roof["algorithmic_flops"] = flops
     roof["mean_launch_ms"] = kern_t[tdom]
@@ -218,7 +265,7 @@ def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
     dim, M, ntr = wl.dim, wl.M, wl.ntransf
     N = wl.N[:dim]
     Ntot = math.prod(N)
-    S = cpu_sample or {1: 200, 2: 24, 3: 10}[dim]
+    S = cpu_sample or {1: 1000, 2: 100, 3: 24}[dim]
     t_full = 0.0
     parts = []
     parity = {}
@@ -236,7 +283,7 @@ def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
         idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
         parity["type1_rel_l2"] = O.rel_l2(fg[idx], ref)
     if 2 in wl.types:
-        sel = I.sample_points(coords, 1024, seed=37)
+        sel = I.sample_points(coords, 16384 if dim == 3 else 4096, seed=37)
         f0 = f_np[0] if ntr > 1 else f_np
         t0 = time.perf_counter()
         ref = O.type2([a[sel] for a in coords], f0, -1, nthreads=threads)

@@ -50,6 +50,7 @@ struct GeomArgs {
   const int32_t* sub_bin;    // subproblem -> bin
   const int32_t* sub_start;  // subproblem -> first sorted position
   const int32_t* sub_len;    // subproblem -> number of points
+  int nsub;                  // number of subproblems
 };
 
 // ---- kernel launchers (kernels_*.hip) ----

@@ -105,6 +105,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
   g.sub_bin = p->d_sub_bin;
   g.sub_start = p->d_sub_start;
   g.sub_len = p->d_sub_len;
+  g.nsub = p->nsub;
   return g;
 }
 
