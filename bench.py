@@ -136,10 +136,18 @@ def main():
     c_in = torch.from_numpy(c_np).cuda()
     f_in = torch.from_numpy(f_np).cuda()
 
+    tuned = {}
+    if wl.extra.get("autotune"):
+        # bin / subproblem / fusion options picked by timing on these points,
+        # before the timed region (like planning)
+        from paper_1808_06736_amd import autotune
+        for t in wl.types:
+            tuned[t], _ = autotune.tune(t, N, wl.eps, coords, c_in if t == 1 else f_in,
+                                        dtype=cdt, ntransf=ntr)
     plans = {}
     outs = {}
     for t in wl.types:
-        plans[t] = B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1)
+        plans[t] = B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1, **tuned.get(t, {}))
         plans[t].setpts(*coords)
         if t == 1:
             outs[t] = torch.empty_like(f_in)
@@ -242,6 +250,13 @@ def main():
         "roofline": roof,
     }
 
+    if tuned:
+        out["config"]["autotuned"] = {f"type{t}": {k: (list(v) if isinstance(v, tuple) else v)
+                                                   for k, v in o.items()}
+                                      for t, o in tuned.items()}
+    if ntr > 1:
+        out["batched_vs_plain"] = batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
                                                           outs, args.cpu_sample)
@@ -250,12 +265,67 @@ def main():
     print(json.dumps(out))
 
 
+def batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt, reps=5):
+    """NU pts/s of the fused batched execute against the same ntransf vectors
+    run one at a time: on one plan (ntransf = 1, points already sorted), and as
+    one-shot calls that plan, sort and execute per vector (the paper's plain
+    interface, Sec. 2)."""
+    import torch
+    from paper_1808_06736_amd import binding as B
+    N = wl.N[:wl.dim]
+    ntr, M = wl.ntransf, wl.M
+    res = {}
+
+    def best(fn, reps=reps):
+        fn()
+        torch.cuda.synchronize()
+        b = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            b = min(b, time.perf_counter() - t0)
+        return b
+
+    t = wl.types[0]
+    pb = plans[t]
+    tb = best(lambda: pb.execute(c_in, outs[1]) if t == 1 else pb.execute(outs[2], f_in))
+    res["batched_pts_per_s"] = M * ntr / tb
+    p1 = B.Plan(t, N, wl.eps, dtype=cdt)
+    p1.setpts(*coords)
+    if t == 1:
+        o1 = torch.empty(tuple(reversed(N)), dtype=cdt, device="cuda")
+        loop = lambda: [p1.execute(c_in[k], o1) for k in range(ntr)]
+    else:
+        o1 = torch.empty(M, dtype=cdt, device="cuda")
+        loop = lambda: [p1.execute(o1, f_in[k]) for k in range(ntr)]
+    tl = best(loop)
+    p1.close()
+    res["plan_loop_pts_per_s"] = M * ntr / tl
+
+    def oneshots():
+        for k in range(ntr):
+            q = B.Plan(t, N, wl.eps, dtype=cdt)
+            q.setpts(*coords)
+            if t == 1:
+                q.execute(c_in[k], o1)
+            else:
+                q.execute(o1, f_in[k])
+            q.close()
+    to = best(oneshots, reps=2)
+    res["oneshot_pts_per_s"] = M * ntr / to
+    res["speedup_vs_plan_loop"] = tl / tb
+    res["speedup_vs_oneshot"] = to / tb
+    return res
+
+
 def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
     """Time the FP64 oracle on a bounded sample and scale to NU pts/s of a full step.
 
     type 1: a seeded product set of S modes per dim (incl. min, 0, max) for all M
-    points -> extrapolated to all N modes.  type 2: 1024 seeded points (incl.
-    the extreme ones) over all N modes -> extrapolated to all M points.  For
+    points -> extrapolated to all N modes.  type 2: seeded points (incl. the
+    extreme ones; about 2e10 terms, at least 16384 points or all of them) over
+    all N modes -> extrapolated to all M points.  For
     batched workloads only the first transform is timed and the time scaled
     by ntransf.
     """
@@ -283,7 +353,8 @@ def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
         idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
         parity["type1_rel_l2"] = O.rel_l2(fg[idx], ref)
     if 2 in wl.types:
-        sel = I.sample_points(coords, 16384 if dim == 3 else 4096, seed=37)
+        # about 2e10 oracle terms (all points when M is small)
+        sel = I.sample_points(coords, max(16384, int(2e10 // Ntot)), seed=37)
         f0 = f_np[0] if ntr > 1 else f_np
         t0 = time.perf_counter()
         ref = O.type2([a[sel] for a in coords], f0, -1, nthreads=threads)

@@ -167,7 +167,7 @@ WORKLOADS = {
     "2d_t2_batched_radial": Workload("2d_t2_batched_radial", 2, (2,),
                                      (256, 256, 1), 400 * 512, 1e-4, "f32",
                                      "radial", ntransf=32, seed=4,
-                                     extra={"nspokes": 400, "nrad": 512}),
+                                     extra={"nspokes": 400, "nrad": 512, "autotune": True}),
 }
 
 
