@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), the "
                          "reference for scaling HBM byte counters")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests in the serving measurement (0: skip it)")
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.8, 2.0],
+                    help="offered loads as fractions of the plain serial throughput")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--traffic", default="",
                     help="JSON with measured HBM bytes per launch of the dominant "
                          "kernel ({\"kernel\": ..., \"bytes\": ...}) for roofline.traffic")
@@ -257,12 +262,112 @@ def main():
     if ntr > 1:
         out["batched_vs_plain"] = batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt)
 
+    if args.serve_requests > 0 and args.workload == "3d_clustered":
+        out["serving"] = serve_bench(args.serve_requests, args.serve_load, args.serve_slots)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
                                                           outs, args.cpu_sample)
     for p in plans.values():
         p.close()
     print(json.dumps(out))
+
+
+def serve_bench(nreq, loads, nslots, seed=5):
+    """Served vs plain latency on the serving mix (Poisson arrivals).
+
+    The mix: type U{1,2}, d U{2,3}, N_i U[64,512] (2D) / U[64,160] (3D), M
+    log-uniform in [1e5, 5e6], uniform or clustered points, eps U{1e-3, 1e-6
+    (single), 1e-9 (double)} (inputs.serve_mix).  Plain = the same requests
+    one at a time in arrival order, each planned, sorted, executed and freed
+    (the paper's one-call interface, Sec. 2).  Served = the request loop with
+    `nslots` worker streams.  Arrivals are Poisson at each of `loads` x the plain
+    serial request rate (above 1 the plain path cannot keep up and throughput
+    shows capacity).  Every shape is run once untimed first on both paths (rocFFT
+    compiles kernels for new sizes), then the timed pass starts.
+    """
+    import torch
+    from paper_1808_06736_amd import binding as B
+    reqs = I.serve_mix(nreq, seed=seed)
+    data = []
+    for k, wl in enumerate(reqs):
+        cdt = torch.complex64 if wl.prec == "f32" else torch.complex128
+        rdt = torch.float32 if wl.prec == "f32" else torch.float64
+        xs = I.device_points(wl.M, wl.dim, 20_000 + k, wl.points, 0.3, rdt)
+        N = wl.N[:wl.dim]
+        if wl.types[0] == 1:
+            c = I.device_complex((wl.M,), 30_000 + k, cdt)
+            f = torch.empty(tuple(reversed(N)), dtype=cdt, device="cuda")
+        else:
+            c = torch.empty(wl.M, dtype=cdt, device="cuda")
+            f = I.device_complex(tuple(reversed(N)), 30_000 + k, cdt)
+        data.append((wl, xs, c, f))
+    torch.cuda.synchronize()
+
+    def plain_one(wl, xs, c, f):
+        p = B.Plan(wl.types[0], wl.N[:wl.dim], wl.eps, dtype=c.dtype)
+        p.setpts(*xs)
+        p.execute(c, f)
+        torch.cuda.synchronize()
+        p.close()
+
+    # warm-up: every shape once on both paths
+    for d in data:
+        plain_one(*d)
+    srv = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
+    for tk in [srv.submit(wl.types[0], xs, c, f, wl.eps) for wl, xs, c, f in data]:
+        srv.wait(tk)
+
+    # plain serial service time -> arrival rates
+    t0 = time.perf_counter()
+    for d in data:
+        plain_one(*d)
+    serial = time.perf_counter() - t0
+    pts = float(sum(wl.M for wl, *_ in data))
+
+    def wait_until(t_abs):
+        while True:
+            dt = t_abs - time.perf_counter()
+            if dt <= 0:
+                return
+            time.sleep(dt - 2e-4 if dt > 1e-3 else 0)
+
+    runs = []
+    for load in loads:
+        rate = load * nreq / serial
+        gaps = np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / rate, size=nreq)
+        arrive = np.cumsum(gaps)
+        # plain: one at a time, in arrival order
+        lat = []
+        start = time.perf_counter()
+        for k, d in enumerate(data):
+            wait_until(start + arrive[k])
+            plain_one(*d)
+            lat.append(time.perf_counter() - (start + arrive[k]))
+        plain_wall = time.perf_counter() - start
+        plain = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                 "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                 "pts_per_s": pts / plain_wall}
+        # served: submit at the arrival times
+        srv.reset_stats()
+        tickets = []
+        start = time.perf_counter()
+        for k, (wl, xs, c, f) in enumerate(data):
+            wait_until(start + arrive[k])
+            tickets.append(srv.submit(wl.types[0], xs, c, f, wl.eps))
+        statuses = [srv.wait(t)[0] for t in tickets]
+        served_wall = time.perf_counter() - start
+        s = srv.stats()
+        served = {"p50_ms": s.p50_ms, "p99_ms": s.p99_ms, "pts_per_s": pts / served_wall,
+                  "failed": int(sum(1 for x in statuses if x >= 2)),
+                  "plan_cache_hits": int(s.plan_cache_hits), "hbm_peak_bytes": int(s.hbm_peak)}
+        runs.append({"offered_load": load, "arrival_rate_per_s": rate, "plain": plain,
+                     "served": served,
+                     "p50_speedup": plain["p50_ms"] / max(served["p50_ms"], 1e-9),
+                     "p99_speedup": plain["p99_ms"] / max(served["p99_ms"], 1e-9),
+                     "throughput_ratio": served["pts_per_s"] / plain["pts_per_s"]})
+    srv.close()
+    return {"requests": nreq, "slots": nslots, "plain_serial_s": serial, "loads": runs}
 
 
 def batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt, reps=5):

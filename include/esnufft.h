@@ -208,6 +208,62 @@ int esn_3d2(int64_t M, const double* x, const double* y, const double* z, void* 
             int isign, double eps, int64_t N1, int64_t N2, int64_t N3,
             const void* f, int prec, const esn_opts* opts, void* stream);
 
+/* ---- serving: a request loop for many independent transforms -------------
+ * Not from the paper (its remark on repeated small problems, Sec. 2, is what
+ * plan reuse answers); this is the library's own continuous-batching front
+ * end.  Worker threads, each with its own HIP stream (default priority), take
+ * requests from one FIFO queue; a request starts as soon as a worker is free
+ * and its estimated device memory fits the budget, evicting idle cached plans
+ * (least recently used first) when needed.  Requests that can never fit fail
+ * with ESN_ERR_BUDGET.  Plans are cached by (type, dim, modes, isign, eps,
+ * prec); a cached plan remembers the points_id it last sorted, and a request
+ * naming the same nonzero points_id (the caller promises the same points)
+ * skips setpts.  Data pointers are device pointers that must stay valid until
+ * esn_server_wait returns for the ticket.  Kernels of concurrent requests
+ * overlap on the device; results do not depend on what else is running. */
+typedef struct esn_request {
+  int type;                /* 1 or 2 */
+  int dim;                 /* 1..3 */
+  int64_t nmodes[3];       /* entries beyond dim ignored */
+  int isign;               /* +1 / -1 */
+  double eps;
+  int prec;                /* ESN_SINGLE / ESN_DOUBLE: dtype of c and f */
+  int64_t M;
+  int coord_prec;          /* ESN_SINGLE / ESN_DOUBLE: dtype of x, y, z */
+  const void* x;
+  const void* y;
+  const void* z;
+  void* c;                 /* [M] strengths (type 1 input, type 2 output) */
+  void* f;                 /* [N3][N2][N1] modes (type 1 output, type 2 input) */
+  long long points_id;     /* 0, or an id shared by requests with identical points */
+} esn_request;
+
+typedef struct esn_serve_stats {
+  long long submitted, completed, failed, rejected, queued, running;
+  long long plan_cache_hits, plan_cache_misses, point_cache_hits, cached_plans;
+  long long hbm_in_use, hbm_peak;      /* bytes counted against the budget */
+  double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-done latency of completed requests */
+  double pts_per_s;                    /* completed NU points / (last done - first submit) */
+} esn_serve_stats;
+
+typedef struct esn_server_s* esn_server;
+
+/* Start a server with nslots workers (1..64) and an HBM budget in bytes on
+ * the current device.  opts (may be NULL) apply to every plan it makes. */
+int esn_server_create(const esn_opts* opts, int nslots, long long hbm_budget_bytes,
+                      esn_server* out);
+/* Queue a request (host struct, copied); *ticket identifies it.  Returns
+ * ESN_ERR_BAD_ARG for malformed requests, ESN_ERR_QUEUE after destroy began. */
+int esn_server_submit(esn_server s, const esn_request* r, long long* ticket);
+/* Block until the request is done; *status is its status, *latency_ms its
+ * submit-to-done time (either may be NULL).  A ticket can be waited once. */
+int esn_server_wait(esn_server s, long long ticket, int* status, double* latency_ms);
+/* Counters and latency percentiles since creation or the last reset. */
+int esn_server_stats(esn_server s, esn_serve_stats* out);
+int esn_server_reset_stats(esn_server s);
+/* Finish every queued request, then free all plans, streams and threads. */
+int esn_server_destroy(esn_server s);
+
 /* Text for a status code (static string). */
 const char* esn_strerror(int status);
 

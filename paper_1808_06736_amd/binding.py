@@ -58,6 +58,20 @@ class EsnStats(ctypes.Structure):
                 ("t_deconv_or_amplify", cd), ("t_execute", cd)]
 
 
+class EsnRequest(ctypes.Structure):
+    _fields_ = [("type", ci), ("dim", ci), ("nmodes", i64 * 3), ("isign", ci), ("eps", cd),
+                ("prec", ci), ("M", i64), ("coord_prec", ci), ("x", vp), ("y", vp), ("z", vp),
+                ("c", vp), ("f", vp), ("points_id", ctypes.c_longlong)]
+
+
+class EsnServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_longlong) for n in
+                ("submitted", "completed", "failed", "rejected", "queued", "running",
+                 "plan_cache_hits", "plan_cache_misses", "point_cache_hits", "cached_plans",
+                 "hbm_in_use", "hbm_peak")] + \
+               [(n, cd) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "pts_per_s")]
+
+
 class EsnError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         self.status = status
@@ -91,6 +105,12 @@ _SIGS = {
     "esn_gauss_legendre": ([ci, vp, vp], ci),
     "esn_correction_factors": ([ci, cd, ci, i64, i64, vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
+    "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
+    "esn_server_submit": ([vp, ctypes.POINTER(EsnRequest), ctypes.POINTER(ctypes.c_longlong)], ci),
+    "esn_server_wait": ([vp, ctypes.c_longlong, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
+    "esn_server_stats": ([vp, ctypes.POINTER(EsnServeStats)], ci),
+    "esn_server_reset_stats": ([vp], ci),
+    "esn_server_destroy": ([vp], ci),
 }
 
 
@@ -384,6 +404,106 @@ class Plan:
         if getattr(self, "handle", None):
             esn_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving -------------------------------------------------------------------
+def esn_server_create(opts, nslots, hbm_budget_bytes):
+    h = vp()
+    st = lib().esn_server_create(ctypes.byref(opts) if opts is not None else None, int(nslots),
+                                 int(hbm_budget_bytes), ctypes.byref(h))
+    return st, h
+
+
+def esn_server_submit(server, req):
+    t = ctypes.c_longlong()
+    st = lib().esn_server_submit(server, ctypes.byref(req), ctypes.byref(t))
+    return st, t.value
+
+
+def esn_server_wait(server, ticket):
+    st = ci()
+    lat = cd()
+    rc = lib().esn_server_wait(server, int(ticket), ctypes.byref(st), ctypes.byref(lat))
+    return rc, st.value, lat.value
+
+
+def esn_server_stats(server):
+    o = EsnServeStats()
+    check(lib().esn_server_stats(server, ctypes.byref(o)), "esn_server_stats")
+    return o
+
+
+def esn_server_reset_stats(server):
+    return lib().esn_server_reset_stats(server)
+
+
+def esn_server_destroy(server):
+    return lib().esn_server_destroy(server)
+
+
+class Server:
+    """Continuous-batching request loop over torch CUDA tensors.
+
+    ``submit`` takes the request's tensors (kept referenced until ``wait``) and
+    returns a ticket; ``wait`` blocks until that request is done and returns
+    (status, latency in ms).
+    """
+
+    def __init__(self, nslots=4, hbm_budget_bytes=64 << 30, **opts):
+        import torch
+        self.torch = torch
+        self.opts = make_opts(**opts)
+        st, self.handle = esn_server_create(self.opts, nslots, hbm_budget_bytes)
+        check(st, "esn_server_create")
+        self._keep = {}
+
+    def submit(self, type_, coords, c, f, eps, isign=None, points_id=0):
+        torch = self.torch
+        dim = len(coords)
+        N = tuple(reversed(f.shape[-dim:]))
+        r = EsnRequest()
+        r.type = int(type_)
+        r.dim = dim
+        for m in range(3):
+            r.nmodes[m] = int(N[m]) if m < dim else 1
+        r.isign = isign if isign is not None else (1 if type_ == 1 else -1)
+        r.eps = float(eps)
+        r.prec = ESN_SINGLE if f.dtype == torch.complex64 else ESN_DOUBLE
+        r.M = coords[0].numel()
+        r.coord_prec = ESN_SINGLE if coords[0].dtype == torch.float32 else ESN_DOUBLE
+        ptrs = [a.data_ptr() if r.M else None for a in coords] + [None] * (3 - dim)
+        r.x, r.y, r.z = ptrs[0], ptrs[1], ptrs[2]
+        r.c = c.data_ptr() if r.M else None
+        r.f = f.data_ptr()
+        r.points_id = int(points_id)
+        st, t = esn_server_submit(self.handle, r)
+        check(st, "esn_server_submit")
+        self._keep[t] = (coords, c, f)
+        return t
+
+    def wait(self, ticket):
+        rc, st, lat = esn_server_wait(self.handle, ticket)
+        check(rc, "esn_server_wait")
+        self._keep.pop(ticket, None)
+        return st, lat
+
+    def stats(self):
+        return esn_server_stats(self.handle)
+
+    def reset_stats(self):
+        esn_server_reset_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            esn_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

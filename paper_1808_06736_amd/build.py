@@ -28,7 +28,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
-SOURCES = ["params.cpp", "fft.cpp", "plan.cpp",
+SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "serve.cpp",
            "kernels_sort.hip", "kernels_deconv.hip", "kernels_spread.hip",
            "kernels_interp.hip", "kernels_mfma.hip"]
 

@@ -145,6 +145,15 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, int batch, int prec,
 int fft_exec(FFTPlan* p, void* data);
 void fft_destroy(FFTPlan* p);
 
+// Move a plan (and its rocFFT execution info) to another stream.  The caller
+// makes sure no work of the plan is pending on the old stream.
+int plan_set_stream(esn_plan p, hipStream_t s);
+// Device bytes a plan of this shape would hold with M points (an estimate used
+// for admission before the plan exists; rocFFT's work buffer is taken as one
+// fine grid).
+int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps, int prec,
+                            int64_t M);
+
 }  // namespace esn
 
 // The plan object behind esn_plan.

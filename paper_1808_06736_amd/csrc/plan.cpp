@@ -628,6 +628,40 @@ extern "C" int esn_get_stats(esn_plan p, esn_stats* o) {
   return ESN_OK;
 }
 
+namespace esn {
+
+int plan_set_stream(esn_plan p, hipStream_t s) {
+  if (!p) return ESN_ERR_BAD_ARG;
+  p->stream = s;
+  if (p->fft.info && rocfft_execution_info_set_stream(p->fft.info, (void*)s) != rocfft_status_success)
+    return ESN_ERR_FFT_PLAN;
+  if (p->fft_tail.info &&
+      rocfft_execution_info_set_stream(p->fft_tail.info, (void*)s) != rocfft_status_success)
+    return ESN_ERR_FFT_PLAN;
+  return ESN_OK;
+}
+
+int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps, int prec,
+                            int64_t M) {
+  esn_params par;
+  if (esn_choose_params(eps, prec, dim, nmodes, 2.0, &par) >= 2) return -1;
+  const int64_t cs = prec == ESN_DOUBLE ? 16 : 8;
+  int64_t grid = cs, cells = 1;
+  for (int m = 0; m < dim; m++) {
+    grid *= par.nf[m];
+    cells *= par.nf[m] + 64;      // bins may pad the grid
+  }
+  const int64_t rec = prec == ESN_DOUBLE ? 32 : 16;
+  (void)type;
+  return 2 * grid                 // fine grid + rocFFT work buffer
+         + 8 * (cells + 1)        // cell counts and starts
+         + M * (rec + 8)          // sorted records, keys and slots
+         + (int64_t)(M / 256 + 1024) * 12   // subproblem lists
+         + (1 << 20);             // factors, flags, small buffers
+}
+
+}  // namespace esn
+
 extern "C" int esn_destroy(esn_plan p) {
   if (!p) return ESN_OK;
   (void)hipSetDevice(p->device);

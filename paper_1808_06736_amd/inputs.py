@@ -76,6 +76,40 @@ def complex_normal(shape, seed: int, dtype=np.complex128) -> np.ndarray:
     return (re + 1j * im).astype(dtype)
 
 
+def device_points(M: int, d: int, seed: int, kind: str = "uniform", sigma: float = 0.3,
+                  dtype=None):
+    """d coordinate tensors on the GPU from torch's seeded CUDA generator (for
+    large benchmark inputs that no oracle reads): iid U[-pi, pi), or iid
+    N(0, sigma^2) wrapped into [-pi, pi)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    dtype = dtype or torch.float32
+    out = []
+    for _ in range(d):
+        if kind == "uniform":
+            a = (torch.rand(M, generator=g, device="cuda", dtype=torch.float64) * 2 - 1) * math.pi
+        else:
+            a = torch.randn(M, generator=g, device="cuda", dtype=torch.float64) * sigma
+            a = a - TWO_PI * torch.floor((a + math.pi) / TWO_PI)
+        a = a.to(dtype)
+        a[a >= math.pi] = -math.pi
+        out.append(a.contiguous())
+    return out
+
+
+def device_complex(shape, seed: int, dtype=None):
+    """Complex tensor on the GPU with re, im iid N(0, 1) (torch seeded generator)."""
+    import torch
+    dtype = dtype or torch.complex64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    real = torch.float32 if dtype == torch.complex64 else torch.float64
+    re = torch.randn(shape, generator=g, device="cuda", dtype=real)
+    im = torch.randn(shape, generator=g, device="cuda", dtype=real)
+    return torch.complex(re, im).contiguous()
+
+
 def mode_range(N: int) -> np.ndarray:
     """Integer mode indices of one dimension, in increasing order."""
     return np.arange(N, dtype=np.int64) - (N // 2)
