@@ -84,30 +84,39 @@ struct SortArgs {
   int b[3], nb[3], fbits[3];
   int pts_code;
   int chkbnds;
-  int32_t* key;             // [M] cell key of each point
-  int32_t* slot;            // [M] rank of the point within its cell
-  int32_t* count;           // [ncells + 1] points per cell
-  const int32_t* sstart;    // [ncells + 1] first sorted position of a cell
-  int64_t ncells;
-  unsigned char* pts;       // [M] sorted point records
+  uint32_t* key;            // [M] cell key of each point
+  uint32_t* idx;            // [M] original index of each point
+  unsigned char* pts;       // [M] point records (input order for launch_sort_keys)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
 };
-hipError_t launch_bin_count(const SortArgs& a, hipStream_t s);
-hipError_t launch_scatter(const SortArgs& a, hipStream_t s);
+// Cell key, original index and point record of every point, in input order.
+hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s);
+// Point records written unsorted (no binning).
 hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
+// Stable sort of (key, index) pairs on the low key_bits bits of the key.  The
+// pairs are in key[0], idx[0] on entry and in key[sel], idx[sel] on return
+// (sel in {0, 1}); tmp holds sort_tmp_bytes(M) bytes.
+size_t sort_tmp_bytes(int64_t M, int key_bits);
+hipError_t sort_pairs(uint32_t* key[2], uint32_t* idx[2], int* sel, int64_t M, int key_bits,
+                      void* tmp, size_t tmp_bytes, hipStream_t s);
+// Sorted records pts[i] = rec[perm[i]] (rec_bytes 16 or 32), and for every
+// bin b = key / cpb, bcount[b] += (end - start) of its run of sorted keys
+// (bcount zeroed by the caller, nbins + 1 entries).
+hipError_t launch_gather_records(const uint32_t* skey, const uint32_t* perm,
+                                 const unsigned char* rec, unsigned char* pts, int rec_bytes,
+                                 int64_t M, int cpb, int32_t* bcount, hipStream_t s);
 // Exclusive scan of n int32 values (in -> out, may not alias); tmp must hold
 // scan_tmp_elems(n) int32.
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n,
                               int32_t* tmp, hipStream_t s);
-// Per bin: nsub[b] = ceil(points / maxsub) from the cell starts; *nonempty
+// Per bin: nsub[b] = ceil(points / maxsub) from the bin starts; *nonempty
 // (device) is incremented per nonempty bin.
-hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub,
-                                int64_t nbins, int maxsub, int32_t* nonempty, hipStream_t s);
-hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t* nsub,
-                               const int32_t* subofs, int64_t nbins, int maxsub,
-                               int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
-                               hipStream_t s);
+hipError_t launch_subprob_count(const int32_t* bstart, int32_t* nsub, int64_t nbins, int maxsub,
+                                int32_t* nonempty, hipStream_t s);
+hipError_t launch_subprob_fill(const int32_t* bstart, const int32_t* nsub, const int32_t* subofs,
+                               int64_t nbins, int maxsub, int32_t* sub_bin, int32_t* sub_start,
+                               int32_t* sub_len, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // Spread / interp (kernels_spread.hip, kernels_interp.hip).
@@ -190,11 +199,14 @@ struct esn_plan_s {
   int64_t M = -1;                // -1: no points yet
   int64_t cap_M = 0;
   unsigned char* d_pts = nullptr;   // [M] sorted point records
-  int32_t* d_key = nullptr;
-  int32_t* d_slot = nullptr;
-  int64_t ncells = 0;            // bins * cells per bin
-  int32_t* d_count = nullptr;    // [ncells + 1]
-  int32_t* d_sstart = nullptr;   // [ncells + 1]
+  uint32_t* d_key[2] = {nullptr, nullptr};   // [M] cell keys (sort double buffer)
+  uint32_t* d_idx[2] = {nullptr, nullptr};   // [M] original indices (sort double buffer)
+  unsigned char* d_rec0 = nullptr;           // [M] point records in input order
+  void* d_sort_tmp = nullptr;
+  size_t sort_tmp = 0;
+  int key_bits = 0;              // bits of the largest cell key
+  int32_t* d_bcount = nullptr;   // [nbins + 1] points per bin
+  int32_t* d_bstart = nullptr;   // [nbins + 1] first sorted position of a bin
   int32_t* d_nsub = nullptr;
   int32_t* d_subofs = nullptr;
   int32_t* d_scan_tmp = nullptr;

@@ -3,33 +3,50 @@
 // of one bin, Sec. 4.2).
 //
 // Within a bin the points are sorted by column (x, y cell) and then by z cell.
-// For the points of one column every window lies in the (w+1) x (w+1)
-// footprint x in [x_c - floor(w/2), x_c - floor(w/2) + w] (same for y), so
-// spreading them, eq. (bl), is
+// Every point of a column has its window inside the 8 x 8 footprint of cells
+// x_c - floor(w/2) .. x_c - floor(w/2) + 7 (same for y), and every point of
+// one cell inside the 8 planes from z_c - floor(w/2).  Spreading the points of
+// a column, eq. (bl), is then a dense contraction over the points,
 //
-//     B[(x, y), z] = sum_p  kx_p(x) ky_p(y)  *  c_p kz_p(z),
+//     B[(z, x), (y, re/im)] = sum_p  kz_p(z) kx_p(x)  *  ky_p(y) c_p,
 //
-// a dense contraction over the points of a 64 x P matrix of separable x-y
-// weights with a P x (z planes) matrix of strength times z weight.  The wave
-// runs it with v_mfma_f32_16x16x4_f32: the 64 footprint rows are four 16-row
-// tiles, the 16 columns are 8 z planes x (re, im), each instruction takes 4
-// points.  The 8 planes form a ring (plane z -> slot z mod 8): once the wave
-// moves past cell z_c no later point of the column reaches plane
-// z_c - floor(w/2) - 1, which is then added into the wave's LDS tile of the
-// bin (bin + w cells per dim) and its slot reused.  The wave owns the tile, so
-// these adds are plain read-modify-writes; the tile goes to the fine grid once
-// at the end (global atomics on the touched cells only).
+// of a 64 x P matrix of z-x weights with a P x 16 matrix of y weight times
+// strength.  The wave runs it with v_mfma_f32_16x16x4_f32: the 64 rows are
+// four 16-row tiles (two z planes x 8 x cells each), each instruction takes 4
+// points.  The 8 planes form a ring (tile-relative plane r -> slot r mod 8):
+// once the wave moves on to a later z cell of the column, the planes below it
+// receive nothing more, so they are added into the wave's LDS tile of the bin
+// (bin + 7 cells per dim) and their slots reused; a plane lives in half the
+// lanes of one row tile, so this costs 4 read-modify-writes on those lanes.
+// The wave owns the tile, so these adds are plain read-modify-writes; the tile
+// goes to the fine grid once at the end (global atomics on the touched cells
+// only).
 //
 // Interpolation, eq. (interp), runs the same contraction the other way: for
 // the points of one cell, T[p, z] = sum_(x,y) kx_p(x) ky_p(y) B[(x, y), z] on
 // the matrix cores (16 points x 64 footprint cells x 8 planes (re, im)), then
-// c_p = sum_z kz_p(z) T[p, z] by lane shuffles, with the bin's grid tile
-// (bin + 7 cells per dim) copied into LDS first with coalesced reads.
+// c_p = sum_z kz_p(z) T[p, z] by row rotations across lanes, with the bin's
+// grid tile (bin + 7 cells per dim) copied into LDS first.
 #include "device_common.hpp"
 
 namespace esn {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ES kernel values of one point at its w window cells (as es_weights_f32),
+// using the hardware square root and base-2 exponential: bl = beta log2(e),
+// ker[k] = 2^(bl (sqrt(1 - z^2) - 1)).
+template <int W>
+__device__ __forceinline__ void es_weights_hw(int sh, float f, float bl, float* ker) {
+  const float off = (float)(sh - W / 2) - f;
+  const float s = 2.0f / (float)W;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    const float z = (off + (float)k) * s;
+    const float a = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+    ker[k] = __builtin_amdgcn_exp2f(fmaf(bl, __builtin_amdgcn_sqrtf(a), -bl));
+  }
+}
 
 // The w kernel values placed at slots sh .. sh + w - 1 of an 8-slot vector
 // (sh in {0, 1}), zeros elsewhere; built with selects so it stays in registers.
@@ -79,61 +96,86 @@ __device__ __forceinline__ int wrap2(int g, int n) {
   return g;
 }
 
+// Hides a register value from the optimizer (no instruction is emitted), so
+// that loads indexed by it, issued a loop step ahead, are not merged back into
+// the next step.
+__device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
 
-// Tile of tc complex cells, padded to a 16-byte boundary so that the staging
-// arrays after it are aligned for 16-byte LDS accesses.
-__host__ __device__ inline size_t tile_bytes16(size_t tc) { return (tc * sizeof(float2) + 15) & ~(size_t)15; }
+// Keeps the memory accesses before it ahead of the code after it (a compiler
+// barrier only: no instruction, no wait).
+__device__ __forceinline__ void keep_order() { asm volatile("" ::: "memory"); }
+
+// Sum of v over the 8 lanes of the same parity in each 16-lane row (row
+// rotations by 8, 4 and 2 lanes).
+__device__ __forceinline__ float row_sum_parity(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x124, 0xf, 0xf, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x122, 0xf, 0xf, false));
+  return v;
+}
+
+// Floats per z plane of a bin tile of T0 x T1 complex cells: 2 T0 T1 padded
+// to 8 mod 32, so that the 8 planes a wave touches at once start in distinct
+// LDS banks.
+__host__ __device__ inline int plane_floats(int T0, int T1) {
+  return ((2 * T0 * T1 + 23) / 32) * 32 + 8;
+}
+
+// LDS layout shared by both kernels: the bin tile (bin + 7 cells per dim,
+// planes of plane_floats), [64][8] x, y and z weights, a float2 per point, the
+// wrapped grid offsets of the tile's z planes (int64), then nint ints per point
+// and the wrapped grid offsets of the tile's x and y lines.
+static inline size_t mfma_lds_bytes(const int* b, int nint) {
+  const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
+  return T2 * plane_floats((int)T0, (int)T1) * sizeof(float) + 3 * 64 * 8 * sizeof(float) +
+         64 * sizeof(float2) + T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) +
+         (T0 + T1) * sizeof(int);
+}
 
 size_t mfma_spread_lds_bytes(int w, const int* b) {
-  const size_t tile = tile_bytes16((size_t)(b[0] + w) * (b[1] + w) * (b[2] + w));
-  return tile + 3 * 64 * 8 * sizeof(float) + 64 * sizeof(float2) + 2 * 64 * sizeof(int);
+  (void)w;   // 8-wide footprints for every w
+  return mfma_lds_bytes(b, 2);
 }
 
-size_t mfma_interp_lds_bytes(const int* b) {
-  const size_t tile = tile_bytes16((size_t)(b[0] + 7) * (b[1] + 7) * (b[2] + 7));
-  return tile + 3 * 64 * 8 * sizeof(float) + 3 * 64 * sizeof(int);
+size_t mfma_interp_lds_bytes(const int* b) { return mfma_lds_bytes(b, 3); }
+
+// Fill the wrapped grid offsets of the tile lines whose origin is (ox, oy, oz):
+// gx[i] = wrap(ox + i), gy[i] = n0 wrap(oy + i), gz[i] = n0 n1 wrap(oz + i).
+__device__ __forceinline__ void tile_offsets(int lane, int T0, int T1, int T2, int ox, int oy,
+                                             int oz, int n0, int n1, int n2, int* gx, int* gy,
+                                             int64_t* gz) {
+  for (int i = lane; i < T0; i += 64) gx[i] = wrap2(ox + i, n0);
+  for (int i = lane; i < T1; i += 64) gy[i] = n0 * wrap2(oy + i, n1);
+  for (int i = lane; i < T2; i += 64) gz[i] = (int64_t)n0 * n1 * wrap2(oz + i, n2);
 }
 
-// Kernel values of one point for the matrix-core kernels: x and y weights by
-// footprint slot (8 slots; y de-interleaved as {0, 2, 4, 6, 1, 3, 5, 7} when
-// ydeint), z weights either by ring slot (ring) or relative to the cell.
-template <int W>
-__device__ __forceinline__ void point_weights(uint32_t qx, uint32_t qy, uint32_t qz,
-                                              const GeomArgs& g, float beta, bool ring,
-                                              bool ydeint, float* vx, float* vy, float* vz,
-                                              int* cell) {
-  constexpr int H = W / 2;
-  const uint32_t q[3] = {qx, qy, qz};
-  float k[3][W];
-  int sh[3];
-#pragma unroll
-  for (int m = 0; m < 3; m++) {
-    const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
-    // window shift decided on the exact fraction bits (see decode_coord)
-    sh[m] = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
-    cell[m] = (int)(q[m] >> g.fbits[m]);
-    es_weights_f32<W>(sh[m], ldexpf((float)fr, -g.fbits[m]), beta, k[m]);
+// Walks the cells lane, lane + 64, ... of a T0 x T1 x T2 tile (x fastest),
+// keeping (ix, iy, iz) without divisions in the loop.
+struct TileWalk {
+  int ix, iy, iz, dx, dq, T0, T1;
+  // float offset of the cell in a tile with planes of ps floats
+  __device__ __forceinline__ int ofs(int ps) const { return iz * ps + 2 * (iy * T0 + ix); }
+  __device__ __forceinline__ TileWalk(int lane, int T0_, int T1_) : T0(T0_), T1(T1_) {
+    ix = lane % T0;
+    const int r = lane / T0;
+    iy = r % T1;
+    iz = r / T1;
+    dx = 64 % T0;
+    dq = 64 / T0;
   }
-  slots8<W>(k[0], sh[0], vx);
-  float t[8];
-  slots8<W>(k[1], sh[1], t);
-  if (ydeint) {
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      vy[i] = t[2 * i];
-      vy[4 + i] = t[2 * i + 1];
+  __device__ __forceinline__ void next() {
+    ix += dx;
+    iy += dq;
+    if (ix >= T0) {
+      ix -= T0;
+      iy++;
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; i++) vy[i] = t[i];
+    while (iy >= T1) {
+      iy -= T1;
+      iz++;
+    }
   }
-  if (ring) {
-    slots8<W>(k[2], 0, vz);
-    rotate8(vz, (cell[2] - H + sh[2]) & 7);
-  } else {
-    slots8<W>(k[2], sh[2], vz);
-  }
-}
+};
 
 template <int W>
 __global__ void __launch_bounds__(64)
@@ -142,15 +184,19 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   constexpr int H = W / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b0 = g.b[0], b1 = g.b[1], b2 = g.b[2];
-  const int T0 = b0 + W, T1 = b1 + W, T2 = b2 + W;
+  const int T0 = b0 + 7, T1 = b1 + 7, T2 = b2 + 7;   // 8-wide footprints for every w
   const int tc = T0 * T1 * T2;
-  float* otf = reinterpret_cast<float*>(smem_raw);               // [T2][T1][T0][2]
-  float* skx = reinterpret_cast<float*>(smem_raw + tile_bytes16(tc));   // [64][8] x slots
-  float* sky = skx + 64 * 8;                                      // [64][8] y slots, de-interleaved
-  float* skz = sky + 64 * 8;                                      // [64][8] z ring slots
-  float2* sc = reinterpret_cast<float2*>(skz + 64 * 8);           // [64]
-  int* scol = reinterpret_cast<int*>(sc + 64);                    // [64] column in the bin
-  int* szc = scol + 64;                                           // [64] z cell
+  const int ps = plane_floats(T0, T1);               // floats per tile plane
+  float* otf = reinterpret_cast<float*>(smem_raw);               // [T2][ps]: [T1][T0][2]
+  float* skx = otf + T2 * ps;                                     // [64][8] x slots
+  float* sky = skx + 64 * 8;                                      // [64][8] y slots
+  float* skz = sky + 64 * 8;                                      // [64][8] z ring, pairs split
+  float2* sc = reinterpret_cast<float2*>(skz + 64 * 8);           // [64] strengths
+  int64_t* gz = reinterpret_cast<int64_t*>(sc + 64);              // [T2]
+  int* scol = reinterpret_cast<int*>(gz + T2);                    // [64] column in the bin
+  int* szr = scol + 64;                                           // [64] z cell in the bin
+  int* gx = szr + 64;                                             // [T0]
+  int* gy = gx + T0;                                              // [T1]
 
   const int sidx = blockIdx.x;
   const int bin = g.sub_bin[sidx];
@@ -159,70 +205,93 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
   const int lane = threadIdx.x;
-  const float beta = (float)g.beta;
+  const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
+  const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
-  for (int i = lane; i < tc * 2; i += 64) otf[i] = 0.f;
+  {
+    float4* o4 = reinterpret_cast<float4*>(otf);
+    const int n4 = T2 * ps / 4;
+    for (int i = lane; i < n4; i += 64) o4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  tile_offsets(lane, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
+
+  // lane roles in the accumulators: row tile t holds ring slots 2t + hz, x
+  // cells x0 .. x0 + 3 (one per accumulator element), y cell yl, re/im reim
+  const int yl = (lane & 15) >> 1;
+  const int reim = lane & 1;
+  const int hz = lane >> 5;
+  const int x0 = 4 * ((lane >> 4) & 1);
+  const int kzo = 4 * ((lane >> 3) & 1);   // this lane's 4 ring weights (A operand rows)
   v4f acc[4];
 #pragma unroll
   for (int t = 0; t < 4; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int myslot = (lane & 15) >> 1;   // ring slot of this lane's accumulator column
-  const int reim = lane & 1;
-  int cur = -1;                          // current column (lx + b0 ly), -1: none
-  int clx = 0, cly = 0;
-  int pend = bz0 - H;                    // the ring holds planes pend .. pend + 7
+  int cur = -1;        // current column (lx + b0 ly), -1: none
+  int colbase = 0;     // this lane's float offset in a tile plane for the current column
+  int pend = 0;        // the ring holds tile planes pend .. pend + 7
 
-  // add plane P of the current column's ring into the bin tile
-  auto flush = [&](int P) {
-    const int rel = P - (bz0 - H);
-    const bool mine = myslot == (P & 7);
-    if (mine && rel >= 0 && rel < T2) {
+  // add the ring slots in mask fm (wave-uniform) into the bin tile and clear them
+  auto flush = [&](unsigned fm) {
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
+    for (int t = 0; t < 4; t++) {
+      if (fm & (3u << (2 * t))) {
+        const int s = 2 * t + hz;
+        if ((fm >> s) & 1u) {
+          float* d = otf + (pend + ((s - pend) & 7)) * ps + colbase;
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int row = 16 * t + 4 * (lane >> 4) + i;   // footprint (x, y) = (row & 7, row >> 3)
-          const int x = clx + (row & 7), y = cly + (row >> 3);
-          if (x < T0 && y < T1) {
-            float* d = otf + ((rel * T1 + y) * T0 + x) * 2 + reim;
-            *d += acc[t][i];
-          }
+          for (int i = 0; i < 4; i++) d[2 * i] += acc[t][i];
+          acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
         }
       }
-    }
-    if (mine) {
-#pragma unroll
-      for (int t = 0; t < 4; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     }
   };
 
   // point records flow through registers one batch ahead of the matrix work:
   // while batch b runs on the matrix cores, the records of batch b+2 and the
   // strengths of batch b+1 (gathered through the permutation) are in flight
+  // (the loads are unconditional, at indices clamped into the subproblem, so
+  // that the waits for them can be placed where the values are used)
   const uint4* rec = reinterpret_cast<const uint4*>(g.pts);
-  uint4 r0 = make_uint4(0, 0, 0, 0), r1 = make_uint4(0, 0, 0, 0);
-  float2 cc0 = make_float2(0.f, 0.f);
-  if (p0 + lane < p1) {
-    r0 = rec[p0 + lane];
-    cc0 = c[(int)r0.w];
-  }
-  if (p0 + 64 + lane < p1) r1 = rec[p0 + 64 + lane];
+  const int plast = p1 - 1;
+  uint4 r0 = rec[min(p0 + lane, plast)];
+  uint4 r1 = rec[min(p0 + 64 + lane, plast)];
+  float2 cc0 = c[(int)r0.w];
   for (int base = p0; base < p1; base += 64) {
     const int nbatch = min(64, p1 - base);
-    float2 cc1 = make_float2(0.f, 0.f);
-    uint4 r2 = make_uint4(0, 0, 0, 0);
-    if (base + 64 + lane < p1) cc1 = c[(int)r1.w];
-    if (base + 128 + lane < p1) r2 = rec[base + 128 + lane];
+    const uint4 r2 = rec[min(base + 128 + lane, plast)];
+    const float2 cc1 = c[(int)r1.w];
     __syncthreads();
-    if (lane < nbatch) {
-      float vx[8], vy[8], vz[8];
-      int cell[3];
-      point_weights<W>(r0.x, r0.y, r0.z, g, beta, true, true, vx, vy, vz, cell);
-      store8(skx + lane * 8, vx);
-      store8(sky + lane * 8, vy);
+    int mycol, myzr;   // this lane's point: column in the bin, z cell in the bin
+    {
+      const uint32_t q[3] = {r0.x, r0.y, r0.z};
+      float k[3][W];
+      int sh[3], cell[3];
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
+        // window shift decided on the exact fraction bits (see decode_coord)
+        sh[m] = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
+        cell[m] = (int)(q[m] >> g.fbits[m]);
+        es_weights_hw<W>(sh[m], ldexpf((float)fr, -g.fbits[m]), bl, k[m]);
+      }
+      const int zr = cell[2] - bz0;
+      float v[8], vz[8];
+      slots8<W>(k[0], sh[0], v);
+      store8(skx + lane * 8, v);
+      slots8<W>(k[1], sh[1], v);
+      store8(sky + lane * 8, v);
+      slots8<W>(k[2], sh[2], v);   // planes zr .. zr + 7 of the tile
+      rotate8(v, zr & 7);          // -> ring slots
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        vz[i] = v[2 * i];
+        vz[4 + i] = v[2 * i + 1];
+      }
       store8(skz + lane * 8, vz);
       sc[lane] = cc0;
-      scol[lane] = (cell[0] - bx0) + b0 * (cell[1] - by0);
-      szc[lane] = cell[2];
+      mycol = (cell[0] - bx0) + b0 * (cell[1] - by0);
+      myzr = zr;
+      scol[lane] = mycol;
+      szr[lane] = myzr;
     }
     r0 = r1;
     r1 = r2;
@@ -230,61 +299,76 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
     __syncthreads();
     // runs of points with the same column and z cell
     const bool starts = lane < nbatch &&
-                        (lane == 0 || szc[lane] != szc[lane - 1] || scol[lane] != scol[lane - 1]);
+                        (lane == 0 || szr[lane] != szr[lane - 1] || scol[lane] != scol[lane - 1]);
     uint64_t runs = __ballot(starts);
     while (runs) {
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-      const int col = scol[q0];
-      const int zc = szc[q0];
+      const int col = __builtin_amdgcn_readlane(mycol, q0);
+      const int zr = __builtin_amdgcn_readlane(myzr, q0);
       if (col != cur) {
-        if (cur >= 0)
-          for (int f = 0; f < 8; f++) flush(pend + f);
+        if (cur >= 0) flush(0xffu);
         cur = col;
-        clx = col % b0;
-        cly = col / b0;
-        pend = bz0 - H;
+        const int clx = col % b0, cly = col / b0;
+        colbase = ((cly + yl) * T0 + clx + x0) * 2 + reim;
+        pend = zr;
+      } else if (zr > pend) {
+        // planes pend .. zr - 1 receive nothing more
+        const int nfl = zr - pend;
+        unsigned fm = 0xffu;
+        if (nfl < 8) {
+          const unsigned m = ((1u << nfl) - 1u) << (pend & 7);
+          fm = (m | (m >> 8)) & 0xffu;
+        }
+        flush(fm);
+        pend = zr;
       }
-      int nfl = zc - H - pend;           // planes below zc - H receive nothing more
-      if (nfl > 0) {
-        if (nfl > 8) nfl = 8;
-        for (int f = 0; f < nfl; f++) flush(pend + f);
-        pend = zc - H;
+      // the operands of each 4-point step are read from LDS one step ahead
+      // (at an index clamped into the run), so the reads overlap the matrix work
+      float ax_n, ky_n;
+      float4 kz_n;
+      float2 cv_n;
+      {
+        const int qs = min(q0 + (lane >> 4), q1 - 1);
+        ax_n = skx[qs * 8 + (lane & 7)];
+        kz_n = *reinterpret_cast<const float4*>(skz + qs * 8 + kzo);
+        cv_n = sc[qs];
+        ky_n = sky[qs * 8 + yl];
       }
       for (int q = q0; q < q1; q += 4) {
-        const int qq = q + (lane >> 4);
-        const float valid = qq < q1 ? 1.f : 0.f;
-        const int qs = qq < q1 ? qq : q0;
-        const float ax = skx[qs * 8 + (lane & 7)];
-        const float4 ky4 = *reinterpret_cast<const float4*>(sky + qs * 8 + ((lane >> 3) & 1) * 4);
-        const float2 cv = sc[qs];
-        const float bv = (reim ? cv.y : cv.x) * (skz[qs * 8 + myslot] * valid);
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * ky4.x, bv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * ky4.y, bv, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * ky4.z, bv, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * ky4.w, bv, acc[3], 0, 0, 0);
+        const float ax = ax_n, ky = ky_n;
+        const float4 kz4 = kz_n;
+        const float2 cv = cv_n;
+        {
+          int qs = min(q + 4 + (lane >> 4), q1 - 1);
+          opaque(qs);
+          ax_n = skx[qs * 8 + (lane & 7)];
+          kz_n = *reinterpret_cast<const float4*>(skz + qs * 8 + kzo);
+          cv_n = sc[qs];
+          ky_n = sky[qs * 8 + yl];
+          keep_order();
+        }
+        const bool ok = q + (lane >> 4) < q1;
+        const float bv = ok ? (reim ? cv.y : cv.x) * ky : 0.f;
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.x, bv, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.y, bv, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.z, bv, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.w, bv, acc[3], 0, 0, 0);
       }
     }
   }
-  if (cur >= 0)
-    for (int f = 0; f < 8; f++) flush(pend + f);
+  if (cur >= 0) flush(0xffu);
   __syncthreads();
 
   // add the bin tile to the periodic fine grid (touched cells only)
-  const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
-  const int ox = bx0 - H, oy = by0 - H, oz = bz0 - H;
-  for (int i = lane; i < tc; i += 64) {
-    const float vr = otf[2 * i], vi = otf[2 * i + 1];
-    if (vr != 0.f || vi != 0.f) {
-      const int ix = i % T0;
-      const int r = i / T0;
-      const int gx = wrap2(ox + ix, n0);
-      const int gy = wrap2(oy + r % T1, n1);
-      const int gz = wrap2(oz + r / T1, n2);
-      float* dst = grid + 2 * ((int64_t)gx + (int64_t)n0 * ((int64_t)gy + (int64_t)n1 * gz));
-      atomicAdd(dst, vr);
-      atomicAdd(dst + 1, vi);
+  TileWalk tw(lane, T0, T1);
+  for (int i = lane; i < tc; i += 64, tw.next()) {
+    const float2 v = *reinterpret_cast<const float2*>(otf + tw.ofs(ps));
+    if (v.x != 0.f || v.y != 0.f) {
+      float* dst = grid + 2 * (gz[tw.iz] + gy[tw.iy] + gx[tw.ix]);
+      atomicAdd(dst, v.x);
+      atomicAdd(dst + 1, v.y);
     }
   }
 }
@@ -298,14 +382,18 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int b0 = g.b[0], b1 = g.b[1], b2 = g.b[2];
   const int T0 = b0 + 7, T1 = b1 + 7, T2 = b2 + 7;   // 8-wide footprints for every w
   const int tc = T0 * T1 * T2;
-  float2* gt = reinterpret_cast<float2*>(smem_raw);               // [T2][T1][T0]
-  const float* gtf = reinterpret_cast<const float*>(gt);
-  float* skx = reinterpret_cast<float*>(smem_raw + tile_bytes16(tc));   // [64][8] x slots
+  const int ps = plane_floats(T0, T1);               // floats per tile plane
+  float* gtf = reinterpret_cast<float*>(smem_raw);                 // [T2][ps]: [T1][T0][2]
+  float* skx = gtf + T2 * ps;                                      // [64][8] x slots
   float* sky = skx + 64 * 8;                                       // [64][8] y slots
   float* skz = sky + 64 * 8;                                       // [64][8] z rel. to the cell
-  int* scol = reinterpret_cast<int*>(skz + 64 * 8);                // [64]
-  int* szc = scol + 64;                                            // [64]
-  int* sperm = szc + 64;                                           // [64]
+  float2* sout = reinterpret_cast<float2*>(skz + 64 * 8);          // [64] results
+  int64_t* gz = reinterpret_cast<int64_t*>(sout + 64);             // [T2]
+  int* scol = reinterpret_cast<int*>(gz + T2);                     // [64]
+  int* szr = scol + 64;                                            // [64]
+  int* sperm = szr + 64;                                           // [64]
+  int* gx = sperm + 64;                                            // [T0]
+  int* gy = gx + T0;                                               // [T1]
 
   const int sidx = blockIdx.x;
   const int bin = g.sub_bin[sidx];
@@ -314,89 +402,129 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
   const int lane = threadIdx.x;
-  const float beta = (float)g.beta;
+  const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
-  const int ox = bx0 - H, oy = by0 - H, oz = bz0 - H;
 
+  // (record loads are unconditional, at indices clamped into the subproblem,
+  // so that the waits for them can be placed where the values are used)
   const uint4* rec = reinterpret_cast<const uint4*>(g.pts);
-  uint4 r0 = make_uint4(0, 0, 0, 0);
-  if (p0 + lane < p1) r0 = rec[p0 + lane];
-  for (int i = lane; i < tc; i += 64) {
-    const int ix = i % T0;
-    const int r = i / T0;
-    const int gx = wrap2(ox + ix, n0);
-    const int gy = wrap2(oy + r % T1, n1);
-    const int gz = wrap2(oz + r / T1, n2);
-    gt[i] = grid[(int64_t)gx + (int64_t)n0 * ((int64_t)gy + (int64_t)n1 * gz)];
+  const int plast = p1 - 1;
+  uint4 r0 = rec[min(p0 + lane, plast)];
+  tile_offsets(lane, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
+  __syncthreads();
+  {
+    // the bin's grid tile, 8 cells per lane in flight at a time
+    constexpr int U = 8;
+    TileWalk tw(lane, T0, T1);
+    for (int i0 = 0; i0 < tc; i0 += 64 * U) {
+      float2 v[U];
+      int o[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        // past the tile's last cell the walk runs on in z; the load then
+        // stays on the last plane and its value is not stored
+        o[u] = tw.ofs(ps);
+        v[u] = grid[gz[min(tw.iz, T2 - 1)] + gy[tw.iy] + gx[tw.ix]];
+        tw.next();
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++)
+        if (i0 + 64 * u + lane < tc) *reinterpret_cast<float2*>(gtf + o[u]) = v[u];
+    }
   }
 
   const int n = lane & 15;         // MFMA column: plane n >> 1, (re, im) = n & 1
   const int kq = lane >> 4;        // MFMA k lane group
   for (int base = p0; base < p1; base += 64) {
     const int nbatch = min(64, p1 - base);
-    uint4 r1 = make_uint4(0, 0, 0, 0);
-    if (base + 64 + lane < p1) r1 = rec[base + 64 + lane];
+    const uint4 r1 = rec[min(base + 64 + lane, plast)];
     __syncthreads();
-    if (lane < nbatch) {
-      float vx[8], vy[8], vz[8];
+    int mycol, myzr;   // this lane's point: column in the bin, z cell in the bin
+    {
+      const uint32_t q[3] = {r0.x, r0.y, r0.z};
+      float k[W], v[8];
       int cell[3];
-      point_weights<W>(r0.x, r0.y, r0.z, g, beta, false, false, vx, vy, vz, cell);
-      store8(skx + lane * 8, vx);
-      store8(sky + lane * 8, vy);
-      store8(skz + lane * 8, vz);
-      scol[lane] = (cell[0] - bx0) + b0 * (cell[1] - by0);
-      szc[lane] = cell[2];
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
+        // window shift decided on the exact fraction bits (see decode_coord)
+        const int sh = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
+        cell[m] = (int)(q[m] >> g.fbits[m]);
+        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[m]), bl, k);
+        slots8<W>(k, sh, v);
+        store8((m == 0 ? skx : m == 1 ? sky : skz) + lane * 8, v);
+      }
+      mycol = (cell[0] - bx0) + b0 * (cell[1] - by0);
+      myzr = cell[2] - bz0;
+      scol[lane] = mycol;
+      szr[lane] = myzr;
       sperm[lane] = (int)r0.w;
     }
     r0 = r1;
     __syncthreads();
     const bool starts = lane < nbatch &&
-                        (lane == 0 || szc[lane] != szc[lane - 1] || scol[lane] != scol[lane - 1]);
+                        (lane == 0 || szr[lane] != szr[lane - 1] || scol[lane] != scol[lane - 1]);
     uint64_t runs = __ballot(starts);
     while (runs) {
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-      const int col = scol[q0];
+      const int col = __builtin_amdgcn_readlane(mycol, q0);
       const int lx = col % b0, ly = col / b0;
-      const int zrel = szc[q0] - bz0;      // first window plane of the cell, in the tile
+      const int zrel = __builtin_amdgcn_readlane(myzr, q0);   // first window plane of the cell
       // B operand of the run: footprint cell (x, y) = (4 (s & 1) + kq, s >> 1), plane n >> 1
       float bop[16];
 #pragma unroll
       for (int s = 0; s < 16; s++) {
         const int x = lx + 4 * (s & 1) + kq, y = ly + (s >> 1);
-        bop[s] = gtf[(((zrel + (n >> 1)) * T1 + y) * T0 + x) * 2 + (n & 1)];
+        bop[s] = gtf[(zrel + (n >> 1)) * ps + 2 * (y * T0 + x) + (n & 1)];
+      }
+      // the x, y weights of each 16-point step are read from LDS one step
+      // ahead (at an index clamped into the run)
+      float kxa_n, kxb_n;
+      float4 kya_n, kyb_n;
+      {
+        const int qs = min(q0 + n, q1 - 1);
+        kxa_n = skx[qs * 8 + kq];
+        kxb_n = skx[qs * 8 + 4 + kq];
+        kya_n = *reinterpret_cast<const float4*>(sky + qs * 8);
+        kyb_n = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
       }
       for (int q = q0; q < q1; q += 16) {
-        const int qq = q + n;                   // this lane's point (MFMA row)
-        const float valid = qq < q1 ? 1.f : 0.f;
-        const int qs = qq < q1 ? qq : q0;
-        const float kxa = skx[qs * 8 + kq] * valid;
-        const float kxb = skx[qs * 8 + 4 + kq] * valid;
-        const float4 kya = *reinterpret_cast<const float4*>(sky + qs * 8);
-        const float4 kyb = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
-        const float ky[8] = {kya.x, kya.y, kya.z, kya.w, kyb.x, kyb.y, kyb.z, kyb.w};
-        v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+        const float valid = q + n < q1 ? 1.f : 0.f;   // this lane's point (MFMA row)
+        const float kxa = kxa_n * valid, kxb = kxb_n * valid;
+        const float ky[8] = {kya_n.x, kya_n.y, kya_n.z, kya_n.w, kyb_n.x, kyb_n.y, kyb_n.z, kyb_n.w};
+        // z weights of the 4 result rows of this lane
+        float kz[4];
 #pragma unroll
-        for (int s = 0; s < 16; s++) {
-          const float a = ((s & 1) ? kxb : kxa) * ky[s >> 1];
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[s], acc, 0, 0, 0);
+        for (int i = 0; i < 4; i++) kz[i] = skz[min(q + 4 * kq + i, q1 - 1) * 8 + (n >> 1)];
+        {
+          int qs = min(q + 16 + n, q1 - 1);
+          opaque(qs);
+          kxa_n = skx[qs * 8 + kq];
+          kxb_n = skx[qs * 8 + 4 + kq];
+          kya_n = *reinterpret_cast<const float4*>(sky + qs * 8);
+          kyb_n = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
+          keep_order();
+        }
+        // two independent accumulation chains (x half 0 and x half 1)
+        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 16; s += 2) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(kxa * ky[s >> 1], bop[s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(kxb * ky[s >> 1], bop[s + 1], acc1, 0, 0, 0);
         }
         // acc[i] = T[point q + 4 kq + i][column n]: weight by kz and sum the columns
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int pt = q + 4 * kq + i;
-          const bool pv = pt < q1;
-          const int ps = pv ? pt : q0;         // keeps the LDS index in range
-          float v = pv ? acc[i] * skz[ps * 8 + (n >> 1)] : 0.f;
-          v += __shfl_xor(v, 2);
-          v += __shfl_xor(v, 4);
-          v += __shfl_xor(v, 8);
-          const float vim = __shfl_down(v, 1);
-          if (pv && n == 0) c[sperm[ps]] = make_float2(v, vim);
+          const float v = row_sum_parity((acc0[i] + acc1[i]) * kz[i]);
+          if (pt < q1 && n < 2) reinterpret_cast<float*>(sout)[2 * pt + n] = v;
         }
       }
     }
+    __syncthreads();
+    if (lane < nbatch) c[sperm[lane]] = sout[lane];
   }
 }
 

@@ -1,15 +1,20 @@
-// Bin sort of the nonuniform points (Sec. 4.1, a histogram sort without any
-// ordering inside a cell) and the work lists for spreading (Sec. 4.2).
+// Bin sort of the nonuniform points (Sec. 4.1) and the work lists for
+// spreading (Sec. 4.2).
 //
-//   bin_count : fold each coordinate into [0, 2pi), rescale to fine-grid units
-//               t = x n / 2pi (FP64), take the cell floor(t) and count the
-//               point into it; the count before the increment is the point's
-//               slot within the cell.  Cells are numbered bin-major, so every
-//               bin (and, in 3D, every column of a bin) is a run of keys.
-//   scan      : exclusive prefix sums of the counts = first position of a cell.
-//   scatter   : place point j at start[cell] + slot, storing its permutation
-//               entry and its rescaled coordinate.
+//   sort_keys : fold each coordinate into [0, 2pi), rescale to fine-grid units
+//               t = x n / 2pi (FP64), take the cell floor(t); write the cell
+//               key, the point's index and its record in input order.  Cells
+//               are numbered bin-major, so every bin (and, in 3D, every
+//               column of a bin) is a run of keys.
+//   sort      : stable LSD radix sort of the (key, index) pairs (rocPRIM), so
+//               points of one cell keep their input order.
+//   gather    : sorted records pts[i] = rec[perm[i]]; the run of each bin in
+//               the sorted keys gives its point count.
+//   scan      : exclusive prefix sums of the bin counts = first position of a bin.
 //   subprob   : split each bin's points into runs of at most maxsub.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "device_common.hpp"
 
 namespace esn {
@@ -91,7 +96,7 @@ __device__ __forceinline__ void write_record(const SortArgs& a, int64_t pos, con
 }
 
 template <typename CTy>
-__global__ void bin_count_kernel(const SortArgs a) {
+__global__ void sort_keys_kernel(const SortArgs a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.M) return;
   int flag = 0;
@@ -99,21 +104,25 @@ __global__ void bin_count_kernel(const SortArgs a) {
   double t[3];
   const int key = point_key<CTy>(a, j, &flag, q, t);
   if (flag) atomicOr(a.flags, flag);
-  a.key[j] = key;
-  a.slot[j] = atomicAdd(&a.count[key], 1);
+  a.key[j] = (uint32_t)key;
+  a.idx[j] = (uint32_t)j;
+  write_record(a, j, q, t, j);
 }
 
-template <typename CTy>
-__global__ void scatter_kernel(const SortArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.M) return;
-  int flag = 0;
-  uint32_t q[3];
-  double t[3];
-  point_key<CTy>(a, j, &flag, q, t);
-  const int key = a.key[j];
-  const int64_t pos = (int64_t)a.sstart[key] + a.slot[j];
-  write_record(a, pos, q, t, j);
+__global__ void gather_records_kernel(const uint32_t* __restrict__ skey,
+                                      const uint32_t* __restrict__ perm,
+                                      const uint4* __restrict__ rec, uint4* __restrict__ pts,
+                                      int nvec, int64_t M, uint32_t cpb,
+                                      int32_t* __restrict__ bcount) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int64_t src = (int64_t)perm[i] * nvec;
+  for (int v = 0; v < nvec; v++) pts[i * nvec + v] = rec[src + v];
+  // bin b occupies sorted positions [start, end): add end at its last
+  // position and subtract start at its first, so bcount[b] = end - start
+  const uint32_t b = skey[i] / cpb;
+  if (i == 0 || skey[i - 1] / cpb != b) atomicSub(&bcount[b], (int32_t)i);
+  if (i == M - 1 || skey[i + 1] / cpb != b) atomicAdd(&bcount[b], (int32_t)(i + 1));
 }
 
 template <typename CTy>
@@ -130,21 +139,43 @@ __global__ void encode_unsorted_kernel(const SortArgs a) {
 
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t launch_bin_count(const SortArgs& a, hipStream_t s) {
+hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
   if (a.coord_prec == ESN_SINGLE)
-    hipLaunchKernelGGL(bin_count_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sort_keys_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(bin_count_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sort_keys_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const SortArgs& a, hipStream_t s) {
-  if (a.M <= 0) return hipSuccess;
-  if (a.coord_prec == ESN_SINGLE)
-    hipLaunchKernelGGL(scatter_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(scatter_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+size_t sort_tmp_bytes(int64_t M, int key_bits) {
+  size_t bytes = 0;
+  rocprim::double_buffer<uint32_t> k(nullptr, nullptr), v(nullptr, nullptr);
+  if (rocprim::radix_sort_pairs(nullptr, bytes, k, v, (unsigned)M, 0u, (unsigned)key_bits) !=
+      hipSuccess)
+    return 0;
+  return bytes;
+}
+
+hipError_t sort_pairs(uint32_t* key[2], uint32_t* idx[2], int* sel, int64_t M, int key_bits,
+                      void* tmp, size_t tmp_bytes, hipStream_t s) {
+  *sel = 0;
+  if (M <= 1 || key_bits <= 0) return hipSuccess;
+  rocprim::double_buffer<uint32_t> k(key[0], key[1]), v(idx[0], idx[1]);
+  size_t bytes = tmp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(tmp, bytes, k, v, (unsigned)M, 0u, (unsigned)key_bits, s);
+  if (e != hipSuccess) return e;
+  *sel = k.current() == key[0] ? 0 : 1;
+  return hipSuccess;
+}
+
+hipError_t launch_gather_records(const uint32_t* skey, const uint32_t* perm,
+                                 const unsigned char* rec, unsigned char* pts, int rec_bytes,
+                                 int64_t M, int cpb, int32_t* bcount, hipStream_t s) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_records_kernel, dim3(nblocks(M, 256)), dim3(256), 0, s, skey, perm,
+                     reinterpret_cast<const uint4*>(rec), reinterpret_cast<uint4*>(pts),
+                     rec_bytes / 16, M, (uint32_t)cpb, bcount);
   return hipGetLastError();
 }
 
@@ -240,17 +271,17 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_
 }
 
 // ---- subproblems ----
-__global__ void subprob_count_kernel(const int32_t* __restrict__ sstart, int64_t cpb,
+__global__ void subprob_count_kernel(const int32_t* __restrict__ bstart,
                                      int32_t* __restrict__ nsub, int64_t nbins, int maxsub,
                                      int32_t* nonempty) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
-  const int cnt = sstart[(b + 1) * cpb] - sstart[b * cpb];
+  const int cnt = bstart[b + 1] - bstart[b];
   nsub[b] = (cnt + maxsub - 1) / maxsub;
   if (cnt > 0) atomicAdd(nonempty, 1);
 }
 
-__global__ void subprob_fill_kernel(const int32_t* __restrict__ sstart, int64_t cpb,
+__global__ void subprob_fill_kernel(const int32_t* __restrict__ bstart,
                                     const int32_t* __restrict__ nsub,
                                     const int32_t* __restrict__ subofs, int64_t nbins,
                                     int maxsub, int32_t* __restrict__ sub_bin,
@@ -260,8 +291,8 @@ __global__ void subprob_fill_kernel(const int32_t* __restrict__ sstart, int64_t 
   if (b >= nbins) return;
   const int ns = nsub[b];
   const int o = subofs[b];
-  const int st = sstart[b * cpb];
-  const int cnt = sstart[(b + 1) * cpb] - st;
+  const int st = bstart[b];
+  const int cnt = bstart[b + 1] - st;
   for (int k = 0; k < ns; k++) {
     sub_bin[o + k] = (int32_t)b;
     sub_start[o + k] = st + k * maxsub;
@@ -274,19 +305,18 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
   if (i < n) p[i] = (int32_t)i;
 }
 
-hipError_t launch_subprob_count(const int32_t* sstart, int64_t cpb, int32_t* nsub, int64_t nbins,
-                                int maxsub, int32_t* nonempty, hipStream_t s) {
-  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, sstart,
-                     cpb, nsub, nbins, maxsub, nonempty);
+hipError_t launch_subprob_count(const int32_t* bstart, int32_t* nsub, int64_t nbins, int maxsub,
+                                int32_t* nonempty, hipStream_t s) {
+  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, bstart,
+                     nsub, nbins, maxsub, nonempty);
   return hipGetLastError();
 }
 
-hipError_t launch_subprob_fill(const int32_t* sstart, int64_t cpb, const int32_t* nsub,
-                               const int32_t* subofs, int64_t nbins, int maxsub,
-                               int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, sstart,
-                     cpb, nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
+hipError_t launch_subprob_fill(const int32_t* bstart, const int32_t* nsub, const int32_t* subofs,
+                               int64_t nbins, int maxsub, int32_t* sub_bin, int32_t* sub_start,
+                               int32_t* sub_len, hipStream_t s) {
+  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, bstart,
+                     nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
   return hipGetLastError();
 }
 

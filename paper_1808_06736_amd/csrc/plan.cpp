@@ -111,8 +111,13 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
 
 void free_points(esn_plan_s* p) {
   dfree(p, (void**)&p->d_pts);
-  dfree(p, (void**)&p->d_key);
-  dfree(p, (void**)&p->d_slot);
+  dfree(p, (void**)&p->d_rec0);
+  for (int k = 0; k < 2; k++) {
+    dfree(p, (void**)&p->d_key[k]);
+    dfree(p, (void**)&p->d_idx[k]);
+  }
+  dfree(p, &p->d_sort_tmp);
+  p->sort_tmp = 0;
   p->cap_M = 0;
 }
 
@@ -131,8 +136,8 @@ void destroy_all(esn_plan_s* p) {
   free_subs(p);
   for (int m = 0; m < 3; m++) dfree(p, (void**)&p->d_pf[m]);
   dfree(p, &p->d_grid);
-  dfree(p, (void**)&p->d_count);
-  dfree(p, (void**)&p->d_sstart);
+  dfree(p, (void**)&p->d_bcount);
+  dfree(p, (void**)&p->d_bstart);
   dfree(p, (void**)&p->d_nsub);
   dfree(p, (void**)&p->d_subofs);
   dfree(p, (void**)&p->d_scan_tmp);
@@ -356,11 +361,13 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   // ---- per-cell / per-bin arrays ----
   {
     const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
-    p->ncells = p->nbins * cpb;
-    if (p->ncells + 1 > (int64_t)1 << 31) return fail(ESN_ERR_BAD_ARG);
-    const int64_t nscan = std::max(p->ncells + 1, p->nbins);
-    if (dalloc(p, (void**)&p->d_count, 4 * (p->ncells + 1)) ||
-        dalloc(p, (void**)&p->d_sstart, 4 * (p->ncells + 1)) ||
+    const int64_t ncells = p->nbins * cpb;
+    if (ncells + 1 > (int64_t)1 << 31) return fail(ESN_ERR_BAD_ARG);
+    p->key_bits = 0;
+    while (((int64_t)1 << p->key_bits) < ncells) p->key_bits++;
+    const int64_t nscan = p->nbins + 1;
+    if (dalloc(p, (void**)&p->d_bcount, 4 * (p->nbins + 1)) ||
+        dalloc(p, (void**)&p->d_bstart, 4 * (p->nbins + 1)) ||
         dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
         dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(nscan) + 1)) ||
         dalloc(p, (void**)&p->d_flags, 4 * 4))
@@ -390,9 +397,16 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
   if (M > p->cap_M) {
     free_points(p);
-    if (dalloc(p, (void**)&p->d_pts, (size_t)pts_record_bytes(p->pts_code) * M) ||
-        dalloc(p, (void**)&p->d_key, 4 * M) || dalloc(p, (void**)&p->d_slot, 4 * M))
-      return ESN_ERR_ALLOC;
+    const size_t rb = (size_t)pts_record_bytes(p->pts_code) * M;
+    if (dalloc(p, (void**)&p->d_pts, rb)) return ESN_ERR_ALLOC;
+    if (p->opts.sort) {
+      p->sort_tmp = sort_tmp_bytes(M, p->key_bits);
+      if (dalloc(p, (void**)&p->d_rec0, rb) || dalloc(p, (void**)&p->d_key[0], 4 * M) ||
+          dalloc(p, (void**)&p->d_key[1], 4 * M) || dalloc(p, (void**)&p->d_idx[0], 4 * M) ||
+          dalloc(p, (void**)&p->d_idx[1], 4 * M) ||
+          dalloc(p, &p->d_sort_tmp, std::max<size_t>(p->sort_tmp, 256)))
+        return ESN_ERR_ALLOC;
+    }
     p->cap_M = M;
   }
   SortArgs a;
@@ -409,22 +423,22 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   }
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
-  a.key = p->d_key;
-  a.slot = p->d_slot;
-  a.count = p->d_count;
-  a.sstart = p->d_sstart;
-  a.ncells = p->ncells;
-  a.pts = p->d_pts;
+  a.key = p->d_key[0];
+  a.idx = p->d_idx[0];
+  a.pts = p->opts.sort ? p->d_rec0 : p->d_pts;
   a.flags = p->d_flags;
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
   int nsub = 0;
   const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
   if (p->opts.sort) {
-    ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * (p->ncells + 1), s));
-    ESN_HIP(launch_bin_count(a, s));
-    ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_scan_tmp, s));
-    ESN_HIP(launch_scatter(a, s));
-    ESN_HIP(launch_subprob_count(p->d_sstart, cpb, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
+    ESN_HIP(hipMemsetAsync(p->d_bcount, 0, 4 * (p->nbins + 1), s));
+    ESN_HIP(launch_sort_keys(a, s));
+    int sel = 0;
+    ESN_HIP(sort_pairs(p->d_key, p->d_idx, &sel, M, p->key_bits, p->d_sort_tmp, p->sort_tmp, s));
+    ESN_HIP(launch_gather_records(p->d_key[sel], p->d_idx[sel], p->d_rec0, p->d_pts,
+                                  pts_record_bytes(p->pts_code), M, (int)cpb, p->d_bcount, s));
+    ESN_HIP(exclusive_scan_i32(p->d_bcount, p->d_bstart, p->nbins + 1, p->d_scan_tmp, s));
+    ESN_HIP(launch_subprob_count(p->d_bstart, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
     ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned + 2, p->d_subofs + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
@@ -449,7 +463,7 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
         return ESN_ERR_ALLOC;
       p->cap_sub = nsub;
     }
-    ESN_HIP(launch_subprob_fill(p->d_sstart, cpb, p->d_nsub, p->d_subofs, p->nbins, p->maxsub,
+    ESN_HIP(launch_subprob_fill(p->d_bstart, p->d_nsub, p->d_subofs, p->nbins, p->maxsub,
                                 p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
   }
   p->nsub = nsub;
@@ -654,8 +668,9 @@ int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps
   const int64_t rec = prec == ESN_DOUBLE ? 32 : 16;
   (void)type;
   return 2 * grid                 // fine grid + rocFFT work buffer
-         + 8 * (cells + 1)        // cell counts and starts
-         + M * (rec + 8)          // sorted records, keys and slots
+         + 8 * (cells + 1)        // bin counts and starts (at most one bin per cell)
+         + M * (2 * rec + 24)     // records (input order, sorted), key and index
+                                  // double buffers, radix sort scratch
          + (int64_t)(M / 256 + 1024) * 12   // subproblem lists
          + (1 << 20);             // factors, flags, small buffers
 }
