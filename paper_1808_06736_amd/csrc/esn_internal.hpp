@@ -85,26 +85,24 @@ struct SortArgs {
   int pts_code;
   int chkbnds;
   uint32_t* key;            // [M] cell key of each point
-  uint32_t* idx;            // [M] original index of each point
   unsigned char* pts;       // [M] point records (input order for launch_sort_keys)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
 };
-// Cell key, original index and point record of every point, in input order.
+// Cell key and point record of every point, in input order.
 hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s);
 // Point records written unsorted (no binning).
 hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
-// Stable sort of (key, index) pairs on the low key_bits bits of the key.  The
-// pairs are in key[0], idx[0] on entry and in key[sel], idx[sel] on return
-// (sel in {0, 1}); tmp holds sort_tmp_bytes(M) bytes.
-size_t sort_tmp_bytes(int64_t M, int key_bits);
-hipError_t sort_pairs(uint32_t* key[2], uint32_t* idx[2], int* sel, int64_t M, int key_bits,
-                      void* tmp, size_t tmp_bytes, hipStream_t s);
-// Sorted records pts[i] = rec[perm[i]] (rec_bytes 16 or 32), and for every
-// bin b = key / cpb, bcount[b] += (end - start) of its run of sorted keys
-// (bcount zeroed by the caller, nbins + 1 entries).
-hipError_t launch_gather_records(const uint32_t* skey, const uint32_t* perm,
-                                 const unsigned char* rec, unsigned char* pts, int rec_bytes,
-                                 int64_t M, int cpb, int32_t* bcount, hipStream_t s);
+// Stable sort of the M point records (rec_bytes 16 or 32) by the low key_bits
+// bits of their keys.  Keys and records are in key[0], rec[0] on entry and in
+// key[sel], rec[sel] on return (sel in {0, 1}); tmp holds
+// sort_tmp_bytes(M, key_bits, rec_bytes) bytes.
+size_t sort_tmp_bytes(int64_t M, int key_bits, int rec_bytes);
+hipError_t sort_records(uint32_t* key[2], unsigned char* rec[2], int* sel, int64_t M,
+                        int key_bits, int rec_bytes, void* tmp, size_t tmp_bytes, hipStream_t s);
+// For every bin b = key / cpb of the sorted keys, bcount[b] += (end - start)
+// of its run (bcount zeroed by the caller, nbins + 1 entries).
+hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,
+                             hipStream_t s);
 // Exclusive scan of n int32 values (in -> out, may not alias); tmp must hold
 // scan_tmp_elems(n) int32.
 int64_t scan_tmp_elems(int64_t n);
@@ -200,8 +198,7 @@ struct esn_plan_s {
   int64_t cap_M = 0;
   unsigned char* d_pts = nullptr;   // [M] sorted point records
   uint32_t* d_key[2] = {nullptr, nullptr};   // [M] cell keys (sort double buffer)
-  uint32_t* d_idx[2] = {nullptr, nullptr};   // [M] original indices (sort double buffer)
-  unsigned char* d_rec0 = nullptr;           // [M] point records in input order
+  unsigned char* d_rec0 = nullptr;           // [M] point records (sort double buffer with d_pts)
   void* d_sort_tmp = nullptr;
   size_t sort_tmp = 0;
   int key_bits = 0;              // bits of the largest cell key

@@ -3,13 +3,12 @@
 //
 //   sort_keys : fold each coordinate into [0, 2pi), rescale to fine-grid units
 //               t = x n / 2pi (FP64), take the cell floor(t); write the cell
-//               key, the point's index and its record in input order.  Cells
-//               are numbered bin-major, so every bin (and, in 3D, every
-//               column of a bin) is a run of keys.
-//   sort      : stable LSD radix sort of the (key, index) pairs (rocPRIM), so
+//               key and the point's record (coordinates and index) in input
+//               order.  Cells are numbered bin-major, so every bin (and, in
+//               3D, every column of a bin) is a run of keys.
+//   sort      : stable LSD radix sort of the records by key (rocPRIM), so
 //               points of one cell keep their input order.
-//   gather    : sorted records pts[i] = rec[perm[i]]; the run of each bin in
-//               the sorted keys gives its point count.
+//   bounds    : the run of each bin in the sorted keys gives its point count.
 //   scan      : exclusive prefix sums of the bin counts = first position of a bin.
 //   subprob   : split each bin's points into runs of at most maxsub.
 #include <cstring>
@@ -105,19 +104,13 @@ __global__ void sort_keys_kernel(const SortArgs a) {
   const int key = point_key<CTy>(a, j, &flag, q, t);
   if (flag) atomicOr(a.flags, flag);
   a.key[j] = (uint32_t)key;
-  a.idx[j] = (uint32_t)j;
   write_record(a, j, q, t, j);
 }
 
-__global__ void gather_records_kernel(const uint32_t* __restrict__ skey,
-                                      const uint32_t* __restrict__ perm,
-                                      const uint4* __restrict__ rec, uint4* __restrict__ pts,
-                                      int nvec, int64_t M, uint32_t cpb,
-                                      int32_t* __restrict__ bcount) {
+__global__ void bin_bounds_kernel(const uint32_t* __restrict__ skey, int64_t M, uint32_t cpb,
+                                  int32_t* __restrict__ bcount) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const int64_t src = (int64_t)perm[i] * nvec;
-  for (int v = 0; v < nvec; v++) pts[i * nvec + v] = rec[src + v];
   // bin b occupies sorted positions [start, end): add end at its last
   // position and subtract start at its first, so bcount[b] = end - start
   const uint32_t b = skey[i] / cpb;
@@ -148,34 +141,48 @@ hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t sort_tmp_bytes(int64_t M, int key_bits) {
-  size_t bytes = 0;
-  rocprim::double_buffer<uint32_t> k(nullptr, nullptr), v(nullptr, nullptr);
-  if (rocprim::radix_sort_pairs(nullptr, bytes, k, v, (unsigned)M, 0u, (unsigned)key_bits) !=
-      hipSuccess)
-    return 0;
-  return bytes;
-}
+// The sorted records as rocPRIM values.
+struct alignas(16) Rec16 { uint32_t w[4]; };
+struct alignas(16) Rec32 { uint32_t w[8]; };
 
-hipError_t sort_pairs(uint32_t* key[2], uint32_t* idx[2], int* sel, int64_t M, int key_bits,
-                      void* tmp, size_t tmp_bytes, hipStream_t s) {
-  *sel = 0;
-  if (M <= 1 || key_bits <= 0) return hipSuccess;
-  rocprim::double_buffer<uint32_t> k(key[0], key[1]), v(idx[0], idx[1]);
-  size_t bytes = tmp_bytes;
-  hipError_t e = rocprim::radix_sort_pairs(tmp, bytes, k, v, (unsigned)M, 0u, (unsigned)key_bits, s);
-  if (e != hipSuccess) return e;
-  *sel = k.current() == key[0] ? 0 : 1;
+template <typename R>
+static hipError_t sort_records_t(uint32_t* key[2], unsigned char* rec[2], int* sel, int64_t M,
+                                 int key_bits, void* tmp, size_t* tmp_bytes, hipStream_t s) {
+  rocprim::double_buffer<uint32_t> k(key[0], key[1]);
+  rocprim::double_buffer<R> v(reinterpret_cast<R*>(rec[0]), reinterpret_cast<R*>(rec[1]));
+  hipError_t e = rocprim::radix_sort_pairs(tmp, *tmp_bytes, k, v, (unsigned)M, 0u,
+                                           (unsigned)key_bits, s);
+  if (e != hipSuccess || !tmp) return e;
+  *sel = v.current() == reinterpret_cast<R*>(rec[0]) ? 0 : 1;
+  if ((k.current() == key[0] ? 0 : 1) != *sel) return hipErrorUnknown;
   return hipSuccess;
 }
 
-hipError_t launch_gather_records(const uint32_t* skey, const uint32_t* perm,
-                                 const unsigned char* rec, unsigned char* pts, int rec_bytes,
-                                 int64_t M, int cpb, int32_t* bcount, hipStream_t s) {
+size_t sort_tmp_bytes(int64_t M, int key_bits, int rec_bytes) {
+  size_t bytes = 0;
+  uint32_t* k[2] = {nullptr, nullptr};
+  unsigned char* r[2] = {nullptr, nullptr};
+  int sel = 0;
+  const hipError_t e =
+      rec_bytes == 16 ? sort_records_t<Rec16>(k, r, &sel, M, key_bits, nullptr, &bytes, 0)
+                      : sort_records_t<Rec32>(k, r, &sel, M, key_bits, nullptr, &bytes, 0);
+  return e == hipSuccess ? bytes : 0;
+}
+
+hipError_t sort_records(uint32_t* key[2], unsigned char* rec[2], int* sel, int64_t M,
+                        int key_bits, int rec_bytes, void* tmp, size_t tmp_bytes, hipStream_t s) {
+  *sel = 0;
+  if (M <= 1 || key_bits <= 0) return hipSuccess;
+  size_t bytes = tmp_bytes;
+  return rec_bytes == 16 ? sort_records_t<Rec16>(key, rec, sel, M, key_bits, tmp, &bytes, s)
+                         : sort_records_t<Rec32>(key, rec, sel, M, key_bits, tmp, &bytes, s);
+}
+
+hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,
+                             hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_records_kernel, dim3(nblocks(M, 256)), dim3(256), 0, s, skey, perm,
-                     reinterpret_cast<const uint4*>(rec), reinterpret_cast<uint4*>(pts),
-                     rec_bytes / 16, M, (uint32_t)cpb, bcount);
+  hipLaunchKernelGGL(bin_bounds_kernel, dim3(nblocks(M, 256)), dim3(256), 0, s, skey, M,
+                     (uint32_t)cpb, bcount);
   return hipGetLastError();
 }
 

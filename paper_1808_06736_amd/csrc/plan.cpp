@@ -112,10 +112,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
 void free_points(esn_plan_s* p) {
   dfree(p, (void**)&p->d_pts);
   dfree(p, (void**)&p->d_rec0);
-  for (int k = 0; k < 2; k++) {
-    dfree(p, (void**)&p->d_key[k]);
-    dfree(p, (void**)&p->d_idx[k]);
-  }
+  for (int k = 0; k < 2; k++) dfree(p, (void**)&p->d_key[k]);
   dfree(p, &p->d_sort_tmp);
   p->sort_tmp = 0;
   p->cap_M = 0;
@@ -401,10 +398,9 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     const size_t rb = (size_t)pts_record_bytes(p->pts_code) * M;
     if (dalloc(p, (void**)&p->d_pts, rb)) return ESN_ERR_ALLOC;
     if (p->opts.sort) {
-      p->sort_tmp = sort_tmp_bytes(M, p->key_bits);
+      p->sort_tmp = sort_tmp_bytes(M, p->key_bits, pts_record_bytes(p->pts_code));
       if (dalloc(p, (void**)&p->d_rec0, rb) || dalloc(p, (void**)&p->d_key[0], 4 * M) ||
-          dalloc(p, (void**)&p->d_key[1], 4 * M) || dalloc(p, (void**)&p->d_idx[0], 4 * M) ||
-          dalloc(p, (void**)&p->d_idx[1], 4 * M) ||
+          dalloc(p, (void**)&p->d_key[1], 4 * M) ||
           dalloc(p, &p->d_sort_tmp, std::max<size_t>(p->sort_tmp, 256)))
         return ESN_ERR_ALLOC;
     }
@@ -425,7 +421,6 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
   a.key = p->d_key[0];
-  a.idx = p->d_idx[0];
   a.pts = p->opts.sort ? p->d_rec0 : p->d_pts;
   a.flags = p->d_flags;
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
@@ -435,9 +430,13 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     ESN_HIP(hipMemsetAsync(p->d_bcount, 0, 4 * (p->nbins + 1), s));
     ESN_HIP(launch_sort_keys(a, s));
     int sel = 0;
-    ESN_HIP(sort_pairs(p->d_key, p->d_idx, &sel, M, p->key_bits, p->d_sort_tmp, p->sort_tmp, s));
-    ESN_HIP(launch_gather_records(p->d_key[sel], p->d_idx[sel], p->d_rec0, p->d_pts,
-                                  pts_record_bytes(p->pts_code), M, (int)cpb, p->d_bcount, s));
+    unsigned char* recs[2] = {p->d_rec0, p->d_pts};
+    ESN_HIP(sort_records(p->d_key, recs, &sel, M, p->key_bits, pts_record_bytes(p->pts_code),
+                         p->d_sort_tmp, p->sort_tmp, s));
+    // the sorted records are the plan's points; the other buffer is scratch
+    p->d_pts = recs[sel];
+    p->d_rec0 = recs[1 - sel];
+    ESN_HIP(launch_bin_bounds(p->d_key[sel], M, (int)cpb, p->d_bcount, s));
     ESN_HIP(exclusive_scan_i32(p->d_bcount, p->d_bstart, p->nbins + 1, p->d_scan_tmp, s));
     ESN_HIP(launch_subprob_count(p->d_bstart, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
     ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
@@ -670,8 +669,7 @@ int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps
   (void)type;
   return 2 * grid                 // fine grid + rocFFT work buffer
          + 8 * (cells + 1)        // bin counts and starts (at most one bin per cell)
-         + M * (2 * rec + 24)     // records (input order, sorted), key and index
-                                  // double buffers, radix sort scratch
+         + M * (2 * rec + 8)      // record and key double buffers of the sort
          + (int64_t)(M / 256 + 1024) * 12   // subproblem lists
          + (1 << 20);             // factors, flags, small buffers
 }
