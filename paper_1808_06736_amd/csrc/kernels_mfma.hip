@@ -141,27 +141,27 @@ size_t mfma_interp_lds_bytes(const int* b) { return mfma_lds_bytes(b, 3); }
 
 // Fill the wrapped grid offsets of the tile lines whose origin is (ox, oy, oz):
 // gx[i] = wrap(ox + i), gy[i] = n0 wrap(oy + i), gz[i] = n0 n1 wrap(oz + i).
-__device__ __forceinline__ void tile_offsets(int lane, int T0, int T1, int T2, int ox, int oy,
-                                             int oz, int n0, int n1, int n2, int* gx, int* gy,
-                                             int64_t* gz) {
-  for (int i = lane; i < T0; i += 64) gx[i] = wrap2(ox + i, n0);
-  for (int i = lane; i < T1; i += 64) gy[i] = n0 * wrap2(oy + i, n1);
-  for (int i = lane; i < T2; i += 64) gz[i] = (int64_t)n0 * n1 * wrap2(oz + i, n2);
+__device__ __forceinline__ void tile_offsets(int tid, int nthr, int T0, int T1, int T2, int ox,
+                                             int oy, int oz, int n0, int n1, int n2, int* gx,
+                                             int* gy, int64_t* gz) {
+  for (int i = tid; i < T0; i += nthr) gx[i] = wrap2(ox + i, n0);
+  for (int i = tid; i < T1; i += nthr) gy[i] = n0 * wrap2(oy + i, n1);
+  for (int i = tid; i < T2; i += nthr) gz[i] = (int64_t)n0 * n1 * wrap2(oz + i, n2);
 }
 
-// Walks the cells lane, lane + 64, ... of a T0 x T1 x T2 tile (x fastest),
+// Walks the cells tid, tid + nthr, ... of a T0 x T1 x T2 tile (x fastest),
 // keeping (ix, iy, iz) without divisions in the loop.
 struct TileWalk {
   int ix, iy, iz, dx, dq, T0, T1;
   // float offset of the cell in a tile with planes of ps floats
   __device__ __forceinline__ int ofs(int ps) const { return iz * ps + 2 * (iy * T0 + ix); }
-  __device__ __forceinline__ TileWalk(int lane, int T0_, int T1_) : T0(T0_), T1(T1_) {
-    ix = lane % T0;
-    const int r = lane / T0;
+  __device__ __forceinline__ TileWalk(int tid, int nthr, int T0_, int T1_) : T0(T0_), T1(T1_) {
+    ix = tid % T0;
+    const int r = tid / T0;
     iy = r % T1;
     iz = r / T1;
-    dx = 64 % T0;
-    dq = 64 / T0;
+    dx = nthr % T0;
+    dq = nthr / T0;
   }
   __device__ __forceinline__ void next() {
     ix += dx;
@@ -177,8 +177,13 @@ struct TileWalk {
   }
 };
 
+// Two waves per subproblem share the bin tile and the staged weights.  Wave
+// wv accumulates row tiles 2 wv and 2 wv + 1, i.e. ring slots 4 wv .. 4 wv + 3;
+// a tile plane always lives in the same ring slot (plane r -> slot r mod 8),
+// so the two waves never add into the same plane.  In each batch wave 0
+// computes the x and y weights and wave 1 the z weights, strengths and cells.
 template <int W>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
 spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __restrict__ grid) {
   static_assert(W >= 2 && W <= 7, "matrix-core spreading needs w <= 7");
   constexpr int H = W / 2;
@@ -204,16 +209,18 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int p1 = p0 + g.sub_len[sidx];
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
   {
     float4* o4 = reinterpret_cast<float4*>(otf);
     const int n4 = T2 * ps / 4;
-    for (int i = lane; i < n4; i += 64) o4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < n4; i += 128) o4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  tile_offsets(lane, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
+  tile_offsets(tid, 128, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
 
   // lane roles in the accumulators: row tile t holds ring slots 2t + hz, x
   // cells x0 .. x0 + 3 (one per accumulator element), y cell yl, re/im reim
@@ -221,35 +228,35 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int reim = lane & 1;
   const int hz = lane >> 5;
   const int x0 = 4 * ((lane >> 4) & 1);
-  const int kzo = 4 * ((lane >> 3) & 1);   // this lane's 4 ring weights (A operand rows)
-  v4f acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  // this lane's 2 ring weights (A operand rows of tiles 2 wv, 2 wv + 1)
+  const int kzo = 4 * ((lane >> 3) & 1) + 2 * wv;
+  v4f acc[2];
+  acc[0] = acc[1] = v4f{0.f, 0.f, 0.f, 0.f};
   int cur = -1;        // current column (lx + b0 ly), -1: none
   int colbase = 0;     // this lane's float offset in a tile plane for the current column
   int pend = 0;        // the ring holds tile planes pend .. pend + 7
 
-  // add the ring slots in mask fm (wave-uniform) into the bin tile and clear them
+  // add this wave's ring slots in mask fm (block-uniform) into the bin tile and clear them
   auto flush = [&](unsigned fm) {
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
+    for (int u = 0; u < 2; u++) {
+      const int t = 2 * wv + u;
       if (fm & (3u << (2 * t))) {
         const int s = 2 * t + hz;
         if ((fm >> s) & 1u) {
           float* d = otf + (pend + ((s - pend) & 7)) * ps + colbase;
 #pragma unroll
-          for (int i = 0; i < 4; i++) d[2 * i] += acc[t][i];
-          acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+          for (int i = 0; i < 4; i++) d[2 * i] += acc[u][i];
+          acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
         }
       }
     }
   };
 
-  // point records flow through registers one batch ahead of the matrix work:
-  // while batch b runs on the matrix cores, the records of batch b+2 and the
-  // strengths of batch b+1 (gathered through the permutation) are in flight
-  // (the loads are unconditional, at indices clamped into the subproblem, so
-  // that the waits for them can be placed where the values are used)
+  // point records flow through registers one batch ahead of the matrix work
+  // (both waves read them; wave 1 also gathers the strengths, one batch
+  // ahead).  The loads are unconditional, at indices clamped into the
+  // subproblem, so that the waits for them can be placed where the values are used.
   const uint4* rec = reinterpret_cast<const uint4*>(g.pts);
   const int plast = p1 - 1;
   uint4 r0 = rec[min(p0 + lane, plast)];
@@ -260,38 +267,37 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
     const uint4 r2 = rec[min(base + 128 + lane, plast)];
     const float2 cc1 = c[(int)r1.w];
     __syncthreads();
-    int mycol, myzr;   // this lane's point: column in the bin, z cell in the bin
     {
-      const uint32_t q[3] = {r0.x, r0.y, r0.z};
-      float k[3][W];
-      int sh[3], cell[3];
+      float k[W], v[8];
+      if (wv == 0) {
+        const uint32_t q[2] = {r0.x, r0.y};
 #pragma unroll
-      for (int m = 0; m < 3; m++) {
-        const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
-        // window shift decided on the exact fraction bits (see decode_coord)
-        sh[m] = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
-        cell[m] = (int)(q[m] >> g.fbits[m]);
-        es_weights_hw<W>(sh[m], ldexpf((float)fr, -g.fbits[m]), bl, k[m]);
-      }
-      const int zr = cell[2] - bz0;
-      float v[8], vz[8];
-      slots8<W>(k[0], sh[0], v);
-      store8(skx + lane * 8, v);
-      slots8<W>(k[1], sh[1], v);
-      store8(sky + lane * 8, v);
-      slots8<W>(k[2], sh[2], v);   // planes zr .. zr + 7 of the tile
-      rotate8(v, zr & 7);          // -> ring slots
+        for (int m = 0; m < 2; m++) {
+          const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
+          // window shift decided on the exact fraction bits (see decode_coord)
+          const int sh = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
+          es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[m]), bl, k);
+          slots8<W>(k, sh, v);
+          store8((m == 0 ? skx : sky) + lane * 8, v);
+        }
+      } else {
+        const uint32_t fr = r0.z & ((1u << g.fbits[2]) - 1u);
+        const int sh = (W & 1) ? (fr > (1u << (g.fbits[2] - 1))) : (fr != 0u);
+        const int zr = (int)(r0.z >> g.fbits[2]) - bz0;
+        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[2]), bl, k);
+        slots8<W>(k, sh, v);   // planes zr .. zr + 7 of the tile
+        rotate8(v, zr & 7);    // -> ring slots
+        float vz[8];
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        vz[i] = v[2 * i];
-        vz[4 + i] = v[2 * i + 1];
+        for (int i = 0; i < 4; i++) {
+          vz[i] = v[2 * i];
+          vz[4 + i] = v[2 * i + 1];
+        }
+        store8(skz + lane * 8, vz);
+        sc[lane] = cc0;
+        scol[lane] = ((int)(r0.x >> g.fbits[0]) - bx0) + b0 * ((int)(r0.y >> g.fbits[1]) - by0);
+        szr[lane] = zr;
       }
-      store8(skz + lane * 8, vz);
-      sc[lane] = cc0;
-      mycol = (cell[0] - bx0) + b0 * (cell[1] - by0);
-      myzr = zr;
-      scol[lane] = mycol;
-      szr[lane] = myzr;
     }
     r0 = r1;
     r1 = r2;
@@ -305,8 +311,8 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-      const int col = __builtin_amdgcn_readlane(mycol, q0);
-      const int zr = __builtin_amdgcn_readlane(myzr, q0);
+      const int col = scol[q0];
+      const int zr = szr[q0];
       if (col != cur) {
         if (cur >= 0) flush(0xffu);
         cur = col;
@@ -327,34 +333,31 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
       // the operands of each 4-point step are read from LDS one step ahead
       // (at an index clamped into the run), so the reads overlap the matrix work
       float ax_n, ky_n;
-      float4 kz_n;
-      float2 cv_n;
+      float2 kz_n, cv_n;
       {
         const int qs = min(q0 + (lane >> 4), q1 - 1);
         ax_n = skx[qs * 8 + (lane & 7)];
-        kz_n = *reinterpret_cast<const float4*>(skz + qs * 8 + kzo);
+        kz_n = *reinterpret_cast<const float2*>(skz + qs * 8 + kzo);
         cv_n = sc[qs];
         ky_n = sky[qs * 8 + yl];
       }
       for (int q = q0; q < q1; q += 4) {
         const float ax = ax_n, ky = ky_n;
-        const float4 kz4 = kz_n;
+        const float2 kz2 = kz_n;
         const float2 cv = cv_n;
         {
           int qs = min(q + 4 + (lane >> 4), q1 - 1);
           opaque(qs);
           ax_n = skx[qs * 8 + (lane & 7)];
-          kz_n = *reinterpret_cast<const float4*>(skz + qs * 8 + kzo);
+          kz_n = *reinterpret_cast<const float2*>(skz + qs * 8 + kzo);
           cv_n = sc[qs];
           ky_n = sky[qs * 8 + yl];
           keep_order();
         }
         const bool ok = q + (lane >> 4) < q1;
         const float bv = ok ? (reim ? cv.y : cv.x) * ky : 0.f;
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.x, bv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.y, bv, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.z, bv, acc[2], 0, 0, 0);
-        acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz4.w, bv, acc[3], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.x, bv, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.y, bv, acc[1], 0, 0, 0);
       }
     }
   }
@@ -362,8 +365,8 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   __syncthreads();
 
   // add the bin tile to the periodic fine grid (touched cells only)
-  TileWalk tw(lane, T0, T1);
-  for (int i = lane; i < tc; i += 64, tw.next()) {
+  TileWalk tw(tid, 128, T0, T1);
+  for (int i = tid; i < tc; i += 128, tw.next()) {
     const float2 v = *reinterpret_cast<const float2*>(otf + tw.ofs(ps));
     if (v.x != 0.f || v.y != 0.f) {
       float* dst = grid + 2 * (gz[tw.iz] + gy[tw.iy] + gx[tw.ix]);
@@ -373,8 +376,11 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   }
 }
 
+// Two waves per subproblem share the grid tile and the staged weights: in
+// each batch wave 0 computes the x and y weights and wave 1 the z weights and
+// cells; the waves then take alternate runs.
 template <int W>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(128)
 interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __restrict__ c) {
   static_assert(W >= 2 && W <= 7, "matrix-core interpolation needs w <= 7");
   constexpr int H = W / 2;
@@ -401,7 +407,9 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int p1 = p0 + g.sub_len[sidx];
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
@@ -410,13 +418,13 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const uint4* rec = reinterpret_cast<const uint4*>(g.pts);
   const int plast = p1 - 1;
   uint4 r0 = rec[min(p0 + lane, plast)];
-  tile_offsets(lane, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
+  tile_offsets(tid, 128, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
   __syncthreads();
   {
-    // the bin's grid tile, 8 cells per lane in flight at a time
-    constexpr int U = 8;
-    TileWalk tw(lane, T0, T1);
-    for (int i0 = 0; i0 < tc; i0 += 64 * U) {
+    // the bin's grid tile, 4 cells per thread in flight at a time
+    constexpr int U = 4;
+    TileWalk tw(tid, 128, T0, T1);
+    for (int i0 = 0; i0 < tc; i0 += 128 * U) {
       float2 v[U];
       int o[U];
 #pragma unroll
@@ -429,7 +437,7 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       }
 #pragma unroll
       for (int u = 0; u < U; u++)
-        if (i0 + 64 * u + lane < tc) *reinterpret_cast<float2*>(gtf + o[u]) = v[u];
+        if (i0 + 128 * u + tid < tc) *reinterpret_cast<float2*>(gtf + o[u]) = v[u];
     }
   }
 
@@ -439,39 +447,40 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
     const int nbatch = min(64, p1 - base);
     const uint4 r1 = rec[min(base + 64 + lane, plast)];
     __syncthreads();
-    int mycol, myzr;   // this lane's point: column in the bin, z cell in the bin
     {
-      const uint32_t q[3] = {r0.x, r0.y, r0.z};
       float k[W], v[8];
-      int cell[3];
-#pragma unroll
-      for (int m = 0; m < 3; m++) {
+      const int m0 = wv == 0 ? 0 : 2;
+      const int m1 = wv == 0 ? 2 : 3;
+      const uint32_t q[3] = {r0.x, r0.y, r0.z};
+      for (int m = m0; m < m1; m++) {
         const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
         // window shift decided on the exact fraction bits (see decode_coord)
         const int sh = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
-        cell[m] = (int)(q[m] >> g.fbits[m]);
         es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[m]), bl, k);
         slots8<W>(k, sh, v);
         store8((m == 0 ? skx : m == 1 ? sky : skz) + lane * 8, v);
       }
-      mycol = (cell[0] - bx0) + b0 * (cell[1] - by0);
-      myzr = cell[2] - bz0;
-      scol[lane] = mycol;
-      szr[lane] = myzr;
-      sperm[lane] = (int)r0.w;
+      if (wv == 1) {
+        scol[lane] = ((int)(r0.x >> g.fbits[0]) - bx0) + b0 * ((int)(r0.y >> g.fbits[1]) - by0);
+        szr[lane] = (int)(r0.z >> g.fbits[2]) - bz0;
+        sperm[lane] = (int)r0.w;
+      }
     }
     r0 = r1;
     __syncthreads();
     const bool starts = lane < nbatch &&
                         (lane == 0 || szr[lane] != szr[lane - 1] || scol[lane] != scol[lane - 1]);
     uint64_t runs = __ballot(starts);
+    // this wave takes every other run
+    if (wv == 1 && runs) runs &= runs - 1;
     while (runs) {
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-      const int col = __builtin_amdgcn_readlane(mycol, q0);
+      if (runs) runs &= runs - 1;   // skip the other wave's run
+      const int col = scol[q0];
       const int lx = col % b0, ly = col / b0;
-      const int zrel = __builtin_amdgcn_readlane(myzr, q0);   // first window plane of the cell
+      const int zrel = szr[q0];          // first window plane of the cell, in the tile
       // B operand of the run: footprint cell (x, y) = (4 (s & 1) + kq, s >> 1), plane n >> 1
       float bop[16];
 #pragma unroll
@@ -524,7 +533,7 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       }
     }
     __syncthreads();
-    if (lane < nbatch) c[sperm[lane]] = sout[lane];
+    if (tid < nbatch) c[sperm[tid]] = sout[tid];
   }
 }
 
@@ -532,7 +541,7 @@ template <int W>
 static hipError_t spread_mfma_w(const GeomArgs& g, int nsub, const void* c, void* grid,
                                 hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
-  hipLaunchKernelGGL((spread_mfma_kernel<W>), dim3(nsub), dim3(64), mfma_spread_lds_bytes(W, g.b),
+  hipLaunchKernelGGL((spread_mfma_kernel<W>), dim3(nsub), dim3(128), mfma_spread_lds_bytes(W, g.b),
                      s, g, static_cast<const float2*>(c), static_cast<float*>(grid));
   return hipGetLastError();
 }
@@ -541,7 +550,7 @@ template <int W>
 static hipError_t interp_mfma_w(const GeomArgs& g, int nsub, const void* grid, void* c,
                                 hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
-  hipLaunchKernelGGL((interp_mfma_kernel<W>), dim3(nsub), dim3(64), mfma_interp_lds_bytes(g.b), s,
+  hipLaunchKernelGGL((interp_mfma_kernel<W>), dim3(nsub), dim3(128), mfma_interp_lds_bytes(g.b), s,
                      g, static_cast<const float2*>(grid), static_cast<float2*>(c));
   return hipGetLastError();
 }
