@@ -33,10 +33,16 @@ SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "serve.cpp",
            "kernels_interp.hip", "kernels_mfma.hip"]
 
 
+# Per-source extra flags.  The matrix-core kernels keep their MFMA accumulators
+# in ordinary VGPRs (gfx950 accepts them there), which saves the copies between
+# accumulator and vector registers around the data-dependent flushes.
+EXTRA = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

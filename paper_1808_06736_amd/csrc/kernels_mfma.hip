@@ -100,6 +100,8 @@ __device__ __forceinline__ int wrap2(int g, int n) {
 // that loads indexed by it, issued a loop step ahead, are not merged back into
 // the next step.
 __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+// The same for a wave-uniform value, kept in a scalar register.
+__device__ __forceinline__ void opaque_s(int& v) { asm volatile("" : "+s"(v)); }
 
 // Keeps the memory accesses before it ahead of the code after it (a compiler
 // barrier only: no instruction, no wait).
@@ -121,23 +123,35 @@ __host__ __device__ inline int plane_floats(int T0, int T1) {
   return ((2 * T0 * T1 + 23) / 32) * 32 + 8;
 }
 
-// LDS layout shared by both kernels: the bin tile (bin + 7 cells per dim,
-// planes of plane_floats), [64][8] x, y and z weights, a float2 per point, the
-// wrapped grid offsets of the tile's z planes (int64), then nint ints per point
-// and the wrapped grid offsets of the tile's x and y lines.
-static inline size_t mfma_lds_bytes(const int* b, int nint) {
+// Points staged per batch by the spreading kernel: 64, plus 3 zero points so
+// that the 4-point steps may read past a run's end without a bound check.
+constexpr int kSpreadStage = 67;
+
+// LDS layouts.  Both start with the bin tile (bin + 7 cells per dim, planes of
+// plane_floats) and end with the wrapped grid offsets of the tile's z planes
+// (int64), per-point ints and the offsets of the tile's x and y lines.
+// Spreading stages [67][8] x and z weights and [67][16] B operands;
+// interpolation [64][8] x, y and z weights and a float2 result per point.
+static inline size_t mfma_tail_bytes(const int* b, int nint) {
   const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
-  return T2 * plane_floats((int)T0, (int)T1) * sizeof(float) + 3 * 64 * 8 * sizeof(float) +
-         64 * sizeof(float2) + T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) +
-         (T0 + T1) * sizeof(int);
+  return T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) + (T0 + T1) * sizeof(int);
+}
+
+static inline size_t mfma_tile_bytes(const int* b) {
+  const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
+  return T2 * plane_floats((int)T0, (int)T1) * sizeof(float);
 }
 
 size_t mfma_spread_lds_bytes(int w, const int* b) {
   (void)w;   // 8-wide footprints for every w
-  return mfma_lds_bytes(b, 2);
+  return mfma_tile_bytes(b) + (size_t)kSpreadStage * (8 + 8 + 16) * sizeof(float) +
+         mfma_tail_bytes(b, 2);
 }
 
-size_t mfma_interp_lds_bytes(const int* b) { return mfma_lds_bytes(b, 3); }
+size_t mfma_interp_lds_bytes(const int* b) {
+  return mfma_tile_bytes(b) + 3 * 64 * 8 * sizeof(float) + 64 * sizeof(float2) +
+         mfma_tail_bytes(b, 3);
+}
 
 // Fill the wrapped grid offsets of the tile lines whose origin is (ox, oy, oz):
 // gx[i] = wrap(ox + i), gy[i] = n0 wrap(oy + i), gz[i] = n0 n1 wrap(oz + i).
@@ -192,12 +206,12 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int T0 = b0 + 7, T1 = b1 + 7, T2 = b2 + 7;   // 8-wide footprints for every w
   const int tc = T0 * T1 * T2;
   const int ps = plane_floats(T0, T1);               // floats per tile plane
+  constexpr int NS = kSpreadStage;
   float* otf = reinterpret_cast<float*>(smem_raw);               // [T2][ps]: [T1][T0][2]
-  float* skx = otf + T2 * ps;                                     // [64][8] x slots
-  float* sky = skx + 64 * 8;                                      // [64][8] y slots
-  float* skz = sky + 64 * 8;                                      // [64][8] z ring, pairs split
-  float2* sc = reinterpret_cast<float2*>(skz + 64 * 8);           // [64] strengths
-  int64_t* gz = reinterpret_cast<int64_t*>(sc + 64);              // [T2]
+  float* skx = otf + T2 * ps;                                     // [NS][8] x slots
+  float* skz = skx + NS * 8;                                      // [NS][8] z ring, pairs split
+  float* sb = skz + NS * 8;                                       // [NS][16] B operand
+  int64_t* gz = reinterpret_cast<int64_t*>(sb + NS * 16);         // [T2]
   int* scol = reinterpret_cast<int*>(gz + T2);                    // [64] column in the bin
   int* szr = scol + 64;                                           // [64] z cell in the bin
   int* gx = szr + 64;                                             // [T0]
@@ -216,8 +230,9 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
   {
+    // the tile and the staging (whose padding points stay zero)
     float4* o4 = reinterpret_cast<float4*>(otf);
-    const int n4 = T2 * ps / 4;
+    const int n4 = (T2 * ps + NS * 32) / 4;
     for (int i = tid; i < n4; i += 128) o4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   tile_offsets(tid, 128, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
@@ -228,8 +243,12 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int reim = lane & 1;
   const int hz = lane >> 5;
   const int x0 = 4 * ((lane >> 4) & 1);
-  // this lane's 2 ring weights (A operand rows of tiles 2 wv, 2 wv + 1)
-  const int kzo = 4 * ((lane >> 3) & 1) + 2 * wv;
+  // LDS float offsets of this lane's operands for point 0 of a step: x weight
+  // (row l & 7), its 2 ring weights (rows of tiles 2 wv, 2 wv + 1), B column
+  const int kg = lane >> 4;   // the step's point this lane feeds
+  const int ox = kg * 8 + (lane & 7);
+  const int oz = kg * 8 + 4 * ((lane >> 3) & 1) + 2 * wv;
+  const int ob = kg * 16 + (lane & 15);
   v4f acc[2];
   acc[0] = acc[1] = v4f{0.f, 0.f, 0.f, 0.f};
   int cur = -1;        // current column (lx + b0 ly), -1: none
@@ -254,8 +273,8 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   };
 
   // point records flow through registers one batch ahead of the matrix work
-  // (both waves read them; wave 1 also gathers the strengths, one batch
-  // ahead).  The loads are unconditional, at indices clamped into the
+  // (both waves read them; the strengths, gathered one batch ahead, are used
+  // by wave 1).  The loads are unconditional, at indices clamped into the
   // subproblem, so that the waits for them can be placed where the values are used.
   const uint4* rec = reinterpret_cast<const uint4*>(g.pts);
   const int plast = p1 - 1;
@@ -270,19 +289,15 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
     {
       float k[W], v[8];
       if (wv == 0) {
-        const uint32_t q[2] = {r0.x, r0.y};
-#pragma unroll
-        for (int m = 0; m < 2; m++) {
-          const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
-          // window shift decided on the exact fraction bits (see decode_coord)
-          const int sh = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
-          es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[m]), bl, k);
-          slots8<W>(k, sh, v);
-          store8((m == 0 ? skx : sky) + lane * 8, v);
-        }
-      } else {
-        const uint32_t fr = r0.z & ((1u << g.fbits[2]) - 1u);
-        const int sh = (W & 1) ? (fr > (1u << (g.fbits[2] - 1))) : (fr != 0u);
+        // x weights by footprint slot, z weights by ring slot
+        uint32_t fr = r0.x & ((1u << g.fbits[0]) - 1u);
+        // window shift decided on the exact fraction bits (see decode_coord)
+        int sh = (W & 1) ? (fr > (1u << (g.fbits[0] - 1))) : (fr != 0u);
+        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[0]), bl, k);
+        slots8<W>(k, sh, v);
+        store8(skx + lane * 8, v);
+        fr = r0.z & ((1u << g.fbits[2]) - 1u);
+        sh = (W & 1) ? (fr > (1u << (g.fbits[2] - 1))) : (fr != 0u);
         const int zr = (int)(r0.z >> g.fbits[2]) - bz0;
         es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[2]), bl, k);
         slots8<W>(k, sh, v);   // planes zr .. zr + 7 of the tile
@@ -294,9 +309,19 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
           vz[4 + i] = v[2 * i + 1];
         }
         store8(skz + lane * 8, vz);
-        sc[lane] = cc0;
+      } else {
+        // B operand: y weight times strength, column 2 y + (re, im)
+        const uint32_t fr = r0.y & ((1u << g.fbits[1]) - 1u);
+        const int sh = (W & 1) ? (fr > (1u << (g.fbits[1] - 1))) : (fr != 0u);
+        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[1]), bl, k);
+        slots8<W>(k, sh, v);
+        float4* b4 = reinterpret_cast<float4*>(sb + lane * 16);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          b4[i] = make_float4(v[2 * i] * cc0.x, v[2 * i] * cc0.y, v[2 * i + 1] * cc0.x,
+                              v[2 * i + 1] * cc0.y);
         scol[lane] = ((int)(r0.x >> g.fbits[0]) - bx0) + b0 * ((int)(r0.y >> g.fbits[1]) - by0);
-        szr[lane] = zr;
+        szr[lane] = (int)(r0.z >> g.fbits[2]) - bz0;
       }
     }
     r0 = r1;
@@ -330,32 +355,26 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
         flush(fm);
         pend = zr;
       }
-      // the operands of each 4-point step are read from LDS one step ahead
-      // (at an index clamped into the run), so the reads overlap the matrix work
-      float ax_n, ky_n;
-      float2 kz_n, cv_n;
-      {
-        const int qs = min(q0 + (lane >> 4), q1 - 1);
-        ax_n = skx[qs * 8 + (lane & 7)];
-        kz_n = *reinterpret_cast<const float2*>(skz + qs * 8 + kzo);
-        cv_n = sc[qs];
-        ky_n = sky[qs * 8 + yl];
-      }
+      // the operands of each 4-point step are read from LDS one step ahead,
+      // so the reads overlap the matrix work; a step may run up to 3 points
+      // past the run (other runs' or zero points), whose B operand is masked
+      float ax_n = skx[q0 * 8 + ox];
+      float2 kz_n = *reinterpret_cast<const float2*>(skz + q0 * 8 + oz);
+      float bv_n = sb[q0 * 16 + ob];
       for (int q = q0; q < q1; q += 4) {
-        const float ax = ax_n, ky = ky_n;
+        const float ax = ax_n;
         const float2 kz2 = kz_n;
-        const float2 cv = cv_n;
+        const float bq = bv_n;
         {
-          int qs = min(q + 4 + (lane >> 4), q1 - 1);
-          opaque(qs);
-          ax_n = skx[qs * 8 + (lane & 7)];
-          kz_n = *reinterpret_cast<const float2*>(skz + qs * 8 + kzo);
-          cv_n = sc[qs];
-          ky_n = sky[qs * 8 + yl];
+          // (clamped so that the last, unused prefetch stays in the staging)
+          int qn = min(q + 4, NS - 4);
+          opaque_s(qn);
+          ax_n = skx[qn * 8 + ox];
+          kz_n = *reinterpret_cast<const float2*>(skz + qn * 8 + oz);
+          bv_n = sb[qn * 16 + ob];
           keep_order();
         }
-        const bool ok = q + (lane >> 4) < q1;
-        const float bv = ok ? (reim ? cv.y : cv.x) * ky : 0.f;
+        const float bv = q + kg < q1 ? bq : 0.f;
         acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.x, bv, acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.y, bv, acc[1], 0, 0, 0);
       }
