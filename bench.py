@@ -93,14 +93,14 @@ def measured_traffic(path, kernel, workload):
     if not os.path.exists(path):
         return None
     tr = json.load(open(path))
-    if tr.get("kernel") != kernel or tr.get("workload") != workload:
+    if tr.get("workload") != workload or kernel not in tr.get("kernels", {}):
         return None
     src = os.path.join(ROOT, tr.get("source_file", ""))
     if not os.path.isfile(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != tr.get("source_sha256_16"):
         return None
-    return tr["bytes"]
+    return tr["kernels"][kernel]
 
 
 def copy_calibration(mib):

@@ -74,14 +74,18 @@ typedef struct esn_opts {
   int chkbnds;        /* 1: setpts rejects coordinates outside [-3pi, 3pi] */
   int modeord;        /* 0: increasing k from -floor(N/2); 1: FFT order */
   double upsampfac;   /* fine grid / modes ratio sigma; only 2.0 is supported */
-  int sort;           /* 1 (default): bin-sort points (Sec. 4.1); 0: keep order */
+  int sort;           /* bin-sort the points (Sec. 4.1): 1 (default) choose by
+                         size; 2 stable radix sort of the point records by cell;
+                         3 counting sort by cell (atomic per point, no order
+                         inside a cell); 0: keep the caller's order */
   int spread_method;  /* 0 auto; 1 LDS tile per subproblem; 2 global atomics;
                          3 matrix cores (3D, single precision, w <= 7) */
   int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather;
                          3 matrix cores (3D, single precision, w <= 7) */
   int bin[3];         /* bin size in fine-grid cells per dim; 0 = default */
   int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default
-                         (2048 on the matrix cores, 1024 otherwise) */
+                         (on the matrix cores 1024 for type 1 and 512 for
+                         type 2, 1024 otherwise) */
   int ntransf_chunk;  /* transforms per fused launch; 0 = as many as fit */
   int block;          /* threads per workgroup for spread/interp; 0 = 256 */
 } esn_opts;

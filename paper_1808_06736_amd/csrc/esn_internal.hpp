@@ -85,7 +85,11 @@ struct SortArgs {
   int pts_code;
   int chkbnds;
   uint32_t* key;            // [M] cell key of each point
-  unsigned char* pts;       // [M] point records (input order for launch_sort_keys)
+  int32_t* slot;            // [M] rank of the point within its cell (counting sort)
+  int32_t* count;           // [ncells + 1] points per cell (counting sort)
+  const int32_t* sstart;    // [ncells + 1] first sorted position of a cell (counting sort)
+  unsigned char* pts;       // [M] point records (radix sort: input order; counting
+                            // sort: sorted; no sort: input order)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
 };
 // Cell key and point record of every point, in input order.
@@ -99,6 +103,14 @@ hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
 size_t sort_tmp_bytes(int64_t M, int key_bits, int rec_bytes);
 hipError_t sort_records(uint32_t* key[2], unsigned char* rec[2], int* sel, int64_t M,
                         int key_bits, int rec_bytes, void* tmp, size_t tmp_bytes, hipStream_t s);
+// Counting sort: count each point into its cell (the count before the
+// increment is its slot), then, after an exclusive scan of the counts, store
+// its record at start[cell] + slot.
+hipError_t launch_bin_count(const SortArgs& a, hipStream_t s);
+hipError_t launch_scatter(const SortArgs& a, hipStream_t s);
+// bstart[b] = sstart[b * cpb] for b = 0 .. nbins.
+hipError_t launch_bin_starts(const int32_t* sstart, int64_t cpb, int64_t nbins, int32_t* bstart,
+                             hipStream_t s);
 // For every bin b = key / cpb of the sorted keys, bcount[b] += (end - start)
 // of its run (bcount zeroed by the caller, nbins + 1 entries).
 hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,
@@ -202,6 +214,14 @@ struct esn_plan_s {
   void* d_sort_tmp = nullptr;
   size_t sort_tmp = 0;
   int key_bits = 0;              // bits of the largest cell key
+  int64_t ncells = 0;            // bins * cells per bin
+  int64_t cap_radix = 0;         // points the radix sort buffers hold
+  int64_t cap_count = 0;         // points the counting sort buffers hold
+  int32_t* d_slot = nullptr;     // [M] counting sort: slot within the cell
+  int32_t* d_count = nullptr;    // [ncells + 1] counting sort: points per cell
+  int32_t* d_sstart = nullptr;   // [ncells + 1] counting sort: first position of a cell
+  int32_t* d_cell_scan_tmp = nullptr;   // scan scratch over the cells
+  int last_sort = 0;             // method of the last setpts (2 radix, 3 counting)
   int32_t* d_bcount = nullptr;   // [nbins + 1] points per bin
   int32_t* d_bstart = nullptr;   // [nbins + 1] first sorted position of a bin
   int32_t* d_nsub = nullptr;

@@ -9,6 +9,13 @@
 //   sort      : stable LSD radix sort of the records by key (rocPRIM), so
 //               points of one cell keep their input order.
 //   bounds    : the run of each bin in the sorted keys gives its point count.
+//
+// For small point sets the sort is a counting sort instead (the radix sort's
+// fixed cost dominates there):
+//   bin_count : as sort_keys, and count the point into its cell; the count
+//               before the increment is the point's slot within the cell.
+//   scan      : exclusive prefix sums of the counts = first position of a cell.
+//   scatter   : place point j at start[cell] + slot, storing its record.
 //   scan      : exclusive prefix sums of the bin counts = first position of a bin.
 //   subprob   : split each bin's points into runs of at most maxsub.
 #include <cstring>
@@ -107,6 +114,37 @@ __global__ void sort_keys_kernel(const SortArgs a) {
   write_record(a, j, q, t, j);
 }
 
+template <typename CTy>
+__global__ void bin_count_kernel(const SortArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.M) return;
+  int flag = 0;
+  uint32_t q[3];
+  double t[3];
+  const int key = point_key<CTy>(a, j, &flag, q, t);
+  if (flag) atomicOr(a.flags, flag);
+  a.key[j] = (uint32_t)key;
+  a.slot[j] = atomicAdd(&a.count[key], 1);
+}
+
+template <typename CTy>
+__global__ void scatter_kernel(const SortArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.M) return;
+  int flag = 0;
+  uint32_t q[3];
+  double t[3];
+  point_key<CTy>(a, j, &flag, q, t);
+  const int64_t pos = (int64_t)a.sstart[a.key[j]] + a.slot[j];
+  write_record(a, pos, q, t, j);
+}
+
+__global__ void bin_starts_kernel(const int32_t* __restrict__ sstart, int64_t cpb, int64_t nbins,
+                                  int32_t* __restrict__ bstart) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= nbins) bstart[b] = sstart[b * cpb];
+}
+
 __global__ void bin_bounds_kernel(const uint32_t* __restrict__ skey, int64_t M, uint32_t cpb,
                                   int32_t* __restrict__ bcount) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,6 +214,31 @@ hipError_t sort_records(uint32_t* key[2], unsigned char* rec[2], int* sel, int64
   size_t bytes = tmp_bytes;
   return rec_bytes == 16 ? sort_records_t<Rec16>(key, rec, sel, M, key_bits, tmp, &bytes, s)
                          : sort_records_t<Rec32>(key, rec, sel, M, key_bits, tmp, &bytes, s);
+}
+
+hipError_t launch_bin_count(const SortArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.coord_prec == ESN_SINGLE)
+    hipLaunchKernelGGL(bin_count_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(bin_count_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const SortArgs& a, hipStream_t s) {
+  if (a.M <= 0) return hipSuccess;
+  if (a.coord_prec == ESN_SINGLE)
+    hipLaunchKernelGGL(scatter_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(scatter_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_starts(const int32_t* sstart, int64_t cpb, int64_t nbins, int32_t* bstart,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(bin_starts_kernel, dim3(nblocks(nbins + 1, 256)), dim3(256), 0, s, sstart,
+                     cpb, nbins, bstart);
+  return hipGetLastError();
 }
 
 hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,

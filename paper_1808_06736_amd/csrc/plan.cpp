@@ -114,8 +114,9 @@ void free_points(esn_plan_s* p) {
   dfree(p, (void**)&p->d_rec0);
   for (int k = 0; k < 2; k++) dfree(p, (void**)&p->d_key[k]);
   dfree(p, &p->d_sort_tmp);
+  dfree(p, (void**)&p->d_slot);
   p->sort_tmp = 0;
-  p->cap_M = 0;
+  p->cap_M = p->cap_radix = p->cap_count = 0;
 }
 
 void free_subs(esn_plan_s* p) {
@@ -135,6 +136,9 @@ void destroy_all(esn_plan_s* p) {
   dfree(p, &p->d_grid);
   dfree(p, (void**)&p->d_bcount);
   dfree(p, (void**)&p->d_bstart);
+  dfree(p, (void**)&p->d_count);
+  dfree(p, (void**)&p->d_sstart);
+  dfree(p, (void**)&p->d_cell_scan_tmp);
   dfree(p, (void**)&p->d_nsub);
   dfree(p, (void**)&p->d_subofs);
   dfree(p, (void**)&p->d_scan_tmp);
@@ -198,7 +202,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
   if (o.bin[0] < 0 || o.bin[1] < 0 || o.bin[2] < 0 || o.maxsubprob < 0 ||
       o.ntransf_chunk < 0 || o.block < 0 || o.block > 1024 ||
       (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 3 ||
-      o.interp_method < 0 || o.interp_method > 3)
+      o.interp_method < 0 || o.interp_method > 3 || o.sort < 0 || o.sort > 3)
     return ESN_ERR_BAD_ARG;
 
   esn_plan_s* p = new (std::nothrow) esn_plan_s();
@@ -361,6 +365,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
     const int64_t ncells = p->nbins * cpb;
     if (ncells + 1 > (int64_t)1 << 31) return fail(ESN_ERR_BAD_ARG);
+    p->ncells = ncells;
     p->key_bits = 0;
     while (((int64_t)1 << p->key_bits) < ncells) p->key_bits++;
     const int64_t nscan = p->nbins + 1;
@@ -393,18 +398,43 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   hipStream_t s = p->stream;
   p->M = -1;
   if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+  // bin sort method: the radix sort's fixed cost dominates for small point
+  // sets, the counting sort's scattered atomics for large ones
+  int method = 0;
+  if (p->opts.sort == 1)
+    method = (M < ((int64_t)1 << 21) && p->ncells < ((int64_t)1 << 23)) ? 3 : 2;
+  else if (p->opts.sort >= 2)
+    method = p->opts.sort;
+  const size_t rbytes = (size_t)pts_record_bytes(p->pts_code);
   if (M > p->cap_M) {
     free_points(p);
-    const size_t rb = (size_t)pts_record_bytes(p->pts_code) * M;
-    if (dalloc(p, (void**)&p->d_pts, rb)) return ESN_ERR_ALLOC;
-    if (p->opts.sort) {
-      p->sort_tmp = sort_tmp_bytes(M, p->key_bits, pts_record_bytes(p->pts_code));
-      if (dalloc(p, (void**)&p->d_rec0, rb) || dalloc(p, (void**)&p->d_key[0], 4 * M) ||
-          dalloc(p, (void**)&p->d_key[1], 4 * M) ||
-          dalloc(p, &p->d_sort_tmp, std::max<size_t>(p->sort_tmp, 256)))
+    if (dalloc(p, (void**)&p->d_pts, rbytes * M) || dalloc(p, (void**)&p->d_key[0], 4 * M))
+      return ESN_ERR_ALLOC;
+    p->cap_M = M;
+  }
+  if (method == 2 && M > p->cap_radix) {
+    dfree(p, (void**)&p->d_rec0);
+    dfree(p, (void**)&p->d_key[1]);
+    dfree(p, &p->d_sort_tmp);
+    p->sort_tmp = sort_tmp_bytes(p->cap_M, p->key_bits, (int)rbytes);
+    if (dalloc(p, (void**)&p->d_rec0, rbytes * p->cap_M) ||
+        dalloc(p, (void**)&p->d_key[1], 4 * p->cap_M) ||
+        dalloc(p, &p->d_sort_tmp, std::max<size_t>(p->sort_tmp, 256)))
+      return ESN_ERR_ALLOC;
+    p->cap_radix = p->cap_M;
+  }
+  if (method == 3) {
+    if (!p->d_count) {
+      if (dalloc(p, (void**)&p->d_count, 4 * (p->ncells + 1)) ||
+          dalloc(p, (void**)&p->d_sstart, 4 * (p->ncells + 1)) ||
+          dalloc(p, (void**)&p->d_cell_scan_tmp, 4 * (scan_tmp_elems(p->ncells + 1) + 1)))
         return ESN_ERR_ALLOC;
     }
-    p->cap_M = M;
+    if (M > p->cap_count) {
+      dfree(p, (void**)&p->d_slot);
+      if (dalloc(p, (void**)&p->d_slot, 4 * p->cap_M)) return ESN_ERR_ALLOC;
+      p->cap_count = p->cap_M;
+    }
   }
   SortArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -421,23 +451,35 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
   a.key = p->d_key[0];
-  a.pts = p->opts.sort ? p->d_rec0 : p->d_pts;
+  a.slot = p->d_slot;
+  a.count = p->d_count;
+  a.sstart = p->d_sstart;
+  a.pts = method == 2 ? p->d_rec0 : p->d_pts;
   a.flags = p->d_flags;
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
   int nsub = 0;
   const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
-  if (p->opts.sort) {
+  p->last_sort = method;
+  if (method == 2) {
     ESN_HIP(hipMemsetAsync(p->d_bcount, 0, 4 * (p->nbins + 1), s));
     ESN_HIP(launch_sort_keys(a, s));
     int sel = 0;
     unsigned char* recs[2] = {p->d_rec0, p->d_pts};
-    ESN_HIP(sort_records(p->d_key, recs, &sel, M, p->key_bits, pts_record_bytes(p->pts_code),
-                         p->d_sort_tmp, p->sort_tmp, s));
+    ESN_HIP(sort_records(p->d_key, recs, &sel, M, p->key_bits, (int)rbytes, p->d_sort_tmp,
+                         p->sort_tmp, s));
     // the sorted records are the plan's points; the other buffer is scratch
     p->d_pts = recs[sel];
     p->d_rec0 = recs[1 - sel];
     ESN_HIP(launch_bin_bounds(p->d_key[sel], M, (int)cpb, p->d_bcount, s));
     ESN_HIP(exclusive_scan_i32(p->d_bcount, p->d_bstart, p->nbins + 1, p->d_scan_tmp, s));
+  } else if (method == 3) {
+    ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * (p->ncells + 1), s));
+    ESN_HIP(launch_bin_count(a, s));
+    ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_cell_scan_tmp, s));
+    ESN_HIP(launch_scatter(a, s));
+    ESN_HIP(launch_bin_starts(p->d_sstart, cpb, p->nbins, p->d_bstart, s));
+  }
+  if (method) {
     ESN_HIP(launch_subprob_count(p->d_bstart, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
     ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
     ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
@@ -453,8 +495,8 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   const int flags = p->h_pinned[0];
   if (flags & 1) return ESN_ERR_NAN_PTS;
   if (flags & 2) return ESN_ERR_PTS_OUT_OF_RANGE;
-  p->nbins_nonempty = p->opts.sort ? p->h_pinned[1] : 0;
-  if (p->opts.sort) {
+  p->nbins_nonempty = method ? p->h_pinned[1] : 0;
+  if (method) {
     if (nsub > p->cap_sub) {
       free_subs(p);
       if (dalloc(p, (void**)&p->d_sub_bin, 4 * (size_t)nsub) ||

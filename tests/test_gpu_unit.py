@@ -195,6 +195,29 @@ def test_unsorted_matches_sorted(dim, prec):
     assert O.rel_l2(x, y) < (1e-5 if prec == "f32" else 1e-12)
 
 
+@pytest.mark.parametrize("dim,prec,M", [(2, "f32", 40000), (3, "f32", 300000), (3, "f64", 30000),
+                                        (1, "f64", 20000)])
+def test_sort_methods_agree(dim, prec, M):
+    """Radix sort (stable, records by cell) and counting sort (atomic slots)
+    give the same transforms up to rounding (the order of the points inside
+    a cell, and of the atomic tile add-backs, differs)."""
+    N = (40, 26, 22)[:dim]
+    dt = np.float32 if prec == "f32" else np.float64
+    coords = I.wrapped_gaussian_points(M, dim, 121, 0.3, dt)
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    c = I.complex_normal(M, 122, cdt)
+    f = I.complex_normal(tuple(reversed(N)), 123, cdt)
+    tol = 1e-5 if prec == "f32" else 1e-12
+    r1, _ = run_type1(coords, c, N, 1e-5, prec, sort=2)
+    k1, _ = run_type1(coords, c, N, 1e-5, prec, sort=3)
+    assert O.rel_l2(r1, k1) < tol
+    r2, _ = run_type2(coords, f, N, 1e-5, prec, sort=2)
+    k2, _ = run_type2(coords, f, N, 1e-5, prec, sort=3)
+    assert O.rel_l2(r2, k2) < tol
+    if M * np.prod(N) <= 1e9:
+        assert O.rel_l2(r1, O.type1(coords, c, +1, N=N)) <= 1e-4
+
+
 def test_one_shot_calls_match_plans():
     t = torch()
     M, N = 3000, (20, 18, 16)
