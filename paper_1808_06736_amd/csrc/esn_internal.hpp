@@ -91,6 +91,7 @@ struct SortArgs {
   unsigned char* pts;       // [M] point records (radix sort: input order; counting
                             // sort: sorted; no sort: input order)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
+  int vec4;                 // coordinate arrays aligned for 4-point vector loads
 };
 // Cell key and point record of every point, in input order.
 hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s);
@@ -111,22 +112,26 @@ hipError_t launch_scatter(const SortArgs& a, hipStream_t s);
 // bstart[b] = sstart[b * cpb] for b = 0 .. nbins.
 hipError_t launch_bin_starts(const int32_t* sstart, int64_t cpb, int64_t nbins, int32_t* bstart,
                              hipStream_t s);
-// For every bin b = key / cpb of the sorted keys, bcount[b] += (end - start)
-// of its run (bcount zeroed by the caller, nbins + 1 entries).
-hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,
-                             hipStream_t s);
+// endpos[b] = one past the last sorted position of bin b = key / cpb for each
+// bin with points (endpos zeroed by the caller, nbins entries).
+hipError_t launch_bin_ends(const uint32_t* skey, int64_t M, int cpb, int32_t* endpos,
+                           hipStream_t s);
+// Subproblems of every bin: runs of at most maxsub of its points, in bin order.
+// With endpos (bin ends from launch_bin_ends) the bin starts are written to
+// bstart[0 .. nbins]; without it bstart must hold them.  nsub gets nbins
+// per-bin counts, tiles 3 bin_tiles(nbins) ints of per-tile partials; the
+// sub_* arrays must hold every subproblem (at most min(nbins, M) + M / maxsub).
+// totals[0] = number of subproblems, totals[1] = bins with points.
+int64_t bin_tiles(int64_t nbins);
+hipError_t launch_bin_subproblems(const int32_t* endpos, int32_t* bstart, int64_t nbins,
+                                  int64_t M, int maxsub, int32_t* nsub, int32_t* tiles,
+                                  int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
+                                  int32_t* totals, hipStream_t s);
 // Exclusive scan of n int32 values (in -> out, may not alias); tmp must hold
 // scan_tmp_elems(n) int32.
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n,
                               int32_t* tmp, hipStream_t s);
-// Per bin: nsub[b] = ceil(points / maxsub) from the bin starts; *nonempty
-// (device) is incremented per nonempty bin.
-hipError_t launch_subprob_count(const int32_t* bstart, int32_t* nsub, int64_t nbins, int maxsub,
-                                int32_t* nonempty, hipStream_t s);
-hipError_t launch_subprob_fill(const int32_t* bstart, const int32_t* nsub, const int32_t* subofs,
-                               int64_t nbins, int maxsub, int32_t* sub_bin, int32_t* sub_start,
-                               int32_t* sub_len, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
 
 // Spread / interp (kernels_spread.hip, kernels_interp.hip).
@@ -222,11 +227,10 @@ struct esn_plan_s {
   int32_t* d_sstart = nullptr;   // [ncells + 1] counting sort: first position of a cell
   int32_t* d_cell_scan_tmp = nullptr;   // scan scratch over the cells
   int last_sort = 0;             // method of the last setpts (2 radix, 3 counting)
-  int32_t* d_bcount = nullptr;   // [nbins + 1] points per bin
+  int32_t* d_bend = nullptr;     // [nbins] one past a bin's last sorted position (0: empty)
   int32_t* d_bstart = nullptr;   // [nbins + 1] first sorted position of a bin
   int32_t* d_nsub = nullptr;
-  int32_t* d_subofs = nullptr;
-  int32_t* d_scan_tmp = nullptr;
+  int32_t* d_tiles = nullptr;    // [3 bin_tiles(nbins)] per-tile partials
   int32_t* d_flags = nullptr;
   int32_t* d_sub_bin = nullptr;
   int32_t* d_sub_start = nullptr;

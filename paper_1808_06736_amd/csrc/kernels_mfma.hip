@@ -23,10 +23,11 @@
 // only).
 //
 // Interpolation, eq. (interp), runs the same contraction the other way: for
-// the points of one cell, T[p, z] = sum_(x,y) kx_p(x) ky_p(y) B[(x, y), z] on
-// the matrix cores (16 points x 64 footprint cells x 8 planes (re, im)), then
-// c_p = sum_z kz_p(z) T[p, z] by row rotations across lanes, with the bin's
-// grid tile (bin + 7 cells per dim) copied into LDS first.
+// the points of one cell, T[z, p] = sum_(x,y) B[z, (x, y)] kx_p(x) ky_p(y) on
+// the matrix cores (8 planes (re, im) x 64 footprint cells x 16 points), then
+// c_p = sum_z kz_p(z) T[z, p] in registers and across the four lane groups
+// that hold a point's planes, with the bin's grid tile (bin + 7 cells per
+// dim) copied into LDS first.
 #include "device_common.hpp"
 
 namespace esn {
@@ -106,15 +107,6 @@ __device__ __forceinline__ void opaque_s(int& v) { asm volatile("" : "+s"(v)); }
 // Keeps the memory accesses before it ahead of the code after it (a compiler
 // barrier only: no instruction, no wait).
 __device__ __forceinline__ void keep_order() { asm volatile("" ::: "memory"); }
-
-// Sum of v over the 8 lanes of the same parity in each 16-lane row (row
-// rotations by 8, 4 and 2 lanes).
-__device__ __forceinline__ float row_sum_parity(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x124, 0xf, 0xf, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x122, 0xf, 0xf, false));
-  return v;
-}
 
 // Floats per z plane of a bin tile of T0 x T1 complex cells: 2 T0 T1 padded
 // to 8 mod 32, so that the 8 planes a wave touches at once start in distinct
@@ -500,7 +492,7 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       const int col = scol[q0];
       const int lx = col % b0, ly = col / b0;
       const int zrel = szr[q0];          // first window plane of the cell, in the tile
-      // B operand of the run: footprint cell (x, y) = (4 (s & 1) + kq, s >> 1), plane n >> 1
+      // grid operand of the run: footprint cell (x, y) = (4 (s & 1) + kq, s >> 1), plane n >> 1
       float bop[16];
 #pragma unroll
       for (int s = 0; s < 16; s++) {
@@ -518,14 +510,43 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
         kya_n = *reinterpret_cast<const float4*>(sky + qs * 8);
         kyb_n = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
       }
+      // The products run transposed, T^T[(z, re/im), p] = sum_(x,y) G[(x,y), (z, re/im)]
+      // kx_p ky_p, so that lane (kq, n) ends with point q + n's sums over planes
+      // 2 kq and 2 kq + 1.  A step's z weighting and cross-lane sum are done in
+      // the next step, behind its matrix work.
+      v4f tp = v4f{0.f, 0.f, 0.f, 0.f};
+      float2 kzp = make_float2(0.f, 0.f);
+      int qp = q0 - 16;   // the pending step (none before the first)
+      auto finish = [&](const v4f& t, float2 kz, int qb) {
+        const float re = fmaf(kz.y, t[2], kz.x * t[0]);
+        const float im = fmaf(kz.y, t[3], kz.x * t[1]);
+        // lanes 32..63 of re <-> lanes 0..31 of im: the lower half then sums
+        // re over lane groups (0, 2) and (1, 3), the upper half im
+        const auto h = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, re),
+                                                        __builtin_bit_cast(unsigned, im), false,
+                                                        false);
+        // (elements copied out first: a bit cast taken straight from a vector
+        // element reads element 0)
+        const unsigned h0 = h[0], h1 = h[1];
+        const float u = __builtin_bit_cast(float, h0) + __builtin_bit_cast(float, h1);
+        // odd rows <-> even rows: every row then holds the sum of its row pair
+        const auto g2 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, u),
+                                                         __builtin_bit_cast(unsigned, u), false,
+                                                         false);
+        const unsigned g0 = g2[0], g1 = g2[1];
+        const float v = __builtin_bit_cast(float, g0) + __builtin_bit_cast(float, g1);
+        const int pt = qb + n;
+        // row 0 stores re, row 2 im
+        if ((kq & 1) == 0 && pt >= q0 && pt < q1)
+          reinterpret_cast<float*>(sout)[2 * pt + (kq >> 1)] = v;
+      };
       for (int q = q0; q < q1; q += 16) {
-        const float valid = q + n < q1 ? 1.f : 0.f;   // this lane's point (MFMA row)
+        const int pq = q + n;   // this lane's point (MFMA column)
+        const float valid = pq < q1 ? 1.f : 0.f;
         const float kxa = kxa_n * valid, kxb = kxb_n * valid;
         const float ky[8] = {kya_n.x, kya_n.y, kya_n.z, kya_n.w, kyb_n.x, kyb_n.y, kyb_n.z, kyb_n.w};
-        // z weights of the 4 result rows of this lane
-        float kz[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) kz[i] = skz[min(q + 4 * kq + i, q1 - 1) * 8 + (n >> 1)];
+        // z weights of this lane's point at planes 2 kq, 2 kq + 1
+        const float2 kz2 = *reinterpret_cast<const float2*>(skz + min(pq, q1 - 1) * 8 + 2 * kq);
         {
           int qs = min(q + 16 + n, q1 - 1);
           opaque(qs);
@@ -539,17 +560,15 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
         v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 16; s += 2) {
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(kxa * ky[s >> 1], bop[s], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(kxb * ky[s >> 1], bop[s + 1], acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s], kxa * ky[s >> 1], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s + 1], kxb * ky[s >> 1], acc1, 0, 0, 0);
         }
-        // acc[i] = T[point q + 4 kq + i][column n]: weight by kz and sum the columns
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int pt = q + 4 * kq + i;
-          const float v = row_sum_parity((acc0[i] + acc1[i]) * kz[i]);
-          if (pt < q1 && n < 2) reinterpret_cast<float*>(sout)[2 * pt + n] = v;
-        }
+        finish(tp, kzp, qp);
+        tp = acc0 + acc1;
+        kzp = kz2;
+        qp = q;
       }
+      finish(tp, kzp, qp);
     }
     __syncthreads();
     if (tid < nbatch) c[sperm[tid]] = sout[tid];

@@ -8,7 +8,8 @@
 //               3D, every column of a bin) is a run of keys.
 //   sort      : stable LSD radix sort of the records by key (rocPRIM), so
 //               points of one cell keep their input order.
-//   bounds    : the run of each bin in the sorted keys gives its point count.
+//   ends      : where the sorted keys move on to another bin gives that bin's
+//               end; the bins' starts follow by a running maximum.
 //
 // For small point sets the sort is a counting sort instead (the radix sort's
 // fixed cost dominates there):
@@ -16,8 +17,9 @@
 //               before the increment is the point's slot within the cell.
 //   scan      : exclusive prefix sums of the counts = first position of a cell.
 //   scatter   : place point j at start[cell] + slot, storing its record.
-//   scan      : exclusive prefix sums of the bin counts = first position of a bin.
-//   subprob   : split each bin's points into runs of at most maxsub.
+//   starts    : a bin starts where its first cell starts.
+// Both then split each bin's points into runs of at most maxsub (subproblems),
+// by tiles of bins: counts per tile, then offsets from the tiles before.
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -43,10 +45,13 @@ __device__ __forceinline__ double fold_rescale(double x, int64_t n) {
 __device__ __forceinline__ int encode_t(double t, int64_t n, int code, int fbits,
                                         uint32_t* q_out, double* t_out) {
   if (code == kPtsFixed32) {
-    const uint64_t span = (uint64_t)n << fbits;
-    uint64_t q = (uint64_t)llrint(ldexp(t, fbits));
-    if (q >= span) q -= span;
-    *q_out = (uint32_t)q;
+    // n 2^fbits <= 2^32, so the rounded value (ties to even) is an exact
+    // integer below 2^32 once a round-up to the period is wrapped
+    const double span = ldexp((double)n, fbits);
+    double v = rint(ldexp(t, fbits));
+    if (v >= span) v -= span;
+    const uint32_t q = (uint32_t)v;
+    *q_out = q;
     return (int)(q >> fbits);
   }
   *t_out = t;
@@ -58,13 +63,15 @@ __device__ __forceinline__ double load_coord(const void* p, int64_t j) {
   return (double)static_cast<const CTy*>(p)[j];
 }
 
-// Cell key of point j (see SortArgs); also returns the encoded coordinates.
-template <typename CTy>
-__device__ __forceinline__ int point_key(const SortArgs& a, int64_t j, int* flag, uint32_t* q,
-                                         double* t) {
+// Cell key of a point with coordinates xs[0 .. dim-1] (see SortArgs); also
+// returns the encoded coordinates.
+__device__ __forceinline__ int point_key_of(const SortArgs& a, const double* xs, int* flag,
+                                            uint32_t* q, double* t) {
   int cell[3] = {0, 0, 0};
-  for (int m = 0; m < a.dim; m++) {
-    const double x = load_coord<CTy>(a.x[m], j);
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    if (m >= a.dim) break;
+    const double x = xs[m];
     if (!isfinite(x)) *flag |= 1;
     else if (a.chkbnds && fabs(x) > kThreePi) *flag |= 2;
     const double tt = isfinite(x) ? fold_rescale(x, a.n[m]) : 0.0;
@@ -78,6 +85,17 @@ __device__ __forceinline__ int point_key(const SortArgs& a, int64_t j, int* flag
   if (a.dim == 3) local = lz + a.b[2] * (lx + a.b[0] * ly);
   else local = lx + a.b[0] * ly;
   return bin * cpb + local;
+}
+
+// Cell key of point j, loading its coordinates.
+template <typename CTy>
+__device__ __forceinline__ int point_key(const SortArgs& a, int64_t j, int* flag, uint32_t* q,
+                                         double* t) {
+  double xs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < 3; m++)
+    if (m < a.dim) xs[m] = load_coord<CTy>(a.x[m], j);
+  return point_key_of(a, xs, flag, q, t);
 }
 
 // Store sorted point pos: coordinates (unused dims 0) and original index j,
@@ -101,17 +119,46 @@ __device__ __forceinline__ void write_record(const SortArgs& a, int64_t pos, con
   }
 }
 
+// Four consecutive points per thread: their coordinates come in one 16- or
+// 32-byte load per dimension and their keys go out in one 16-byte store
+// (a.vec4: every coordinate array is 16-byte aligned (32 for FP64); the last
+// partial group takes the scalar path).
 template <typename CTy>
 __global__ void sort_keys_kernel(const SortArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.M) return;
+  const int64_t j0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (j0 >= a.M) return;
   int flag = 0;
   uint32_t q[3];
   double t[3];
-  const int key = point_key<CTy>(a, j, &flag, q, t);
+  if (a.vec4 && j0 + 4 <= a.M) {
+    double xs[4][3] = {};
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+      if (m >= a.dim) break;
+      const CTy* src = static_cast<const CTy*>(a.x[m]) + j0;
+      if constexpr (sizeof(CTy) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        xs[0][m] = v.x; xs[1][m] = v.y; xs[2][m] = v.z; xs[3][m] = v.w;
+      } else {
+        const double2 v0 = reinterpret_cast<const double2*>(src)[0];
+        const double2 v1 = reinterpret_cast<const double2*>(src)[1];
+        xs[0][m] = v0.x; xs[1][m] = v0.y; xs[2][m] = v1.x; xs[3][m] = v1.y;
+      }
+    }
+    uint32_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      k[u] = (uint32_t)point_key_of(a, xs[u], &flag, q, t);
+      write_record(a, j0 + u, q, t, j0 + u);
+    }
+    *reinterpret_cast<uint4*>(a.key + j0) = make_uint4(k[0], k[1], k[2], k[3]);
+  } else {
+    for (int64_t j = j0; j < j0 + 4 && j < a.M; j++) {
+      a.key[j] = (uint32_t)point_key<CTy>(a, j, &flag, q, t);
+      write_record(a, j, q, t, j);
+    }
+  }
   if (flag) atomicOr(a.flags, flag);
-  a.key[j] = (uint32_t)key;
-  write_record(a, j, q, t, j);
 }
 
 template <typename CTy>
@@ -145,15 +192,25 @@ __global__ void bin_starts_kernel(const int32_t* __restrict__ sstart, int64_t cp
   if (b <= nbins) bstart[b] = sstart[b * cpb];
 }
 
-__global__ void bin_bounds_kernel(const uint32_t* __restrict__ skey, int64_t M, uint32_t cpb,
-                                  int32_t* __restrict__ bcount) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  // bin b occupies sorted positions [start, end): add end at its last
-  // position and subtract start at its first, so bcount[b] = end - start
-  const uint32_t b = skey[i] / cpb;
-  if (i == 0 || skey[i - 1] / cpb != b) atomicSub(&bcount[b], (int32_t)i);
-  if (i == M - 1 || skey[i + 1] / cpb != b) atomicAdd(&bcount[b], (int32_t)(i + 1));
+// endpos[b] = one past the last sorted position of bin b = key / cpb, for every
+// bin that holds points (empty bins keep the caller's zeros).  Four keys per
+// thread; the key after them decides whether the last one ends its bin.
+__global__ void bin_ends_kernel(const uint32_t* __restrict__ skey, int64_t M, uint32_t cpb,
+                                int32_t* __restrict__ endpos) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= M) return;
+  uint32_t b[5];
+  if (i0 + 4 < M) {
+    const uint4 v = *reinterpret_cast<const uint4*>(skey + i0);   // i0 is a multiple of 4
+    b[0] = v.x / cpb; b[1] = v.y / cpb; b[2] = v.z / cpb; b[3] = v.w / cpb;
+    b[4] = skey[i0 + 4] / cpb;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 5; u++) b[u] = i0 + u < M ? skey[i0 + u] / cpb : 0xffffffffu;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; u++)
+    if (i0 + u < M && b[u + 1] != b[u]) endpos[b[u]] = (int32_t)(i0 + u + 1);
 }
 
 template <typename CTy>
@@ -172,10 +229,11 @@ static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s) {
   if (a.M <= 0) return hipSuccess;
+  const unsigned nb = nblocks((a.M + 3) / 4, 256);
   if (a.coord_prec == ESN_SINGLE)
-    hipLaunchKernelGGL(sort_keys_kernel<float>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sort_keys_kernel<float>, dim3(nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(sort_keys_kernel<double>, dim3(nblocks(a.M, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sort_keys_kernel<double>, dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -241,11 +299,11 @@ hipError_t launch_bin_starts(const int32_t* sstart, int64_t cpb, int64_t nbins, 
   return hipGetLastError();
 }
 
-hipError_t launch_bin_bounds(const uint32_t* skey, int64_t M, int cpb, int32_t* bcount,
-                             hipStream_t s) {
+hipError_t launch_bin_ends(const uint32_t* skey, int64_t M, int cpb, int32_t* endpos,
+                           hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_bounds_kernel, dim3(nblocks(M, 256)), dim3(256), 0, s, skey, M,
-                     (uint32_t)cpb, bcount);
+  hipLaunchKernelGGL(bin_ends_kernel, dim3(nblocks((M + 3) / 4, 256)), dim3(256), 0, s, skey, M,
+                     (uint32_t)cpb, endpos);
   return hipGetLastError();
 }
 
@@ -340,54 +398,179 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_
   return hipGetLastError();
 }
 
-// ---- subproblems ----
-__global__ void subprob_count_kernel(const int32_t* __restrict__ bstart,
-                                     int32_t* __restrict__ nsub, int64_t nbins, int maxsub,
-                                     int32_t* nonempty) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const int cnt = bstart[b + 1] - bstart[b];
-  nsub[b] = (cnt + maxsub - 1) / maxsub;
-  if (cnt > 0) atomicAdd(nonempty, 1);
+// ---- bins and subproblems by tiles of kBinTile bins (one block each) ----
+constexpr int kBinBS = 256;
+constexpr int kBinIPT = 8;
+constexpr int kBinTile = kBinBS * kBinIPT;
+
+int64_t bin_tiles(int64_t nbins) { return (nbins + kBinTile - 1) / kBinTile; }
+
+struct OpMax {
+  __device__ static int32_t id() { return 0; }
+  __device__ static int32_t op(int32_t a, int32_t b) { return max(a, b); }
+};
+struct OpSum {
+  __device__ static int32_t id() { return 0; }
+  __device__ static int32_t op(int32_t a, int32_t b) { return a + b; }
+};
+
+// Exclusive scan of one value per thread over the block (kBinBS threads);
+// *total gets the whole block's reduction.
+template <typename Op>
+__device__ int32_t block_exclusive(int32_t v, int32_t* sh, int32_t* total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kBinBS; off <<= 1) {
+    const int32_t o = tid >= off ? sh[tid - off] : Op::id();
+    __syncthreads();
+    sh[tid] = Op::op(sh[tid], o);
+    __syncthreads();
+  }
+  const int32_t incl = sh[tid];
+  *total = sh[kBinBS - 1];
+  const int32_t excl = tid > 0 ? sh[tid - 1] : Op::id();
+  __syncthreads();
+  return excl;
 }
 
-__global__ void subprob_fill_kernel(const int32_t* __restrict__ bstart,
-                                    const int32_t* __restrict__ nsub,
-                                    const int32_t* __restrict__ subofs, int64_t nbins,
-                                    int maxsub, int32_t* __restrict__ sub_bin,
-                                    int32_t* __restrict__ sub_start,
-                                    int32_t* __restrict__ sub_len) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const int ns = nsub[b];
-  const int o = subofs[b];
-  const int st = bstart[b];
-  const int cnt = bstart[b + 1] - st;
-  for (int k = 0; k < ns; k++) {
-    sub_bin[o + k] = (int32_t)b;
-    sub_start[o + k] = st + k * maxsub;
-    sub_len[o + k] = min(maxsub, cnt - k * maxsub);
+// Reduction of v[0 .. n-1] by the whole block (every thread gets the result).
+template <typename Op>
+__device__ int32_t block_reduce_prefix(const int32_t* __restrict__ v, int64_t n, int32_t* sh) {
+  int32_t r = Op::id();
+  for (int64_t i = threadIdx.x; i < n; i += kBinBS) r = Op::op(r, v[i]);
+  int32_t total;
+  block_exclusive<Op>(r, sh, &total);
+  return total;
+}
+
+// Pass 1 (radix sort): the largest bin end in each tile.
+__global__ void __launch_bounds__(kBinBS)
+bin_tile_max_kernel(const int32_t* __restrict__ endpos, int64_t nbins, int32_t* __restrict__ tmax) {
+  __shared__ int32_t sh[kBinBS];
+  const int64_t b0 = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinIPT;
+  int32_t m = 0;
+  for (int u = 0; u < kBinIPT; u++)
+    if (b0 + u < nbins) m = max(m, endpos[b0 + u]);
+  int32_t total;
+  block_exclusive<OpMax>(m, sh, &total);
+  if (threadIdx.x == 0) tmax[blockIdx.x] = total;
+}
+
+// Pass 2: bin starts and subproblem counts per tile.  From the bin ends (radix
+// sort) a bin's points follow those of every earlier bin, so its start is the
+// largest end before it; from the bin starts (counting sort) the count is the
+// difference of consecutive starts.
+__global__ void __launch_bounds__(kBinBS)
+bin_tile_count_kernel(const int32_t* __restrict__ endpos, int32_t* __restrict__ bstart,
+                      int64_t nbins, int64_t M, int maxsub, const int32_t* __restrict__ tmax,
+                      int32_t* __restrict__ nsub, int32_t* __restrict__ tsub,
+                      int32_t* __restrict__ tnonempty) {
+  __shared__ int32_t sh[kBinBS];
+  const int64_t b0 = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinIPT;
+  int32_t cnt[kBinIPT];
+  if (endpos) {
+    const int32_t carry = block_reduce_prefix<OpMax>(tmax, blockIdx.x, sh);
+    int32_t e[kBinIPT], m = 0;
+    for (int u = 0; u < kBinIPT; u++) {
+      e[u] = b0 + u < nbins ? endpos[b0 + u] : 0;
+      m = max(m, e[u]);
+    }
+    int32_t total;
+    int32_t run = max(carry, block_exclusive<OpMax>(m, sh, &total));
+    for (int u = 0; u < kBinIPT; u++) {
+      if (b0 + u < nbins) bstart[b0 + u] = run;
+      cnt[u] = e[u] > 0 ? e[u] - run : 0;
+      run = max(run, e[u]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) bstart[nbins] = (int32_t)M;
+  } else {
+    for (int u = 0; u < kBinIPT; u++)
+      cnt[u] = b0 + u < nbins ? bstart[b0 + u + 1] - bstart[b0 + u] : 0;
+  }
+  int32_t ns = 0, ne = 0;
+  for (int u = 0; u < kBinIPT; u++) {
+    const int32_t k = (cnt[u] + maxsub - 1) / maxsub;
+    if (b0 + u < nbins) nsub[b0 + u] = k;
+    ns += k;
+    ne += cnt[u] > 0;
+  }
+  int32_t t1, t2;
+  block_exclusive<OpSum>(ns, sh, &t1);
+  block_exclusive<OpSum>(ne, sh, &t2);
+  if (threadIdx.x == 0) {
+    tsub[blockIdx.x] = t1;
+    tnonempty[blockIdx.x] = t2;
   }
 }
 
+// Pass 3: each bin's subproblems {bin, first sorted position, length} at the
+// number of subproblems of the bins before it.  The last tile writes the
+// totals: totals[0] = subproblems, totals[1] = bins with points.
+__global__ void __launch_bounds__(kBinBS)
+bin_tile_fill_kernel(const int32_t* __restrict__ bstart, const int32_t* __restrict__ nsub,
+                     int64_t nbins, int maxsub, const int32_t* __restrict__ tsub,
+                     const int32_t* __restrict__ tnonempty, int32_t* __restrict__ sub_bin,
+                     int32_t* __restrict__ sub_start, int32_t* __restrict__ sub_len,
+                     int32_t* __restrict__ totals) {
+  __shared__ int32_t sh[kBinBS];
+  const int64_t b0 = (int64_t)blockIdx.x * kBinTile + (int64_t)threadIdx.x * kBinIPT;
+  const int32_t carry = block_reduce_prefix<OpSum>(tsub, blockIdx.x, sh);
+  int32_t k[kBinIPT], m = 0;
+  for (int u = 0; u < kBinIPT; u++) {
+    k[u] = b0 + u < nbins ? nsub[b0 + u] : 0;
+    m += k[u];
+  }
+  int32_t total;
+  int32_t o = carry + block_exclusive<OpSum>(m, sh, &total);
+  for (int u = 0; u < kBinIPT; u++) {
+    if (k[u] > 0) {
+      const int32_t st = bstart[b0 + u];
+      const int32_t cnt = bstart[b0 + u + 1] - st;
+      for (int j = 0; j < k[u]; j++) {
+        sub_bin[o + j] = (int32_t)(b0 + u);
+        sub_start[o + j] = st + j * maxsub;
+        sub_len[o + j] = min(maxsub, cnt - j * maxsub);
+      }
+    }
+    o += k[u];
+  }
+  if (blockIdx.x == gridDim.x - 1) {
+    const int32_t ne = block_reduce_prefix<OpSum>(tnonempty, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      totals[0] = carry + total;
+      totals[1] = ne;
+    }
+  }
+}
+
+hipError_t launch_bin_subproblems(const int32_t* endpos, int32_t* bstart, int64_t nbins,
+                                  int64_t M, int maxsub, int32_t* nsub, int32_t* tiles,
+                                  int32_t* sub_bin, int32_t* sub_start, int32_t* sub_len,
+                                  int32_t* totals, hipStream_t s) {
+  const int64_t nt = bin_tiles(nbins);
+  int32_t* tmax = tiles;
+  int32_t* tsub = tiles + nt;
+  int32_t* tne = tiles + 2 * nt;
+  if (endpos) {
+    hipLaunchKernelGGL(bin_tile_max_kernel, dim3((unsigned)nt), dim3(kBinBS), 0, s, endpos, nbins,
+                       tmax);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(bin_tile_count_kernel, dim3((unsigned)nt), dim3(kBinBS), 0, s, endpos, bstart,
+                     nbins, M, maxsub, tmax, nsub, tsub, tne);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bin_tile_fill_kernel, dim3((unsigned)nt), dim3(kBinBS), 0, s, bstart, nsub,
+                     nbins, maxsub, tsub, tne, sub_bin, sub_start, sub_len, totals);
+  return hipGetLastError();
+}
+
+// ---- subproblems ----
 __global__ void iota_kernel(int32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (int32_t)i;
-}
-
-hipError_t launch_subprob_count(const int32_t* bstart, int32_t* nsub, int64_t nbins, int maxsub,
-                                int32_t* nonempty, hipStream_t s) {
-  hipLaunchKernelGGL(subprob_count_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, bstart,
-                     nsub, nbins, maxsub, nonempty);
-  return hipGetLastError();
-}
-
-hipError_t launch_subprob_fill(const int32_t* bstart, const int32_t* nsub, const int32_t* subofs,
-                               int64_t nbins, int maxsub, int32_t* sub_bin, int32_t* sub_start,
-                               int32_t* sub_len, hipStream_t s) {
-  hipLaunchKernelGGL(subprob_fill_kernel, dim3(nblocks(nbins, 256)), dim3(256), 0, s, bstart,
-                     nsub, subofs, nbins, maxsub, sub_bin, sub_start, sub_len);
-  return hipGetLastError();
 }
 
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s) {

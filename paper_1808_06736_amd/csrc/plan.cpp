@@ -134,14 +134,13 @@ void destroy_all(esn_plan_s* p) {
   free_subs(p);
   for (int m = 0; m < 3; m++) dfree(p, (void**)&p->d_pf[m]);
   dfree(p, &p->d_grid);
-  dfree(p, (void**)&p->d_bcount);
+  dfree(p, (void**)&p->d_bend);
   dfree(p, (void**)&p->d_bstart);
   dfree(p, (void**)&p->d_count);
   dfree(p, (void**)&p->d_sstart);
   dfree(p, (void**)&p->d_cell_scan_tmp);
   dfree(p, (void**)&p->d_nsub);
-  dfree(p, (void**)&p->d_subofs);
-  dfree(p, (void**)&p->d_scan_tmp);
+  dfree(p, (void**)&p->d_tiles);
   dfree(p, (void**)&p->d_flags);
   if (p->h_pinned) (void)hipHostFree(p->h_pinned);
   p->h_pinned = nullptr;
@@ -368,11 +367,10 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     p->ncells = ncells;
     p->key_bits = 0;
     while (((int64_t)1 << p->key_bits) < ncells) p->key_bits++;
-    const int64_t nscan = p->nbins + 1;
-    if (dalloc(p, (void**)&p->d_bcount, 4 * (p->nbins + 1)) ||
+    if (dalloc(p, (void**)&p->d_bend, 4 * p->nbins) ||
         dalloc(p, (void**)&p->d_bstart, 4 * (p->nbins + 1)) ||
-        dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) || dalloc(p, (void**)&p->d_subofs, 4 * p->nbins) ||
-        dalloc(p, (void**)&p->d_scan_tmp, 4 * (scan_tmp_elems(nscan) + 1)) ||
+        dalloc(p, (void**)&p->d_nsub, 4 * p->nbins) ||
+        dalloc(p, (void**)&p->d_tiles, 4 * 3 * bin_tiles(p->nbins)) ||
         dalloc(p, (void**)&p->d_flags, 4 * 4))
       return fail(ESN_ERR_ALLOC);
   }
@@ -456,12 +454,31 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   a.sstart = p->d_sstart;
   a.pts = method == 2 ? p->d_rec0 : p->d_pts;
   a.flags = p->d_flags;
+  {
+    // 4-point vector loads need every coordinate array aligned to 4 values
+    const uintptr_t al = coord_prec == ESN_SINGLE ? 16 : 32;
+    a.vec4 = 1;
+    for (int m = 0; m < p->dim; m++)
+      if (reinterpret_cast<uintptr_t>(xs[m]) % al) a.vec4 = 0;
+  }
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
   int nsub = 0;
   const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
   p->last_sort = method;
+  if (method) {
+    // every subproblem list fits min(nbins, M) + M / maxsub entries
+    const int64_t cap = std::min<int64_t>(p->nbins, M) + M / p->maxsub + 1;
+    if (cap > p->cap_sub) {
+      free_subs(p);
+      if (dalloc(p, (void**)&p->d_sub_bin, 4 * (size_t)cap) ||
+          dalloc(p, (void**)&p->d_sub_start, 4 * (size_t)cap) ||
+          dalloc(p, (void**)&p->d_sub_len, 4 * (size_t)cap))
+        return ESN_ERR_ALLOC;
+      p->cap_sub = cap;
+    }
+  }
   if (method == 2) {
-    ESN_HIP(hipMemsetAsync(p->d_bcount, 0, 4 * (p->nbins + 1), s));
+    ESN_HIP(hipMemsetAsync(p->d_bend, 0, 4 * p->nbins, s));
     ESN_HIP(launch_sort_keys(a, s));
     int sel = 0;
     unsigned char* recs[2] = {p->d_rec0, p->d_pts};
@@ -470,43 +487,33 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     // the sorted records are the plan's points; the other buffer is scratch
     p->d_pts = recs[sel];
     p->d_rec0 = recs[1 - sel];
-    ESN_HIP(launch_bin_bounds(p->d_key[sel], M, (int)cpb, p->d_bcount, s));
-    ESN_HIP(exclusive_scan_i32(p->d_bcount, p->d_bstart, p->nbins + 1, p->d_scan_tmp, s));
+    ESN_HIP(launch_bin_ends(p->d_key[sel], M, (int)cpb, p->d_bend, s));
+    ESN_HIP(launch_bin_subproblems(p->d_bend, p->d_bstart, p->nbins, M, p->maxsub, p->d_nsub,
+                                   p->d_tiles, p->d_sub_bin, p->d_sub_start, p->d_sub_len,
+                                   p->d_flags + 1, s));
   } else if (method == 3) {
     ESN_HIP(hipMemsetAsync(p->d_count, 0, 4 * (p->ncells + 1), s));
     ESN_HIP(launch_bin_count(a, s));
     ESN_HIP(exclusive_scan_i32(p->d_count, p->d_sstart, p->ncells + 1, p->d_cell_scan_tmp, s));
     ESN_HIP(launch_scatter(a, s));
     ESN_HIP(launch_bin_starts(p->d_sstart, cpb, p->nbins, p->d_bstart, s));
-  }
-  if (method) {
-    ESN_HIP(launch_subprob_count(p->d_bstart, p->d_nsub, p->nbins, p->maxsub, p->d_flags + 1, s));
-    ESN_HIP(exclusive_scan_i32(p->d_nsub, p->d_subofs, p->nbins, p->d_scan_tmp, s));
-    ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
-    ESN_HIP(hipMemcpyAsync(p->h_pinned + 2, p->d_subofs + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
-    ESN_HIP(hipMemcpyAsync(p->h_pinned + 3, p->d_nsub + (p->nbins - 1), 4, hipMemcpyDeviceToHost, s));
-    ESN_HIP(hipStreamSynchronize(s));
-    nsub = p->h_pinned[2] + p->h_pinned[3];
+    ESN_HIP(launch_bin_subproblems(nullptr, p->d_bstart, p->nbins, M, p->maxsub, p->d_nsub,
+                                   p->d_tiles, p->d_sub_bin, p->d_sub_start, p->d_sub_len,
+                                   p->d_flags + 1, s));
   } else {
     ESN_HIP(launch_encode_unsorted(a, s));
-    ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 8, hipMemcpyDeviceToHost, s));
-    ESN_HIP(hipStreamSynchronize(s));
   }
+  // error flags, subproblem and nonempty-bin totals
+  ESN_HIP(hipMemcpyAsync(p->h_pinned, p->d_flags, 12, hipMemcpyDeviceToHost, s));
+  ESN_HIP(hipStreamSynchronize(s));
   const int flags = p->h_pinned[0];
   if (flags & 1) return ESN_ERR_NAN_PTS;
   if (flags & 2) return ESN_ERR_PTS_OUT_OF_RANGE;
-  p->nbins_nonempty = method ? p->h_pinned[1] : 0;
   if (method) {
-    if (nsub > p->cap_sub) {
-      free_subs(p);
-      if (dalloc(p, (void**)&p->d_sub_bin, 4 * (size_t)nsub) ||
-          dalloc(p, (void**)&p->d_sub_start, 4 * (size_t)nsub) ||
-          dalloc(p, (void**)&p->d_sub_len, 4 * (size_t)nsub))
-        return ESN_ERR_ALLOC;
-      p->cap_sub = nsub;
-    }
-    ESN_HIP(launch_subprob_fill(p->d_bstart, p->d_nsub, p->d_subofs, p->nbins, p->maxsub,
-                                p->d_sub_bin, p->d_sub_start, p->d_sub_len, s));
+    nsub = p->h_pinned[1];
+    p->nbins_nonempty = p->h_pinned[2];
+  } else {
+    p->nbins_nonempty = 0;
   }
   p->nsub = nsub;
   p->M = M;
