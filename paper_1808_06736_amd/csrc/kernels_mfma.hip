@@ -119,11 +119,17 @@ __host__ __device__ inline int plane_floats(int T0, int T1) {
 // that the 4-point steps may read past a run's end without a bound check.
 constexpr int kSpreadStage = 67;
 
+// Rows of staged z weights in the interpolation kernel: a step reads the
+// weights of 16 points from a start of at most 64 (one batch), so reads reach
+// row 79; rows past the batch only feed output columns that are not stored.
+constexpr int kInterpRows = 80;
+
 // LDS layouts.  Both start with the bin tile (bin + 7 cells per dim, planes of
 // plane_floats) and end with the wrapped grid offsets of the tile's z planes
 // (int64), per-point ints and the offsets of the tile's x and y lines.
 // Spreading stages [67][8] x and z weights and [67][16] B operands;
-// interpolation [64][8] x, y and z weights and a float2 result per point.
+// interpolation [64][8] x and y weights, [80][8] z weights and a float2 result
+// per point.
 static inline size_t mfma_tail_bytes(const int* b, int nint) {
   const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
   return T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) + (T0 + T1) * sizeof(int);
@@ -141,8 +147,8 @@ size_t mfma_spread_lds_bytes(int w, const int* b) {
 }
 
 size_t mfma_interp_lds_bytes(const int* b) {
-  return mfma_tile_bytes(b) + 3 * 64 * 8 * sizeof(float) + 64 * sizeof(float2) +
-         mfma_tail_bytes(b, 3);
+  return mfma_tile_bytes(b) + (2 * 64 + kInterpRows) * 8 * sizeof(float) +
+         64 * sizeof(float2) + mfma_tail_bytes(b, 2);
 }
 
 // Fill the wrapped grid offsets of the tile lines whose origin is (ox, oy, oz):
@@ -216,7 +222,9 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
   const int tid = threadIdx.x;
-  const int wv = tid >> 6;
+  // the wave index, known to the compiler as the same across the wave, so that
+  // ballots and run bounds derived from it stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
@@ -249,6 +257,9 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
 
   // add this wave's ring slots in mask fm (block-uniform) into the bin tile and clear them
   auto flush = [&](unsigned fm) {
+    // the accumulators were written by matrix instructions in another block:
+    // 16 wait states cover their latency before vector instructions read them
+    asm volatile("s_nop 15");
 #pragma unroll
     for (int u = 0; u < 2; u++) {
       const int t = 2 * wv + u;
@@ -387,9 +398,32 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   }
 }
 
+// Weights of one coordinate at the 8 footprint slots from its fixed-point
+// value q (fbits fraction bits): the window shift is decided on the exact
+// fraction bits, as everywhere else.
+template <int W>
+__device__ __forceinline__ void slot_weights(uint32_t q, int fbits, float bl, float* v) {
+  const uint32_t fr = q & ((1u << fbits) - 1u);
+  const int sh = (W & 1) ? (fr > (1u << (fbits - 1))) : (fr != 0u);
+  float k[W];
+  es_weights_hw<W>(sh, ldexpf((float)fr, -fbits), bl, k);
+  slots8<W>(k, sh, v);
+}
+
 // Two waves per subproblem share the grid tile and the staged weights: in
 // each batch wave 0 computes the x and y weights and wave 1 the z weights and
-// cells; the waves then take alternate runs.
+// each point's footprint origin in the tile; the waves then take alternate
+// runs (points of one cell).
+//
+// Matrix layout of a step (16 points q .. q + 15 of a run):
+//   A[m][k] = G[x, y, z(m), re/im(m)]   grid tile, m = lane & 15, k = lane >> 4,
+//             x = 4 (s & 1) + k, y = s >> 1 for instruction s = 0 .. 15;
+//             row m holds plane z(m) = (m >> 2) + 4 ((m >> 1) & 1), part m & 1
+//   B[k][n] = kx_p(x) ky_p(y)          point p = q + n
+// so the output row 4 kq + i of lane (kq, n) is plane kq + 4 (i >> 1), part
+// i & 1 of point q + n, and the z weights a lane needs sit at the same slots
+// kq and kq + 4 as its x weights.  Rows past a run (other points, or stale
+// rows) only reach output columns that are not stored.
 template <int W>
 __global__ void __launch_bounds__(128)
 interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __restrict__ c) {
@@ -403,12 +437,11 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   float* gtf = reinterpret_cast<float*>(smem_raw);                 // [T2][ps]: [T1][T0][2]
   float* skx = gtf + T2 * ps;                                      // [64][8] x slots
   float* sky = skx + 64 * 8;                                       // [64][8] y slots
-  float* skz = sky + 64 * 8;                                       // [64][8] z rel. to the cell
-  float2* sout = reinterpret_cast<float2*>(skz + 64 * 8);          // [64] results
+  float* skz = sky + 64 * 8;                                       // [80][8] z slots
+  float2* sout = reinterpret_cast<float2*>(skz + kInterpRows * 8); // [64] results
   int64_t* gz = reinterpret_cast<int64_t*>(sout + 64);             // [T2]
-  int* scol = reinterpret_cast<int*>(gz + T2);                     // [64]
-  int* szr = scol + 64;                                            // [64]
-  int* sperm = szr + 64;                                           // [64]
+  int* sorg = reinterpret_cast<int*>(gz + T2);                     // [64] footprint origin
+  int* sperm = sorg + 64;                                          // [64]
   int* gx = sperm + 64;                                            // [T0]
   int* gy = gx + T0;                                               // [T1]
 
@@ -419,7 +452,9 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int bi0 = bin % g.nb[0], bi1 = (bin / g.nb[0]) % g.nb[1], bi2 = bin / (g.nb[0] * g.nb[1]);
   const int bx0 = bi0 * b0, by0 = bi1 * b1, bz0 = bi2 * b2;
   const int tid = threadIdx.x;
-  const int wv = tid >> 6;
+  // the wave index, known to the compiler as the same across the wave, so that
+  // ballots and run bounds derived from it stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
@@ -452,35 +487,36 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
     }
   }
 
-  const int n = lane & 15;         // MFMA column: plane n >> 1, (re, im) = n & 1
+  const int n = lane & 15;         // MFMA row of A / column of B and of the output
   const int kq = lane >> 4;        // MFMA k lane group
+  // this lane's float offset in the tile for instruction 0 (x = kq, y = 0)
+  const int lane_g = ((n >> 2) + 4 * ((n >> 1) & 1)) * ps + 2 * kq + (n & 1);
   for (int base = p0; base < p1; base += 64) {
     const int nbatch = min(64, p1 - base);
     const uint4 r1 = rec[min(base + 64 + lane, plast)];
     __syncthreads();
     {
-      float k[W], v[8];
-      const int m0 = wv == 0 ? 0 : 2;
-      const int m1 = wv == 0 ? 2 : 3;
-      const uint32_t q[3] = {r0.x, r0.y, r0.z};
-      for (int m = m0; m < m1; m++) {
-        const uint32_t fr = q[m] & ((1u << g.fbits[m]) - 1u);
-        // window shift decided on the exact fraction bits (see decode_coord)
-        const int sh = (W & 1) ? (fr > (1u << (g.fbits[m] - 1))) : (fr != 0u);
-        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[m]), bl, k);
-        slots8<W>(k, sh, v);
-        store8((m == 0 ? skx : m == 1 ? sky : skz) + lane * 8, v);
-      }
-      if (wv == 1) {
-        scol[lane] = ((int)(r0.x >> g.fbits[0]) - bx0) + b0 * ((int)(r0.y >> g.fbits[1]) - by0);
-        szr[lane] = (int)(r0.z >> g.fbits[2]) - bz0;
+      float v[8];
+      if (wv == 0) {
+        slot_weights<W>(r0.x, g.fbits[0], bl, v);
+        store8(skx + lane * 8, v);
+        slot_weights<W>(r0.y, g.fbits[1], bl, v);
+        store8(sky + lane * 8, v);
+      } else {
+        slot_weights<W>(r0.z, g.fbits[2], bl, v);
+        store8(skz + lane * 8, v);
+        // footprint origin of the point's cell: tile cell (lx, ly, lz), since the
+        // tile starts H cells before the bin
+        const int lx = (int)(r0.x >> g.fbits[0]) - bx0;
+        const int ly = (int)(r0.y >> g.fbits[1]) - by0;
+        const int lz = (int)(r0.z >> g.fbits[2]) - bz0;
+        sorg[lane] = lz * ps + 2 * (ly * T0 + lx);
         sperm[lane] = (int)r0.w;
       }
     }
     r0 = r1;
     __syncthreads();
-    const bool starts = lane < nbatch &&
-                        (lane == 0 || szr[lane] != szr[lane - 1] || scol[lane] != scol[lane - 1]);
+    const bool starts = lane < nbatch && (lane == 0 || sorg[lane] != sorg[lane - 1]);
     uint64_t runs = __ballot(starts);
     // this wave takes every other run
     if (wv == 1 && runs) runs &= runs - 1;
@@ -489,37 +525,34 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
       if (runs) runs &= runs - 1;   // skip the other wave's run
-      const int col = scol[q0];
-      const int lx = col % b0, ly = col / b0;
-      const int zrel = szr[q0];          // first window plane of the cell, in the tile
-      // grid operand of the run: footprint cell (x, y) = (4 (s & 1) + kq, s >> 1), plane n >> 1
-      float bop[16];
-#pragma unroll
-      for (int s = 0; s < 16; s++) {
-        const int x = lx + 4 * (s & 1) + kq, y = ly + (s >> 1);
-        bop[s] = gtf[(zrel + (n >> 1)) * ps + 2 * (y * T0 + x) + (n & 1)];
-      }
-      // the x, y weights of each 16-point step are read from LDS one step
-      // ahead (at an index clamped into the run)
-      float kxa_n, kxb_n;
-      float4 kya_n, kyb_n;
+      const int org = __builtin_amdgcn_readfirstlane(sorg[q0]);
+      // grid operand of the run: one address per footprint row y, the x halves
+      // at +8 floats
+      float gop[16];
       {
-        const int qs = min(q0 + n, q1 - 1);
-        kxa_n = skx[qs * 8 + kq];
-        kxb_n = skx[qs * 8 + 4 + kq];
-        kya_n = *reinterpret_cast<const float4*>(sky + qs * 8);
-        kyb_n = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
+        const float* gl = gtf + org + lane_g;
+#pragma unroll
+        for (int y = 0; y < 8; y++) {
+          const float* r = gl + 2 * y * T0;
+          gop[2 * y] = r[0];
+          gop[2 * y + 1] = r[8];
+        }
       }
-      // The products run transposed, T^T[(z, re/im), p] = sum_(x,y) G[(x,y), (z, re/im)]
-      // kx_p ky_p, so that lane (kq, n) ends with point q + n's sums over planes
-      // 2 kq and 2 kq + 1.  A step's z weighting and cross-lane sum are done in
-      // the next step, behind its matrix work.
-      v4f tp = v4f{0.f, 0.f, 0.f, 0.f};
-      float2 kzp = make_float2(0.f, 0.f);
+      // weights of a step's points, read one step ahead (from a start of at
+      // most 64, inside the staged rows)
+      const float* wx = skx + n * 8 + kq;   // + 8 q: x slots kq, kq + 4; z at + 1024
+      const float* wy = sky + n * 8;        // + 8 q: y slots 0 .. 7
+      float kxa_n = wx[8 * q0], kxb_n = wx[8 * q0 + 4];
+      float4 kya_n = *reinterpret_cast<const float4*>(wy + 8 * q0);
+      float4 kyb_n = *reinterpret_cast<const float4*>(wy + 8 * q0 + 4);
+      float kz0_n = wx[8 * q0 + 1024], kz4_n = wx[8 * q0 + 1028];
+      // A step's z-weighted sums are formed right after its products (the
+      // matrix results are read by vector instructions only in the block that
+      // wrote them); their cross-lane reduction and store run in the next
+      // step, behind its matrix work.
+      float rep = 0.f, imp = 0.f;
       int qp = q0 - 16;   // the pending step (none before the first)
-      auto finish = [&](const v4f& t, float2 kz, int qb) {
-        const float re = fmaf(kz.y, t[2], kz.x * t[0]);
-        const float im = fmaf(kz.y, t[3], kz.x * t[1]);
+      auto finish = [&](float re, float im, int qb) {
         // lanes 32..63 of re <-> lanes 0..31 of im: the lower half then sums
         // re over lane groups (0, 2) and (1, 3), the upper half im
         const auto h = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, re),
@@ -541,34 +574,31 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
           reinterpret_cast<float*>(sout)[2 * pt + (kq >> 1)] = v;
       };
       for (int q = q0; q < q1; q += 16) {
-        const int pq = q + n;   // this lane's point (MFMA column)
-        const float valid = pq < q1 ? 1.f : 0.f;
-        const float kxa = kxa_n * valid, kxb = kxb_n * valid;
+        const float kxa = kxa_n, kxb = kxb_n, kz0 = kz0_n, kz4 = kz4_n;
         const float ky[8] = {kya_n.x, kya_n.y, kya_n.z, kya_n.w, kyb_n.x, kyb_n.y, kyb_n.z, kyb_n.w};
-        // z weights of this lane's point at planes 2 kq, 2 kq + 1
-        const float2 kz2 = *reinterpret_cast<const float2*>(skz + min(pq, q1 - 1) * 8 + 2 * kq);
         {
-          int qs = min(q + 16 + n, q1 - 1);
-          opaque(qs);
-          kxa_n = skx[qs * 8 + kq];
-          kxb_n = skx[qs * 8 + 4 + kq];
-          kya_n = *reinterpret_cast<const float4*>(sky + qs * 8);
-          kyb_n = *reinterpret_cast<const float4*>(sky + qs * 8 + 4);
+          int qn = min(q + 16, 64);
+          opaque(qn);
+          kxa_n = wx[8 * qn];
+          kxb_n = wx[8 * qn + 4];
+          kya_n = *reinterpret_cast<const float4*>(wy + 8 * qn);
+          kyb_n = *reinterpret_cast<const float4*>(wy + 8 * qn + 4);
+          kz0_n = wx[8 * qn + 1024];
+          kz4_n = wx[8 * qn + 1028];
           keep_order();
         }
-        // two independent accumulation chains (x half 0 and x half 1)
-        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
+        v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 16; s += 2) {
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s], kxa * ky[s >> 1], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bop[s + 1], kxb * ky[s >> 1], acc1, 0, 0, 0);
-        }
-        finish(tp, kzp, qp);
-        tp = acc0 + acc1;
-        kzp = kz2;
+        for (int s = 0; s < 16; s++)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], ((s & 1) ? kxb : kxa) * ky[s >> 1],
+                                                     acc, 0, 0, 0);
+        finish(rep, imp, qp);
+        // output rows 4 kq + i: plane kq + 4 (i >> 1), part i & 1
+        rep = fmaf(kz4, acc[2], kz0 * acc[0]);
+        imp = fmaf(kz4, acc[3], kz0 * acc[1]);
         qp = q;
       }
-      finish(tp, kzp, qp);
+      finish(rep, imp, qp);
     }
     __syncthreads();
     if (tid < nbatch) c[sperm[tid]] = sout[tid];

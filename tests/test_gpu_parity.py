@@ -135,3 +135,34 @@ def test_interp_methods_agree(case):
         outs[m] = cc
     for m in methods[1:]:
         assert O.rel_l2(outs[m], outs[methods[0]]) < (1e-5 if prec == "f32" else 1e-12)
+
+
+def _many_small_cases(count, seed):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(count):
+        N = tuple(int(x) for x in rng.integers(12, 48, 3))
+        M = int(10 ** rng.uniform(3.5, 5.2))
+        points = "uniform" if i % 2 == 0 else "wrapped_gaussian"
+        eps = [1e-6, 1e-5, 1e-4, 1e-3][i % 4]
+        cases.append((N, M, points, eps, 1000 + i))
+    return cases
+
+
+@pytest.mark.parametrize("type_", [1, 2])
+def test_matrix_core_matches_lds_tiles_on_many_small_problems(type_):
+    """The matrix-core kernels (3D, single precision) agree with the LDS-tile
+    kernels to rounding on 60 small problems of random shape, size, point
+    distribution and tolerance.  Small problems leave few waves per SIMD, where
+    the matrix results' latency is least hidden by other waves' work; a value
+    read too early shows up as a few wrong points."""
+    for N, M, points, eps, seed in _many_small_cases(60, 17 + type_):
+        coords, c, f = _inputs(3, N, M, points, "f32", seed)
+        outs = {}
+        for m in (1, 3):
+            if type_ == 1:
+                outs[m], _ = run_type1(coords, c, N, eps, "f32", spread_method=m)
+            else:
+                outs[m], _ = run_type2(coords, f, N, eps, "f32", interp_method=m)
+        err = O.rel_l2(outs[3], outs[1])
+        assert err < 1e-5, (N, M, points, eps, err)
