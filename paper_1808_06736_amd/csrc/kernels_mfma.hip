@@ -101,8 +101,6 @@ __device__ __forceinline__ int wrap2(int g, int n) {
 // that loads indexed by it, issued a loop step ahead, are not merged back into
 // the next step.
 __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
-// The same for a wave-uniform value, kept in a scalar register.
-__device__ __forceinline__ void opaque_s(int& v) { asm volatile("" : "+s"(v)); }
 
 // Keeps the memory accesses before it ahead of the code after it (a compiler
 // barrier only: no instruction, no wait).
@@ -115,9 +113,10 @@ __host__ __device__ inline int plane_floats(int T0, int T1) {
   return ((2 * T0 * T1 + 23) / 32) * 32 + 8;
 }
 
-// Points staged per batch by the spreading kernel: 64, plus 3 zero points so
-// that the 4-point steps may read past a run's end without a bound check.
-constexpr int kSpreadStage = 67;
+// Rows of staged points in the spreading kernel: 64 per batch, then zero rows
+// so that the steps may read up to 15 rows past the last run start (row 63)
+// without a bound check.
+constexpr int kSpreadStage = 80;
 
 // Rows of staged z weights in the interpolation kernel: a step reads the
 // weights of 16 points from a start of at most 64 (one batch), so reads reach
@@ -358,28 +357,43 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
         flush(fm);
         pend = zr;
       }
-      // the operands of each 4-point step are read from LDS one step ahead,
-      // so the reads overlap the matrix work; a step may run up to 3 points
-      // past the run (other runs' or zero points), whose B operand is masked
-      float ax_n = skx[q0 * 8 + ox];
-      float2 kz_n = *reinterpret_cast<const float2*>(skz + q0 * 8 + oz);
-      float bv_n = sb[q0 * 16 + ob];
-      for (int q = q0; q < q1; q += 4) {
-        const float ax = ax_n;
-        const float2 kz2 = kz_n;
-        const float bq = bv_n;
+      // Two 4-point steps per iteration.  The operands of a step are read from
+      // LDS into the registers of the step 8 points earlier right after that
+      // step has used them, so the other step's work covers the read latency
+      // (scheduling barriers keep the reads where they are written).
+      // Reads may run past the run (other runs' points, or the zero rows at
+      // the end of the staging; every row read is finite) and past a step's
+      // run end the B operand is masked.
+      const float* px = skx + ox;   // + 8 q: x weight of this lane's row
+      const float* pz = skz + oz;   // + 8 q: its two ring-slot weights
+      const float* pb = sb + ob;    // + 16 q: its B column
+      float axA = px[8 * q0], bvA = pb[16 * q0];
+      float2 kzA = *reinterpret_cast<const float2*>(pz + 8 * q0);
+      // (the first step's reads are issued first, so that waiting for them
+      // leaves the second step's in flight)
+      __builtin_amdgcn_sched_barrier(0);
+      float axB = px[8 * q0 + 32], bvB = pb[16 * q0 + 64];
+      float2 kzB = *reinterpret_cast<const float2*>(pz + 8 * q0 + 32);
+      for (int q = q0; q < q1; q += 8) {
         {
-          // (clamped so that the last, unused prefetch stays in the staging)
-          int qn = min(q + 4, NS - 4);
-          opaque_s(qn);
-          ax_n = skx[qn * 8 + ox];
-          kz_n = *reinterpret_cast<const float2*>(skz + qn * 8 + oz);
-          bv_n = sb[qn * 16 + ob];
-          keep_order();
+          const float bv = kg < q1 - q ? bvA : 0.f;
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axA * kzA.x, bv, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axA * kzA.y, bv, acc[1], 0, 0, 0);
         }
-        const float bv = q + kg < q1 ? bq : 0.f;
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.x, bv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax * kz2.y, bv, acc[1], 0, 0, 0);
+        int qa = q + 8;
+        axA = px[8 * qa];
+        kzA = *reinterpret_cast<const float2*>(pz + 8 * qa);
+        bvA = pb[16 * qa];
+        __builtin_amdgcn_sched_barrier(0);
+        if (q + 4 < q1) {
+          const float bv = kg < q1 - q - 4 ? bvB : 0.f;
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axB * kzB.x, bv, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axB * kzB.y, bv, acc[1], 0, 0, 0);
+        }
+        axB = px[8 * qa + 32];
+        kzB = *reinterpret_cast<const float2*>(pz + 8 * qa + 32);
+        bvB = pb[16 * qa + 64];
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
@@ -593,6 +607,10 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], ((s & 1) ? kxb : kxa) * ky[s >> 1],
                                                      acc, 0, 0, 0);
         finish(rep, imp, qp);
+        // 8 wait states on top of the compiler's own before vector
+        // instructions read the matrix results (margin over the latency; the
+        // accumulator operand ties the nop between the products and the reads)
+        asm volatile("s_nop 7" : "+v"(acc));
         // output rows 4 kq + i: plane kq + 4 (i >> 1), part i & 1
         rep = fmaf(kz4, acc[2], kz0 * acc[0]);
         imp = fmaf(kz4, acc[3], kz0 * acc[1]);
