@@ -2,14 +2,18 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-A step is one pass of the whole hot path over the workload's points: for each
-transform type in the workload, set the points (FP64 fold + bin sort +
-subproblems) and execute (spread / FFT / deconvolve for type 1; amplify / FFT /
-interpolate for type 2).  Plans (kernel parameters, the FP64 quadrature of the
-kernel's Fourier transform, rocFFT plans) are made once before timing, as the
-paper times only calls after planning (Sec. 5).  All inputs are resident in
-HBM before the timed region.  ``value`` = NU points processed per second
-(M * ntransf per transform type, summed) over the timed steps.
+A step is one pass of the whole hot path over the workload's points: set the
+points (FP64 fold + bin sort + subproblems) and execute each transform type
+(spread / FFT / deconvolve for type 1; amplify / FFT / interpolate for type 2).
+Where the workload runs both types on one point set, one type 1 plan sorts the
+points once and runs type 2 as its adjoint (opposite sign) on the same sorted
+points; the same step with one plan per type, each sorting for itself, is timed
+too and reported under ``separate_plans``.  Plans (kernel parameters, the FP64
+quadrature of the kernel's Fourier transform, rocFFT plans) are made once
+before timing, as the paper times only calls after planning (Sec. 5).  All
+inputs are resident in HBM before the timed region.  ``value`` = NU points
+processed per second (M * ntransf per transform type, summed) over the timed
+steps.
 
 One JSON line is printed.  Besides the contract fields it carries
 * ``roofline``: the dominant kernel's algorithmic work per launch divided by
@@ -149,20 +153,37 @@ def main():
         for t in wl.types:
             tuned[t], _ = autotune.tune(t, N, wl.eps, coords, c_in if t == 1 else f_in,
                                         dtype=cdt, ntransf=ntr)
+    # Both types on one point set (the 2D and 3D workloads): one plan of type 1
+    # sorts the points once and runs type 1 and, by its adjoint, type 2 (the
+    # opposite sign, isign -1, on the same sorted points).  Otherwise one plan
+    # per type.
+    shared = len(wl.types) == 2 and ntr == 1
     plans = {}
     outs = {}
     for t in wl.types:
+        outs[t] = torch.empty_like(f_in) if t == 1 else torch.empty_like(c_in)
+    for t in ([1] if shared else wl.types):
         plans[t] = B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1, **tuned.get(t, {}))
         plans[t].setpts(*coords)
-        if t == 1:
-            outs[t] = torch.empty_like(f_in)
-        else:
-            outs[t] = torch.empty_like(c_in)
     torch.cuda.synchronize()
 
-    def step(record=None):
+    def stage_rec(t, st_set, s):
+        return (t, st_set, s.t_spread_or_interp, s.t_fft, s.t_deconv_or_amplify, s.t_execute)
+
+    def step_shared(record=None):
+        p = plans[1]
+        p.setpts(*coords)
+        st_set = p.stats().t_setpts
+        p.execute(c_in, outs[1])
+        if record is not None:
+            record.append(stage_rec(1, st_set, p.stats()))
+        p.execute_adjoint(outs[2], f_in)
+        if record is not None:
+            record.append(stage_rec(2, 0.0, p.stats()))
+
+    def step_separate(pl, record=None):
         for t in wl.types:
-            p = plans[t]
+            p = pl[t]
             p.setpts(*coords)
             st_set = p.stats().t_setpts
             if t == 1:
@@ -170,19 +191,23 @@ def main():
             else:
                 p.execute(outs[2], f_in)
             if record is not None:
-                s = p.stats()
-                record.append((t, st_set, s.t_spread_or_interp, s.t_fft,
-                               s.t_deconv_or_amplify, s.t_execute))
+                record.append(stage_rec(t, st_set, p.stats()))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    rec = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(rec)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        rec = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(rec)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, rec
+
+    if shared:
+        elapsed, rec = timed(step_shared)
+    else:
+        elapsed, rec = timed(lambda r=None: step_separate(plans, r))
     ms_per_step = 1e3 * elapsed / args.steps
     pts_per_step = M * ntr * len(wl.types)
     value = pts_per_step / (elapsed / args.steps)
@@ -199,6 +224,22 @@ def main():
             "execute_ms": float(r[:, 4].mean()),
             "exec_pts_per_s": M * ntr / (r[:, 4].mean() * 1e-3),
         }
+
+    separate = None
+    if shared:
+        # the same step with one plan per type, each sorting the points itself
+        sep_plans = {t: B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1) for t in wl.types}
+        for p in sep_plans.values():
+            p.setpts(*coords)
+        sep_elapsed, sep_rec = timed(lambda r=None: step_separate(sep_plans, r))
+        separate = {"ms_per_step": 1e3 * sep_elapsed / args.steps,
+                    "value": pts_per_step / (sep_elapsed / args.steps),
+                    "setpts_ms": {f"type{t}": float(np.mean([x[1] for x in sep_rec if x[0] == t]))
+                                  for t in wl.types},
+                    "step": "per type: its own plan, setpts (fold+sort+subproblems) + execute"}
+        for p in sep_plans.values():
+            p.close()
+        plans[2] = plans[1]
 
     # dominant kernel: the slower of spread / interp
     info = {t: plans[t].info() for t in wl.types}
@@ -250,10 +291,15 @@ def main():
         "config": {"workload": wl.name, "dim": dim, "N": list(N), "M": M, "ntransf": ntr,
                    "eps": wl.eps, "points": wl.points, "types": list(wl.types),
                    "w": int(inf.w), "nf": nf,
-                   "step": "per type: setpts (fold+sort+subproblems) + execute"},
+                   "step": ("setpts once (fold+sort+subproblems) on a type 1 plan, execute "
+                            "type 1, execute its adjoint (type 2, isign -1) on the same sorted "
+                            "points" if shared else
+                            "per type: setpts (fold+sort+subproblems) + execute")},
         "stages": stages,
         "roofline": roof,
     }
+    if separate is not None:
+        out["separate_plans"] = separate
 
     if tuned:
         out["config"]["autotuned"] = {f"type{t}": {k: (list(v) if isinstance(v, tuple) else v)
@@ -268,7 +314,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
                                                           outs, args.cpu_sample)
-    for p in plans.values():
+    for p in {id(p): p for p in plans.values()}.values():
         p.close()
     print(json.dumps(out))
 

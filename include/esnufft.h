@@ -153,6 +153,18 @@ int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void*
  * Asynchronous on the plan's stream. */
 int esn_execute(esn_plan p, void* c, void* f);
 
+/* The adjoint of the plan's transform on the same sorted points (Sec. 1: the
+ * type 2 sum with sign -isign is the adjoint of the type 1 sum with sign
+ * isign, and the type 2 algorithm of Sec. 3.2 is the exact adjoint of the
+ * type 1 algorithm of Sec. 3.1).  A type 1 plan reads f [ntransf][N3][N2][N1]
+ * and writes c [ntransf][M] (c_j = sum_k f_k e^{-isign i k.x_j}); a type 2
+ * plan reads c and writes f (f_k = sum_j c_j e^{-isign i k.x_j}).  Same
+ * tolerance, bins and subproblems as the plan's own transform, so one
+ * esn_setpts serves both directions.  The first call makes the rocFFT plans
+ * of the opposite sign (device allocation); later calls allocate nothing.
+ * Asynchronous on the plan's stream; errors as esn_execute. */
+int esn_execute_adjoint(esn_plan p, void* c, void* f);
+
 /* The spreading step alone, eq. (bl): grid[t] = sum_j c[t][j] psi~(l h - x_j)
  * for the plan's points, into a caller buffer of ntransf * n1*n2*n3 complex
  * values (n1 fastest, fine-grid cell l at l*h).  Type 1 plans only. */

@@ -88,6 +88,7 @@ _SIGS = {
                       ctypes.POINTER(EsnOpts), vp], ci),
     "esn_setpts": ([vp, i64, ci, vp, vp, vp], ci),
     "esn_execute": ([vp, vp, vp], ci),
+    "esn_execute_adjoint": ([vp, vp, vp], ci),
     "esn_spread": ([vp, vp, vp], ci),
     "esn_interp": ([vp, vp, vp], ci),
     "esn_get_info": ([vp, ctypes.POINTER(EsnInfo)], ci),
@@ -181,6 +182,10 @@ def esn_setpts(plan, M, coord_prec, x, y=None, z=None):
 
 def esn_execute(plan, c, f):
     return lib().esn_execute(plan, c, f)
+
+
+def esn_execute_adjoint(plan, c, f):
+    return lib().esn_execute_adjoint(plan, c, f)
 
 
 def esn_spread(plan, c, grid):
@@ -366,6 +371,32 @@ class Plan:
                          vp(f.data_ptr()))
         check(st, "esn_execute")
         return c, f
+
+    def execute_adjoint(self, c, f):
+        """The adjoint transform on the same sorted points (type 1 plan: reads f,
+        writes c; type 2 plan: reads c, writes f; exponent sign -isign)."""
+        if self.M is None:
+            raise EsnError(ESN_ERR_NO_POINTS, "execute_adjoint")
+        self._check(c, self._shape_c(), "c")
+        self._check(f, self._shape_f(), "f")
+        st = esn_execute_adjoint(self.handle, vp(c.data_ptr()) if c.numel() else None,
+                                 vp(f.data_ptr()))
+        check(st, "esn_execute_adjoint")
+        return c, f
+
+    def adjoint(self, x, out=None):
+        """Adjoint of this plan's transform applied to x: for a type 1 plan x
+        holds modes f and the result is c at the points; for a type 2 plan x
+        holds strengths c and the result is modes f."""
+        if self.type == 1:
+            c = out if out is not None else self.torch.empty(self._shape_c(), dtype=self.dtype,
+                                                             device=self.device)
+            self.execute_adjoint(c, x)
+            return c
+        f = out if out is not None else self.torch.empty(self._shape_f(), dtype=self.dtype,
+                                                         device=self.device)
+        self.execute_adjoint(x, f)
+        return f
 
     def type1(self, c, out=None):
         f = out if out is not None else self.torch.empty(self._shape_f(), dtype=self.dtype,

@@ -198,6 +198,11 @@ struct esn_plan_s {
   int chunk = 1;                 // transforms per fused launch
   esn::FFTPlan fft;
   esn::FFTPlan fft_tail;         // plan for the last, shorter chunk (if any)
+  // the opposite transform direction (esn_execute_adjoint): FFTs of sign
+  // -isign, made on its first call; its transforms per launch and last chunk
+  esn::FFTPlan fft_adj;
+  esn::FFTPlan fft_adj_tail;
+  int adj_chunk = 0, adj_tail = 0;
   int tail = 0;
 
   // binning geometry

@@ -146,6 +146,8 @@ void destroy_all(esn_plan_s* p) {
   p->h_pinned = nullptr;
   fft_destroy(&p->fft);
   fft_destroy(&p->fft_tail);
+  fft_destroy(&p->fft_adj);
+  fft_destroy(&p->fft_adj_tail);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -551,23 +553,62 @@ static int run_interp(esn_plan_s* p, int ntr, const void* grid, void* c) {
   return ESN_OK;
 }
 
-extern "C" int esn_execute(esn_plan p, void* c, void* f) {
-  if (!p) return ESN_ERR_BAD_ARG;
+// The rocFFT plans of the opposite sign and the transforms per launch for
+// the adjoint direction dir (3 - type), made on the first adjoint call.
+static int make_adjoint(esn_plan_s* p) {
+  if (p->fft_adj.plan) return ESN_OK;
+  const int dir = 3 - p->type;
+  const int method = dir == 1 ? p->spread_method : p->interp_method;
+  int chunk = p->chunk;
+  if (method == 3) {
+    chunk = 1;
+  } else if (method == 1) {
+    const size_t budget = lds_budget(p->device);
+    const size_t one = tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, 1, dir == 1);
+    chunk = std::max(1, std::min(chunk, (int)std::max<size_t>(1, budget / one)));
+    while (chunk > 1 && tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, chunk, dir == 1) > budget)
+      chunk--;
+  }
+  chunk = std::max(1, std::min(chunk, p->ntransf));
+  const int tail = p->ntransf % chunk;
+  int rc = fft_make(&p->fft_adj, p->dim, p->nf, chunk, p->prec, -p->isign, p->stream);
+  if (rc == ESN_OK && tail) rc = fft_make(&p->fft_adj_tail, p->dim, p->nf, tail, p->prec, -p->isign,
+                                          p->stream);
+  if (rc != ESN_OK) {
+    fft_destroy(&p->fft_adj);
+    fft_destroy(&p->fft_adj_tail);
+    return rc;
+  }
+  p->device_bytes += (int64_t)(p->fft_adj.work_bytes + p->fft_adj_tail.work_bytes);
+  p->adj_chunk = chunk;
+  p->adj_tail = tail;
+  return ESN_OK;
+}
+
+// Transforms of direction dir (1: spread, FFT, deconvolve; 2: amplify, FFT,
+// interpolate) on the plan's sorted points.  dir == type is the plan's own
+// transform, the other direction its adjoint (opposite exponent sign).
+static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
   if (p->M < 0) return ESN_ERR_NO_POINTS;
   if ((p->M > 0 && !c) || !f) return ESN_ERR_BAD_ARG;
   ESN_HIP(hipSetDevice(p->device));
+  const bool adj = dir != p->type;
+  if (adj) ESN_TRY(make_adjoint(p));
+  const int chunk = adj ? p->adj_chunk : p->chunk;
+  FFTPlan* fft_full = adj ? &p->fft_adj : &p->fft;
+  FFTPlan* fft_last = adj ? &p->fft_adj_tail : &p->fft_tail;
   hipStream_t s = p->stream;
   const size_t cs = csize(p->prec);
   const int64_t G = nf_total(p), Nt = n_total(p);
   const double* pf[3] = {p->d_pf[0], p->d_pf[1], p->d_pf[2]};
   double t_a = 0, t_fft = 0, t_b = 0;
   if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[5], s));
-  for (int c0 = 0; c0 < p->ntransf; c0 += p->chunk) {
-    const int ntr = std::min(p->chunk, p->ntransf - c0);
-    FFTPlan* fp = ntr == p->chunk ? &p->fft : &p->fft_tail;
+  for (int c0 = 0; c0 < p->ntransf; c0 += chunk) {
+    const int ntr = std::min(chunk, p->ntransf - c0);
+    FFTPlan* fp = ntr == chunk ? fft_full : fft_last;
     char* cc = static_cast<char*>(c) + (size_t)c0 * p->M * cs;
     char* ff = static_cast<char*>(f) + (size_t)c0 * Nt * cs;
-    if (p->type == 1) {
+    if (dir == 1) {
       ESN_HIP(hipMemsetAsync(p->d_grid, 0, (size_t)ntr * G * cs, s));
       if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
       ESN_TRY(run_spread(p, ntr, cc, p->d_grid));
@@ -600,7 +641,7 @@ extern "C" int esn_execute(esn_plan p, void* c, void* f) {
     ESN_HIP(hipEventSynchronize(p->ev[4]));
     float tot = 0;
     ESN_HIP(hipEventElapsedTime(&tot, p->ev[5], p->ev[4]));
-    if (p->type == 1) {
+    if (dir == 1) {
       p->stats.t_spread_or_interp = t_a;   // spread kernel(s) only
       p->stats.t_deconv_or_amplify = t_b;
     } else {
@@ -611,6 +652,16 @@ extern "C" int esn_execute(esn_plan p, void* c, void* f) {
     p->stats.t_execute = tot;
   }
   return p->warn;
+}
+
+extern "C" int esn_execute(esn_plan p, void* c, void* f) {
+  if (!p) return ESN_ERR_BAD_ARG;
+  return execute_dir(p, p->type, c, f);
+}
+
+extern "C" int esn_execute_adjoint(esn_plan p, void* c, void* f) {
+  if (!p) return ESN_ERR_BAD_ARG;
+  return execute_dir(p, 3 - p->type, c, f);
 }
 
 extern "C" int esn_spread(esn_plan p, const void* c, void* grid) {
@@ -701,6 +752,9 @@ int plan_set_stream(esn_plan p, hipStream_t s) {
   if (p->fft_tail.info &&
       rocfft_execution_info_set_stream(p->fft_tail.info, (void*)s) != rocfft_status_success)
     return ESN_ERR_FFT_PLAN;
+  for (FFTPlan* f : {&p->fft_adj, &p->fft_adj_tail})
+    if (f->info && rocfft_execution_info_set_stream(f->info, (void*)s) != rocfft_status_success)
+      return ESN_ERR_FFT_PLAN;
   return ESN_OK;
 }
 

@@ -276,3 +276,50 @@ def test_batched_equals_single(dim, prec):
     for k in range(nt):
         ck, _ = run_type2(coords, f[k], N, 1e-5, prec)
         assert O.rel_l2(cb[k], ck) < tol
+
+
+@pytest.mark.parametrize("type_,dim,prec,eps,ntr", [
+    (1, 1, "f64", 1e-9, 1), (1, 2, "f32", 1e-5, 1), (1, 3, "f32", 1e-6, 1), (2, 3, "f32", 1e-6, 1),
+    (1, 3, "f64", 1e-9, 1), (2, 2, "f64", 1e-10, 1), (1, 3, "f32", 1e-4, 3), (2, 2, "f32", 1e-5, 4)])
+def test_execute_adjoint(type_, dim, prec, eps, ntr):
+    """A plan's adjoint on its own sorted points is the opposite type with the
+    opposite sign (Sec. 1): it meets the bar against the oracle, equals a plan
+    of that type to rounding, and is the exact adjoint of the plan's own
+    transform (<T c, f> = <c, T^H f> to rounding, whatever eps)."""
+    t = torch()
+    N = (37, 24, 19)[:dim]
+    M = 20000
+    coords = I.wrapped_gaussian_points(M, dim, 81, 0.5, np.float32 if prec == "f32" else np.float64)
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    shp_c = (ntr, M) if ntr > 1 else (M,)
+    shp_f = ((ntr,) if ntr > 1 else ()) + tuple(reversed(N))
+    c = I.complex_normal(shp_c, 82, cdt)
+    f = I.complex_normal(shp_f, 83, cdt)
+    isign = 1 if type_ == 1 else -1
+    plan = B.Plan(type_, N, eps, dtype=cdtype(prec), isign=isign, ntransf=ntr)
+    plan.setpts(*[dev(a) for a in coords])
+    if type_ == 1:
+        fw = host(plan.type1(dev(c)))            # T c
+        bw = host(plan.adjoint(dev(f)))          # T^H f: type 2, sign -1
+        ref = np.stack([O.type2(coords, f.reshape((-1,) + tuple(reversed(N)))[k], -isign)
+                        for k in range(ntr)]).reshape(shp_c)
+        other, _ = run_type2(coords, f, N, eps, prec, isign=-isign, ntransf=ntr)
+        lhs = np.vdot(f.astype(np.complex128).ravel(), fw.astype(np.complex128).ravel())
+        rhs = np.vdot(bw.astype(np.complex128).ravel(), c.astype(np.complex128).ravel())
+    else:
+        fw = host(plan.type2(dev(f)))            # T f
+        bw = host(plan.adjoint(dev(c)))          # T^H c: type 1, sign +1
+        ref = np.stack([O.type1(coords, c.reshape(ntr, M)[k], -isign, N=N)
+                        for k in range(ntr)]).reshape(shp_f)
+        other, _ = run_type1(coords, c, N, eps, prec, isign=-isign, ntransf=ntr)
+        lhs = np.vdot(c.astype(np.complex128).ravel(), fw.astype(np.complex128).ravel())
+        rhs = np.vdot(bw.astype(np.complex128).ravel(), f.astype(np.complex128).ravel())
+    t.cuda.synchronize()
+    plan.close()
+    err = O.rel_l2(bw, ref)
+    adj = abs(lhs - rhs) / abs(lhs)
+    print(f"adjoint of type {type_} {dim}d {prec} x{ntr}: rel l2 {err:.2e}, "
+          f"vs plan {O.rel_l2(bw, other):.2e}, adjointness {adj:.2e}")
+    assert err <= 10 * eps
+    assert O.rel_l2(bw, other) <= (2 * eps if prec == "f32" else 1e-11)
+    assert adj < (2e-5 if prec == "f32" else 1e-12)
