@@ -158,14 +158,28 @@ size_t mfma_interp_lds_bytes(const int* b);
 size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr, bool staging = true);
 
 // ---- rocFFT wrapper (fft.cpp) ----
+// In 3D only the x columns that hold modes (k1 mod n1 for k1 in I_N1, two
+// runs) need the FFTs along y and z: after the x pass of a type 1 transform the
+// other columns are never read, and before the x pass of a type 2 transform
+// they are zero.  Such a plan runs one batched x pass and, per transform and
+// kept run, a 2D (y, z) FFT batched over the run's columns.
 struct FFTPlan {
-  rocfft_plan plan = nullptr;
+  rocfft_plan plan = nullptr;          // the whole transform, or the x pass
+  rocfft_plan yz[2] = {nullptr, nullptr};   // (y, z) FFTs of the kept x runs
+  int64_t yz_off[2] = {0, 0};          // first column of each kept run
+  int nyz = 0;                         // kept runs (0: not pruned)
+  int batch = 0;                       // transforms
+  int64_t grid = 0;                    // elements per transform
+  int elem = 8;                        // bytes per complex element
+  int x_first = 1;                     // type 1: x pass first; type 2: last
   rocfft_execution_info info = nullptr;
   void* work = nullptr;
   size_t work_bytes = 0;
 };
-int fft_make(FFTPlan* p, int dim, const int64_t* nf, int batch, int prec,
-             int sign, hipStream_t s);
+// nmodes: N per dim, for the kept x runs of a 3D transform; type selects the
+// pass order.
+int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int type, int batch,
+             int prec, int sign, hipStream_t s);
 int fft_exec(FFTPlan* p, void* data);
 void fft_destroy(FFTPlan* p);
 

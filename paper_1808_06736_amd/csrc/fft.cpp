@@ -3,6 +3,12 @@
 // batched over the transforms of one fused launch.  The exponent sign equals
 // the transform's isign: +1 -> rocFFT's inverse (backward, e^{+2 pi i lk/n}),
 // -1 -> rocFFT's forward (e^{-2 pi i lk/n}).
+//
+// 3D transforms skip the y and z FFTs of the x columns that hold no mode
+// (k1 mod n1 outside I_N1): half the grid or more for sigma = 2.  The result
+// at the kept columns is that of the full 3D FFT, since the y and z FFTs act
+// on each x column by itself.
+#include <algorithm>
 #include <mutex>
 
 #include "esn_internal.hpp"
@@ -12,31 +18,78 @@ namespace esn {
 static std::once_flag g_rocfft_once;
 static rocfft_status g_rocfft_setup = rocfft_status_success;
 
-int fft_make(FFTPlan* p, int dim, const int64_t* nf, int batch, int prec, int sign,
-             hipStream_t s) {
+// rocFFT plan of `dim` lengths (fastest first) with optional strides.
+static rocfft_plan make_one(int dim, const size_t* len, size_t batch, const size_t* stride,
+                            size_t dist, int prec, int sign) {
+  rocfft_plan_description d = nullptr;
+  if (stride) {
+    if (rocfft_plan_description_create(&d) != rocfft_status_success) return nullptr;
+    if (rocfft_plan_description_set_data_layout(
+            d, rocfft_array_type_complex_interleaved, rocfft_array_type_complex_interleaved,
+            nullptr, nullptr, (size_t)dim, stride, dist, (size_t)dim, stride, dist) !=
+        rocfft_status_success) {
+      rocfft_plan_description_destroy(d);
+      return nullptr;
+    }
+  }
+  rocfft_plan p = nullptr;
+  const rocfft_status st = rocfft_plan_create(
+      &p, rocfft_placement_inplace,
+      sign > 0 ? rocfft_transform_type_complex_inverse : rocfft_transform_type_complex_forward,
+      prec == ESN_DOUBLE ? rocfft_precision_double : rocfft_precision_single, (size_t)dim, len,
+      batch, d);
+  if (d) rocfft_plan_description_destroy(d);
+  return st == rocfft_status_success ? p : nullptr;
+}
+
+int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int type, int batch,
+             int prec, int sign, hipStream_t s) {
   std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
   if (g_rocfft_setup != rocfft_status_success) return ESN_ERR_FFT_PLAN;
-  size_t lengths[3];
-  for (int m = 0; m < dim; m++) lengths[m] = (size_t)nf[m];   // fastest first
-  rocfft_status st = rocfft_plan_create(
-      &p->plan, rocfft_placement_inplace,
-      sign > 0 ? rocfft_transform_type_complex_inverse : rocfft_transform_type_complex_forward,
-      prec == ESN_DOUBLE ? rocfft_precision_double : rocfft_precision_single, (size_t)dim,
-      lengths, (size_t)batch, nullptr);
-  if (st != rocfft_status_success) {
-    p->plan = nullptr;
-    return ESN_ERR_FFT_PLAN;
+  p->batch = batch;
+  p->elem = prec == ESN_DOUBLE ? 16 : 8;
+  p->grid = 1;
+  for (int m = 0; m < dim; m++) p->grid *= nf[m];
+  p->x_first = type == 1;
+  // kept x runs: k1 = 0 .. ceil(N1/2) - 1 and n1 - floor(N1/2) .. n1 - 1
+  const int64_t lo = (nmodes[0] + 1) / 2, hi = nmodes[0] / 2;
+  const bool prune = dim == 3 && lo + hi < nf[0];
+  size_t work = 0;
+  if (prune) {
+    const size_t lx[1] = {(size_t)nf[0]};
+    p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
+    const size_t lyz[2] = {(size_t)nf[1], (size_t)nf[2]};
+    const size_t syz[2] = {(size_t)nf[0], (size_t)(nf[0] * nf[1])};
+    const int64_t runs[2] = {lo, hi};
+    const int64_t offs[2] = {0, nf[0] - hi};
+    for (int r = 0; r < 2; r++) {
+      if (runs[r] <= 0) continue;
+      p->yz[p->nyz] = make_one(2, lyz, (size_t)runs[r], syz, 1, prec, sign);
+      p->yz_off[p->nyz] = offs[r];
+      if (!p->yz[p->nyz]) return ESN_ERR_FFT_PLAN;
+      p->nyz++;
+    }
+  } else {
+    size_t lengths[3];
+    for (int m = 0; m < dim; m++) lengths[m] = (size_t)nf[m];   // fastest first
+    p->plan = make_one(dim, lengths, (size_t)batch, nullptr, 0, prec, sign);
   }
-  st = rocfft_plan_get_work_buffer_size(p->plan, &p->work_bytes);
-  if (st != rocfft_status_success) return ESN_ERR_FFT_PLAN;
+  if (!p->plan) return ESN_ERR_FFT_PLAN;
+  // one work buffer serves every plan (they run one after another on the stream)
+  for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]}) {
+    if (!q) continue;
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(q, &wb) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
+    work = std::max(work, wb);
+  }
+  p->work_bytes = work;
   if (rocfft_execution_info_create(&p->info) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
-  if (p->work_bytes > 0) {
-    if (hipMalloc(&p->work, p->work_bytes) != hipSuccess) {
+  if (work > 0) {
+    if (hipMalloc(&p->work, work) != hipSuccess) {
       p->work = nullptr;
       return ESN_ERR_ALLOC;
     }
-    if (rocfft_execution_info_set_work_buffer(p->info, p->work, p->work_bytes) !=
-        rocfft_status_success)
+    if (rocfft_execution_info_set_work_buffer(p->info, p->work, work) != rocfft_status_success)
       return ESN_ERR_FFT_PLAN;
   }
   if (rocfft_execution_info_set_stream(p->info, (void*)s) != rocfft_status_success)
@@ -45,19 +98,27 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, int batch, int prec, int si
 }
 
 int fft_exec(FFTPlan* p, void* data) {
-  void* in[1] = {data};
-  rocfft_status st = rocfft_execute(p->plan, in, nullptr, p->info);
-  return st == rocfft_status_success ? ESN_OK : ESN_ERR_FFT_PLAN;
+  auto run = [&](rocfft_plan q, void* ptr) {
+    void* in[1] = {ptr};
+    return rocfft_execute(q, in, nullptr, p->info) == rocfft_status_success;
+  };
+  if (!p->nyz) return run(p->plan, data) ? ESN_OK : ESN_ERR_FFT_PLAN;
+  if (p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+  for (int t = 0; t < p->batch; t++)
+    for (int r = 0; r < p->nyz; r++) {
+      char* base = static_cast<char*>(data) + (size_t)(t * p->grid + p->yz_off[r]) * p->elem;
+      if (!run(p->yz[r], base)) return ESN_ERR_FFT_PLAN;
+    }
+  if (!p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+  return ESN_OK;
 }
 
 void fft_destroy(FFTPlan* p) {
   if (p->info) rocfft_execution_info_destroy(p->info);
-  if (p->plan) rocfft_plan_destroy(p->plan);
+  for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]})
+    if (q) rocfft_plan_destroy(q);
   if (p->work) (void)hipFree(p->work);
-  p->info = nullptr;
-  p->plan = nullptr;
-  p->work = nullptr;
-  p->work_bytes = 0;
+  *p = FFTPlan();
 }
 
 }  // namespace esn

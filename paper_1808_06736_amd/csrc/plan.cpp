@@ -353,10 +353,10 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
 
   // ---- fine grid and FFT plans ----
   if (dalloc(p, &p->d_grid, gbytes * chunk) != ESN_OK) return fail(ESN_ERR_ALLOC);
-  rc = fft_make(&p->fft, dim, p->nf, chunk, prec, isign, s);
+  rc = fft_make(&p->fft, dim, p->nf, p->N, type, chunk, prec, isign, s);
   if (rc != ESN_OK) return fail(rc);
   if (p->tail) {
-    rc = fft_make(&p->fft_tail, dim, p->nf, p->tail, prec, isign, s);
+    rc = fft_make(&p->fft_tail, dim, p->nf, p->N, type, p->tail, prec, isign, s);
     if (rc != ESN_OK) return fail(rc);
   }
   p->device_bytes += (int64_t)(p->fft.work_bytes + p->fft_tail.work_bytes);
@@ -571,9 +571,11 @@ static int make_adjoint(esn_plan_s* p) {
   }
   chunk = std::max(1, std::min(chunk, p->ntransf));
   const int tail = p->ntransf % chunk;
-  int rc = fft_make(&p->fft_adj, p->dim, p->nf, chunk, p->prec, -p->isign, p->stream);
-  if (rc == ESN_OK && tail) rc = fft_make(&p->fft_adj_tail, p->dim, p->nf, tail, p->prec, -p->isign,
-                                          p->stream);
+  int rc = fft_make(&p->fft_adj, p->dim, p->nf, p->N, 3 - p->type, chunk, p->prec, -p->isign,
+                    p->stream);
+  if (rc == ESN_OK && tail)
+    rc = fft_make(&p->fft_adj_tail, p->dim, p->nf, p->N, 3 - p->type, tail, p->prec, -p->isign,
+                  p->stream);
   if (rc != ESN_OK) {
     fft_destroy(&p->fft_adj);
     fft_destroy(&p->fft_adj_tail);
