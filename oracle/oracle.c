@@ -1,5 +1,5 @@
 /*
- * Plain FP64 CPU oracle for the type 1 and type 2 NUFFT sums.
+ * Plain FP64 CPU oracle for the type 1, type 2 and type 3 NUFFT sums.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg load this code.  It shares nothing with the GPU
@@ -11,6 +11,8 @@
  *     (N even: -N/2..N/2-1;  N odd: -(N-1)/2..(N-1)/2)
  *   type 1:  f_k = sum_{j=1..M} c_j exp(+/- i k.x_j),   k in I_{N1} x ... x I_{Nd}
  *   type 2:  c_j = sum_{k in I}  f_k exp(+/- i k.x_j),   j = 1..M
+ *   type 3:  f_k = sum_{j=1..M} c_j exp(+/- i s_k.x_j),  k = 1..N  (eq. (3):
+ *            arbitrary real source points x_j and target frequencies s_k)
  * The sign of i is the caller's isign (+1 or -1); the paper's defaults are +1
  * for type 1 and -1 for type 2.  No normalisation is applied.
  *
@@ -21,8 +23,9 @@
  *
  * Threads only split independent work: type 1 splits the points (each thread
  * sums its own points for every requested mode; partial sums are then added in
- * thread order, so results do not depend on scheduling); type 2 splits the
- * target points.
+ * thread order, so results do not depend on scheduling); types 2 and 3 split
+ * the outputs.  Type 3 forms each phase s_k.x_j in FP64 and takes its cosine
+ * and sine directly (the targets are not a grid, so there is no product form).
  */
 #include <math.h>
 #include <pthread.h>
@@ -209,6 +212,68 @@ int oracle_type2(int dim, int64_t M, const double *x, const double *y,
   }
   for (int t = 0; t < T; t++) pthread_join(th[t], NULL);
   for (int m = 0; m < 3; m++) free(ks[m]);
+  free(jobs); free(th);
+  return 0;
+}
+
+typedef struct {
+  int dim;
+  int64_t k0, k1;                 /* target range [k0, k1) */
+  int64_t M;
+  const double *x[3], *s[3];
+  const double *c;
+  int isign;
+  double *f;
+} job3_t;
+
+static void *type3_worker(void *arg) {
+  job3_t *jb = (job3_t *)arg;
+  for (int64_t k = jb->k0; k < jb->k1; k++) {
+    double fr = 0.0, fi = 0.0;
+    for (int64_t j = 0; j < jb->M; j++) {
+      double ph = 0.0;
+      for (int m = 0; m < jb->dim; m++) ph += jb->s[m][k] * jb->x[m][j];
+      ph *= (double)jb->isign;
+      double cr = jb->c[2 * j], ci = jb->c[2 * j + 1];
+      double er = cos(ph), ei = sin(ph);
+      fr += cr * er - ci * ei;
+      fi += cr * ei + ci * er;
+    }
+    jb->f[2 * k] = fr;
+    jb->f[2 * k + 1] = fi;
+  }
+  return NULL;
+}
+
+/*
+ * Type 3 (eq. (3)): f_k = sum_j c_j exp(isign i s_k.x_j), k = 0..N-1.
+ *   sources x[0..dim-1][M], strengths c: 2*M doubles; targets s[0..dim-1][N];
+ *   f: 2*N doubles, overwritten.
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+int oracle_type3(int dim, int64_t M, const double *x, const double *y, const double *z,
+                 const double *c, int64_t N, const double *s, const double *t,
+                 const double *u, int isign, double *f, int nthreads) {
+  if (dim < 1 || dim > 3 || M < 0 || N < 0) return -1;
+  if (N == 0) return 0;
+  int T = clamp_threads(nthreads, N);
+  job3_t *jobs = calloc(T, sizeof(job3_t));
+  pthread_t *th = calloc(T, sizeof(pthread_t));
+  if (!jobs || !th) return -1;
+  for (int q = 0; q < T; q++) {
+    job3_t *jb = &jobs[q];
+    jb->dim = dim;
+    jb->k0 = N * q / T;
+    jb->k1 = N * (q + 1) / T;
+    jb->M = M;
+    jb->x[0] = x; jb->x[1] = y; jb->x[2] = z;
+    jb->s[0] = s; jb->s[1] = t; jb->s[2] = u;
+    jb->c = c;
+    jb->isign = isign;
+    jb->f = f;
+    pthread_create(&th[q], NULL, type3_worker, jb);
+  }
+  for (int q = 0; q < T; q++) pthread_join(th[q], NULL);
   free(jobs); free(th);
   return 0;
 }

@@ -3,9 +3,10 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the GPU library or its binding.
 
-It evaluates the type 1 / type 2 exponential sums of Sec. 1, eqs. (1)-(2), by
-their definitions in double precision (see ``oracle.c``), plus the relative l2
-error metric of Sec. 4.2 used to compare any approximation against them.
+It evaluates the type 1 / type 2 / type 3 exponential sums of Sec. 1, eqs.
+(1)-(3), by their definitions in double precision (see ``oracle.c``), plus the
+relative l2 error metric of Sec. 4.2 used to compare any approximation against
+them.
 """
 from __future__ import annotations
 
@@ -44,6 +45,8 @@ def _load():
         lib.oracle_type2.argtypes = [ip, i64, dp, dp, dp, dp, i64, i64, i64, ip, dp,
                                      ip]
         lib.oracle_type2.restype = ip
+        lib.oracle_type3.argtypes = [ip, i64, dp, dp, dp, dp, i64, dp, dp, dp, ip, dp, ip]
+        lib.oracle_type3.restype = ip
         _lib = lib
     return _lib
 
@@ -116,6 +119,30 @@ def type2(coords, f, isign: int, nthreads=None) -> np.ndarray:
                               nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_type2: bad arguments")
+    return out
+
+
+def type3(coords, c, targets, isign: int, nthreads=None) -> np.ndarray:
+    """f_k = sum_j c_j exp(isign i s_k.x_j)  (eq. (3)), in complex128.
+
+    ``coords``: d source coordinate arrays (M values each); ``targets``: d
+    target frequency arrays (N values each); ``c``: M strengths.  Returns N
+    values.
+    """
+    d = len(coords)
+    assert len(targets) == d
+    xs = _coords64(coords, d)
+    ss = _coords64(targets, d)
+    cc = np.ascontiguousarray(np.asarray(c, dtype=np.complex128)).reshape(-1)
+    M, N = cc.shape[0], ss[0].shape[0]
+    for m in range(d):
+        assert xs[m].shape[0] == M and ss[m].shape[0] == N
+    out = np.zeros(N, dtype=np.complex128)
+    rc = _load().oracle_type3(d, M, _ptr(xs[0]), _ptr(xs[1]), _ptr(xs[2]), _ptr(cc), N,
+                              _ptr(ss[0]), _ptr(ss[1]), _ptr(ss[2]), int(isign), _ptr(out),
+                              nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_type3: bad arguments")
     return out
 
 

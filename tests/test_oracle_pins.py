@@ -134,3 +134,70 @@ def test_rel_l2():
     e = np.array([3.0, 4.0])
     assert O.rel_l2(e, e) == 0.0
     assert abs(O.rel_l2(e + np.array([0.0, 0.5]), e) - 0.1) < 1e-15
+
+
+# ---- type 3 (eq. (3)) ----
+
+@pytest.mark.parametrize("Ns", [(9,), (6, 5), (4, 3, 5)])
+@pytest.mark.parametrize("isign", [1, -1])
+def test_type3_at_integer_targets_is_type1(Ns, isign):
+    """Targets on the integer mode grid turn eq. (3) into eq. (1); the type 1
+    oracle is itself pinned to numpy's FFT above (a transposed target array,
+    a dropped dimension or a wrong sign fails here)."""
+    d = len(Ns)
+    pts = I.uniform_points(37, d, seed=21)
+    c = I.complex_normal(37, seed=22)
+    modes = [I.mode_range(N) for N in Ns]
+    mesh = np.meshgrid(*reversed(modes), indexing="ij")
+    targets = [m.reshape(-1).astype(np.float64) for m in reversed(mesh)]
+    f3 = O.type3(pts, c, targets, isign)
+    f1 = O.type1(pts, c, isign, N=Ns).reshape(-1)
+    assert np.max(np.abs(f3 - f1)) < 1e-11 * np.max(np.abs(f1))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_type3_swapped_roles_is_adjoint(d):
+    """With A_kj = exp(i s_k.x_j), the type 3 sum from sources s to targets x
+    with the opposite sign applies A^H: <A c, g> = <c, A^H g>."""
+    rng = np.random.default_rng(23)
+    x = [rng.uniform(-3, 3, 41) for _ in range(d)]
+    s = [rng.uniform(-20, 20, 29) for _ in range(d)]
+    c = I.complex_normal(41, seed=24)
+    g = I.complex_normal(29, seed=25)
+    lhs = np.vdot(g, O.type3(x, c, s, +1))
+    rhs = np.vdot(O.type3(s, g, x, -1), c)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_type3_translation_identity(d):
+    """Eq. (trans): shifting the sources by x0 multiplies f_k by
+    exp(isign i s_k.x0); shifting the targets by s0 is prephasing c by
+    exp(isign i s0.x_j)."""
+    rng = np.random.default_rng(26)
+    x = [rng.uniform(-2, 2, 33) for _ in range(d)]
+    s = [rng.uniform(-15, 15, 27) for _ in range(d)]
+    x0 = rng.uniform(-1, 1, d)
+    s0 = rng.uniform(-5, 5, d)
+    c = I.complex_normal(33, seed=27)
+    for isign in (1, -1):
+        f = O.type3(x, c, s, isign)
+        fx = O.type3([x[m] + x0[m] for m in range(d)], c, s, isign)
+        ph = np.exp(isign * 1j * sum(s[m] * x0[m] for m in range(d)))
+        assert np.max(np.abs(fx - ph * f)) < 1e-11 * np.max(np.abs(f))
+        fs = O.type3(x, c, [s[m] + s0[m] for m in range(d)], isign)
+        cpre = c * np.exp(isign * 1j * sum(s0[m] * x[m] for m in range(d)))
+        assert np.max(np.abs(fs - O.type3(x, cpre, s, isign))) < 1e-11 * np.max(np.abs(fs))
+
+
+def test_type3_dilation_invariance():
+    """s_k.x_j is unchanged by x -> x / gamma, s -> gamma s (the dilation of
+    Sec. 3.3, step 1), per dimension."""
+    rng = np.random.default_rng(28)
+    x = [rng.uniform(-4, 4, 25) for _ in range(3)]
+    s = [rng.uniform(-9, 9, 19) for _ in range(3)]
+    gam = [0.37, 2.5, 11.0]
+    c = I.complex_normal(25, seed=29)
+    f = O.type3(x, c, s, 1)
+    g = O.type3([x[m] / gam[m] for m in range(3)], c, [s[m] * gam[m] for m in range(3)], 1)
+    assert np.max(np.abs(f - g)) < 1e-11 * np.max(np.abs(f))
