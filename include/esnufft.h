@@ -146,6 +146,22 @@ int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntrans
 int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
                const void* z);
 
+/* Type 3 plans (esn_makeplan with type 3; nmodes is not read and may be NULL):
+ * give the M source points x[, y[, z]] and the N target frequencies s[, t[, u]]
+ * of eq. (3), f_k = sum_j c_j exp(isign i s_k.x_j), any finite real values
+ * (float if coord_prec == ESN_SINGLE else double; unused dims may be NULL).
+ * Centres both sets (eq. (trans)), sizes the fine grid and the dilation from
+ * their half-widths (eq. (ng) of Sec. 3.3, step 0), bin-sorts the rescaled
+ * sources for spreading and the rescaled targets for the inner type 2 NUFFT,
+ * and evaluates the per-target correction (d p FP64 cosines) and phases.
+ * Synchronises the stream.  Errors: ESN_ERR_BAD_ARG, ESN_ERR_NAN_PTS (a NaN or
+ * infinite coordinate), ESN_ERR_BUDGET (a fine grid of more than 2^31 cells),
+ * ESN_ERR_ALLOC; on error the plan has no points.  esn_execute then reads c
+ * [ntransf][M] and writes f [ntransf][N]; esn_execute_adjoint returns
+ * ESN_ERR_UNSUPPORTED for type 3. */
+int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
+                const void* z, int64_t N, const void* s, const void* t, const void* u);
+
 /* Run the transforms.  type 1: reads c [ntransf][M], writes f
  * [ntransf][N3][N2][N1] (steps of Sec. 3.1: spread eq. (bl), FFT eq. (dft1),
  * truncate and correct eq. (pb1)); type 2: reads f, writes c (Sec. 3.2:

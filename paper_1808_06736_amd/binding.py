@@ -87,6 +87,7 @@ _SIGS = {
     "esn_makeplan": ([ci, ci, ctypes.POINTER(i64), ci, ci, cd, ci, ctypes.POINTER(vp),
                       ctypes.POINTER(EsnOpts), vp], ci),
     "esn_setpts": ([vp, i64, ci, vp, vp, vp], ci),
+    "esn_setpts3": ([vp, i64, ci, vp, vp, vp, i64, vp, vp, vp], ci),
     "esn_execute": ([vp, vp, vp], ci),
     "esn_execute_adjoint": ([vp, vp, vp], ci),
     "esn_spread": ([vp, vp, vp], ci),
@@ -150,7 +151,7 @@ def strerror(status: int) -> str:
 
 
 def _i64x3(vals):
-    v = list(vals) + [1] * (3 - len(vals))
+    v = list(vals or ()) + [1] * (3 - len(vals or ()))
     return (i64 * 3)(*[int(a) for a in v[:3]])
 
 
@@ -178,6 +179,13 @@ def esn_makeplan(type_, dim, nmodes, isign, ntransf, eps, prec, opts=None, strea
 
 def esn_setpts(plan, M, coord_prec, x, y=None, z=None):
     return lib().esn_setpts(plan, int(M), int(coord_prec), x, y, z)
+
+
+def esn_setpts3(plan, M, coord_prec, xs, N, ss):
+    xs = list(xs) + [None] * (3 - len(xs))
+    ss = list(ss) + [None] * (3 - len(ss))
+    return lib().esn_setpts3(plan, int(M), int(coord_prec), xs[0], xs[1], xs[2], int(N),
+                             ss[0], ss[1], ss[2])
 
 
 def esn_execute(plan, c, f):
@@ -430,6 +438,83 @@ class Plan:
         check(esn_interp(self.handle, vp(grid.data_ptr()), vp(c.data_ptr()) if c.numel() else None),
               "esn_interp")
         return c
+
+    def close(self):
+        if getattr(self, "handle", None):
+            esn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan3:
+    """A type 3 plan (eq. (3), Sec. 3.3) over torch CUDA tensors:
+    ``Plan3(dim, eps, dtype=torch.complex64, isign=+1, ntransf=1, **opts)``,
+    then ``setpts(sources, targets)`` (lists of dim coordinate tensors) and
+    ``execute(c)`` -> f at the N targets, f_k = sum_j c_j exp(isign i s_k.x_j).
+    Work is enqueued on torch's current stream."""
+
+    def __init__(self, dim, eps, dtype=None, isign=1, ntransf=1, **opts):
+        import torch
+        self.torch = torch
+        self.dim = int(dim)
+        self.dtype = dtype or torch.complex64
+        if self.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        self.prec = ESN_SINGLE if self.dtype == torch.complex64 else ESN_DOUBLE
+        self.isign = int(isign)
+        self.ntransf = int(ntransf)
+        self.opts = make_opts(**opts)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        st, h = esn_makeplan(3, self.dim, (1,) * self.dim, self.isign, self.ntransf, eps,
+                             self.prec, self.opts, _stream_handle(torch))
+        check(st, "esn_makeplan")
+        self.handle = h
+        self.M = self.N = None
+
+    def info(self) -> EsnInfo:
+        return esn_get_info(self.handle)
+
+    def setpts(self, sources, targets):
+        torch = self.torch
+        if len(sources) != self.dim or len(targets) != self.dim:
+            raise ValueError(f"need {self.dim} source and {self.dim} target coordinate arrays")
+        arrs = list(sources) + list(targets)
+        cdt = arrs[0].dtype
+        if cdt not in (torch.float32, torch.float64):
+            raise ValueError("coordinates must be float32 or float64")
+        M, N = sources[0].numel(), targets[0].numel()
+        for k, a in enumerate(arrs):
+            n = M if k < self.dim else N
+            if a.dtype != cdt or a.numel() != n or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("coordinates: same dtype, same length per set, contiguous, "
+                                 "on the GPU")
+        ptr = lambda a: vp(a.data_ptr()) if a.numel() else None
+        self.M = self.N = None   # a failed call leaves the plan without points
+        st = esn_setpts3(self.handle, M, ESN_SINGLE if cdt == torch.float32 else ESN_DOUBLE,
+                         [ptr(a) for a in sources], N, [ptr(a) for a in targets])
+        check(st, "esn_setpts3")
+        self.M, self.N = M, N
+        return self
+
+    def execute(self, c, out=None):
+        if self.M is None:
+            raise EsnError(ESN_ERR_NO_POINTS, "execute")
+        shp_c = (self.ntransf, self.M) if self.ntransf > 1 else (self.M,)
+        shp_f = (self.ntransf, self.N) if self.ntransf > 1 else (self.N,)
+        if c.dtype != self.dtype or not c.is_cuda or not c.is_contiguous() or \
+                c.numel() != self.ntransf * self.M:
+            raise ValueError(f"c: must be a contiguous {self.dtype} CUDA tensor of {shp_c}")
+        f = out if out is not None else self.torch.empty(shp_f, dtype=self.dtype,
+                                                         device=self.device)
+        st = esn_execute(self.handle, vp(c.data_ptr()) if c.numel() else None,
+                         vp(f.data_ptr()) if f.numel() else None)
+        check(st, "esn_execute")
+        return f
 
     def close(self):
         if getattr(self, "handle", None):

@@ -28,9 +28,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
-SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "serve.cpp",
+SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "type3.cpp", "serve.cpp",
            "kernels_sort.hip", "kernels_deconv.hip", "kernels_spread.hip",
-           "kernels_interp.hip", "kernels_mfma.hip"]
+           "kernels_interp.hip", "kernels_mfma.hip", "kernels_type3.hip"]
 
 
 # Per-source extra flags.  The matrix-core kernels keep their MFMA accumulators

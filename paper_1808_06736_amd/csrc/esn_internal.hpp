@@ -157,6 +157,44 @@ size_t mfma_interp_lds_bytes(const int* b);
 // kernel's per-point staging when staging is true).
 size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr, bool staging = true);
 
+// ---- type 3 (kernels_type3.hip, type3.cpp) ----
+// Per-point (sources) or per-target work of Sec. 3.3 on n values.
+struct T3Args {
+  int dim, isign, w;
+  int64_t n;
+  double x0[3], s0[3];          // centres of the sources and the targets
+  double inv_gam[3];            // 1 / gamma: sources x'' = (x - x0) / gamma
+  double hgam[3];               // h gamma: targets s'' = h gamma (s - s0)
+  double* out[3];               // rescaled coordinates (FP64, n each)
+};
+// Per-block (min, max) pairs of n coordinates into part[2 * t3_minmax_blocks(n)];
+// a NaN shows as the maximum.
+int t3_minmax_blocks(int64_t n);
+hipError_t launch_minmax(const void* x, int coord_prec, int64_t n, double* part, hipStream_t s);
+// Rescaled sources into a.out and prephase factors exp(isign i s0.(x - x0)) into pre.
+hipError_t launch_t3_sources(const T3Args& a, int coord_prec, int prec, const void* const* x,
+                             void* pre, hipStream_t s);
+// Rescaled targets into a.out and per-target factors (correction of step 3 times
+// the postphase exp(isign i s.x0)) into post; zq, wphi: the nq positive
+// quadrature nodes and weights times phi at the nodes.
+hipError_t launch_t3_targets(const T3Args& a, int coord_prec, int prec, const void* const* sx,
+                             const double* zq, const double* wphi, int nq, void* post,
+                             hipStream_t s);
+// out[t][i] = in[t][i] * fac[i], i < n, t < ntr (complex of precision prec).
+hipError_t launch_cmul(int prec, const void* in, const void* fac, void* out, int64_t n, int ntr,
+                       hipStream_t s);
+
+// Plan creation behind esn_makeplan for types 1 and 2; spread_only: no FFT
+// plans and no fine grid (a plan that sorts points and spreads into caller
+// grids, esn_spread).
+int make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntransf, double eps,
+              int prec, esn_plan* out, const esn_opts* opts, void* stream, bool spread_only);
+// Type 3 plans (type3.cpp).
+int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan* out,
+                const esn_opts* opts, void* stream);
+int t3_execute(esn_plan p, void* c, void* f);
+void t3_destroy(esn_plan p);
+
 // ---- rocFFT wrapper (fft.cpp) ----
 // In 3D only the x columns that hold modes (k1 mod n1 for k1 in I_N1, two
 // runs) need the FFTs along y and z: after the x pass of a type 1 transform the
@@ -258,6 +296,25 @@ struct esn_plan_s {
   int nsub = 0;
   int nbins_nonempty = 0;
   int32_t* h_pinned = nullptr;   // small pinned host buffer for read-backs
+  bool spread_only = false;      // no FFT plans or fine grid: sorts and spreads only
+
+  // type 3 (Sec. 3.3): a spread-only type 1 plan spreads the prephased,
+  // rescaled sources onto the type 3 fine grid; a type 2 plan with that grid
+  // as its modes (FFT order) evaluates it at the rescaled targets
+  esn_plan_s* t3_spread = nullptr;
+  esn_plan_s* t3_inner = nullptr;
+  int64_t t3_N = -1;             // targets (-1: no points yet)
+  int64_t t3_n[3] = {1, 1, 1};   // type 3 fine grid n_i, eq. (ng)
+  double t3_x0[3] = {0, 0, 0}, t3_s0[3] = {0, 0, 0}, t3_gam[3] = {1, 1, 1};
+  void* d_t3_pre = nullptr;      // [M] prephase factors (complex, plan precision)
+  void* d_t3_post = nullptr;     // [N] correction times postphase
+  void* d_t3_grid = nullptr;     // [ntransf][n1 n2 n3] spread grid = inner modes
+  void* d_t3_c = nullptr;        // [ntransf][M] prephased strengths
+  double* d_t3_xy = nullptr;     // [3][cap] rescaled coordinates (setpts scratch)
+  double* d_t3_q = nullptr;      // [2 nquad] quadrature nodes, weights * phi
+  double* d_t3_mm = nullptr;     // min/max partials
+  double* h_t3_mm = nullptr;     // pinned copy of the partials
+  int64_t t3_cap_M = 0, t3_cap_N = 0, t3_cap_grid = 0, t3_cap_xy = 0;
 
   // debug timing
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

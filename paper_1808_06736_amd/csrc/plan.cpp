@@ -187,7 +187,14 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
                             void* stream) {
   if (!out) return ESN_ERR_BAD_ARG;
   *out = nullptr;
-  if (type == 3) return ESN_ERR_UNSUPPORTED;
+  if (type == 3) return t3_makeplan(dim, isign, ntransf, eps, prec, out, opts, stream);
+  return esn::make_plan(type, dim, nmodes, isign, ntransf, eps, prec, out, opts, stream, false);
+}
+
+int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntransf, double eps,
+                   int prec, esn_plan* out, const esn_opts* opts, void* stream, bool spread_only) {
+  if (!out) return ESN_ERR_BAD_ARG;
+  *out = nullptr;
   if ((type != 1 && type != 2) || dim < 1 || dim > 3 || !nmodes || ntransf < 1 ||
       (isign != 1 && isign != -1))
     return ESN_ERR_BAD_ARG;
@@ -351,15 +358,19 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
     dfree(p, (void**)&d_q);
   }
 
-  // ---- fine grid and FFT plans ----
-  if (dalloc(p, &p->d_grid, gbytes * chunk) != ESN_OK) return fail(ESN_ERR_ALLOC);
-  rc = fft_make(&p->fft, dim, p->nf, p->N, type, chunk, prec, isign, s);
-  if (rc != ESN_OK) return fail(rc);
-  if (p->tail) {
-    rc = fft_make(&p->fft_tail, dim, p->nf, p->N, type, p->tail, prec, isign, s);
+  // ---- fine grid and FFT plans (none for a plan that only spreads into
+  // caller grids) ----
+  if (!spread_only) {
+    if (dalloc(p, &p->d_grid, gbytes * chunk) != ESN_OK) return fail(ESN_ERR_ALLOC);
+    rc = fft_make(&p->fft, dim, p->nf, p->N, type, chunk, prec, isign, s);
     if (rc != ESN_OK) return fail(rc);
+    if (p->tail) {
+      rc = fft_make(&p->fft_tail, dim, p->nf, p->N, type, p->tail, prec, isign, s);
+      if (rc != ESN_OK) return fail(rc);
+    }
+    p->device_bytes += (int64_t)(p->fft.work_bytes + p->fft_tail.work_bytes);
   }
-  p->device_bytes += (int64_t)(p->fft.work_bytes + p->fft_tail.work_bytes);
+  p->spread_only = spread_only;
 
   // ---- per-cell / per-bin arrays ----
   {
@@ -388,7 +399,7 @@ extern "C" int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign,
 
 extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
                           const void* z) {
-  if (!p || M < 0 || M > kMaxPoints) return ESN_ERR_BAD_ARG;
+  if (!p || p->type == 3 || M < 0 || M > kMaxPoints) return ESN_ERR_BAD_ARG;
   if (coord_prec != ESN_SINGLE && coord_prec != ESN_DOUBLE) return ESN_ERR_BAD_ARG;
   const void* xs[3] = {x, y, z};
   if (M > 0)
@@ -658,11 +669,15 @@ static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
 
 extern "C" int esn_execute(esn_plan p, void* c, void* f) {
   if (!p) return ESN_ERR_BAD_ARG;
+  if (p->type == 3) return t3_execute(p, c, f);
+  if (p->spread_only) return ESN_ERR_BAD_ARG;
   return execute_dir(p, p->type, c, f);
 }
 
 extern "C" int esn_execute_adjoint(esn_plan p, void* c, void* f) {
   if (!p) return ESN_ERR_BAD_ARG;
+  if (p->type == 3) return ESN_ERR_UNSUPPORTED;
+  if (p->spread_only) return ESN_ERR_BAD_ARG;
   return execute_dir(p, 3 - p->type, c, f);
 }
 
@@ -784,6 +799,7 @@ int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps
 extern "C" int esn_destroy(esn_plan p) {
   if (!p) return ESN_OK;
   (void)hipSetDevice(p->device);
+  if (p->type == 3) t3_destroy(p);
   destroy_all(p);
   delete p;
   return ESN_OK;

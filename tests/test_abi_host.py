@@ -102,8 +102,11 @@ def test_status_codes():
     assert _params(1e-6, N=(0, 1, 1))[0] == B.ESN_ERR_BAD_ARG
     st, _ = B.esn_choose_params(1e-6, B.ESN_DOUBLE, 1, (10, 1, 1), upsampfac=1.25)
     assert st == B.ESN_ERR_BAD_ARG
-    # type 3 is a valid request this build does not do; bad args fail before any GPU use
-    assert B.esn_makeplan(3, 1, (10,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_UNSUPPORTED
+    # bad args fail before any GPU use, type 3 ones included
+    assert B.esn_makeplan(4, 1, (10,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
+    assert B.esn_makeplan(3, 4, (10,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
+    assert B.esn_makeplan(3, 2, None, 0, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
+    assert B.esn_makeplan(3, 2, None, 1, 0, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
     assert B.esn_makeplan(1, 1, (10,), 0, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
     assert B.esn_makeplan(1, 1, (10,), 1, 0, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
     assert B.esn_makeplan(1, 1, (0,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
