@@ -133,6 +133,8 @@ def main():
 
     wl = I.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if wl.types == (3,):
+        return bench_type3(args, wl)
     dim, M, ntr = wl.dim, wl.M, wl.ntransf
     N = wl.N[:dim]
     prec = wl.prec
@@ -317,6 +319,92 @@ def main():
     for p in {id(p): p for p in plans.values()}.values():
         p.close()
     print(json.dumps(out))
+
+
+def bench_type3(args, wl):
+    """Type 3 (eq. (3)): a step is setpts (bounds, grid choice, rescaling, sorts of
+    the sources and of the targets, per-target factors) + execute (prephase,
+    spread, inner type 2, correction).  ``value`` counts sources + targets."""
+    import torch
+    from oracle import oracle as O
+    from paper_1808_06736_amd import binding as B
+    prec = wl.prec
+    cdt = torch.complex64 if prec == "f32" else torch.complex128
+    xs_np, ss_np, c_np = wl.coords(), wl.targets(), wl.strengths()
+    xs = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in xs_np]
+    ss = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in ss_np]
+    c_in = torch.from_numpy(c_np).cuda()
+    M, N = wl.M, len(ss_np[0])
+    p = B.Plan3(wl.dim, wl.eps, dtype=cdt, debug=1)
+    p.setpts(xs, ss)
+    out = torch.empty(N, dtype=cdt, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(rec=None):
+        p.setpts(xs, ss)
+        st_set = p.stats().t_setpts
+        p.execute(c_in, out)
+        if rec is not None:
+            s = p.stats()
+            rec.append((st_set, s.t_spread_or_interp, s.t_fft, s.t_deconv_or_amplify,
+                        s.t_execute))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    r = np.array(rec).mean(axis=0)
+    info = p.info()
+    nf = [int(info.nf[m]) for m in range(wl.dim)]
+    stages = {"setpts_ms": float(r[0]), "spread_ms": float(r[1]), "inner_type2_ms": float(r[2]),
+              "inner_interp_ms": float(r[3]), "execute_ms": float(r[4])}
+    # dominant kernel: step 1 spreading (M sources onto the type 3 grid) or the
+    # inner interpolation (N targets)
+    if r[1] >= r[3]:
+        kind, npts, dur, kname = "spread", M, r[1], "spread_mfma_kernel"
+    else:
+        kind, npts, dur, kname = "interp", N, r[3], "interp_mfma_kernel"
+    bytes_, flops = algorithmic_work(int(info.w), wl.dim, npts, 1, nf, prec, kind)
+    peak = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
+    roof = {"bound": "mfma", "achieved": flops / (dur * 1e-3) / 1e12, "peak": peak,
+            "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"traffic": None, "kernel": f"{kname}<{int(info.w)}>", "algorithmic_bytes": bytes_,
+                 "algorithmic_flops": flops, "mean_launch_ms": float(dur),
+                 "hbm_frac": bytes_ / (dur * 1e-3) / 1e9 / HBM_PEAK_GBS})
+    res = {
+        "metric": "NU points/sec (sources + targets), 3D type 3 at eps=1e-6",
+        "value": (M + N) / (elapsed / args.steps), "unit": "NU pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "dim": wl.dim, "M": M, "N_targets": N, "eps": wl.eps,
+                   "sources": "uniform in [-pi, pi)^3",
+                   "targets": f"uniform in [-{wl.extra['S']:g}, {wl.extra['S']:g})^3",
+                   "w": int(info.w), "type3_grid": nf,
+                   "step": "setpts (bounds, grid, rescaling, both sorts, factors) + execute"},
+        "stages": stages, "roofline": roof}
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample of targets (all sources)
+        nt = 64 if args.cpu_sample <= 0 else args.cpu_sample
+        idx = I.rng(7).choice(N, size=nt, replace=False)
+        t1 = time.perf_counter()
+        ref = O.type3(xs_np, c_np, [a[idx] for a in ss_np], 1)
+        dt = time.perf_counter() - t1
+        rate = nt * M / dt
+        res["cpu_baseline"] = {"value": (M + N) / (N * M / rate), "unit": "NU pts/s",
+                               "cores": O.default_threads(), "kind": "oracle",
+                               "sample": f"{nt} targets x {M} sources ({dt:.1f} s); scaled to "
+                                         f"all {N} targets of one step",
+                               "cpu": _cpu_model()}
+        res["parity"] = {"rel_l2": O.rel_l2(out.cpu().numpy()[idx], ref), "bar": 10 * wl.eps}
+    p.close()
+    print(json.dumps(res))
 
 
 def serve_bench(nreq, loads, nslots, seed=5):

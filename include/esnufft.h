@@ -204,7 +204,10 @@ typedef struct esn_info {
 int esn_get_info(esn_plan p, esn_info* out);
 
 typedef struct esn_stats {
-  /* milliseconds of the last setpts / execute, by stage (debug = 1 only) */
+  /* milliseconds of the last setpts / execute, by stage (debug = 1 only).
+   * Type 3 plans: t_spread_or_interp = spreading (step 1), t_fft = the inner
+   * type 2 transform (step 2), t_deconv_or_amplify = that transform's
+   * interpolation alone. */
   double t_setpts, t_spread_or_interp, t_fft, t_deconv_or_amplify, t_execute;
 } esn_stats;
 

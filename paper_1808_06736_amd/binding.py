@@ -479,6 +479,9 @@ class Plan3:
     def info(self) -> EsnInfo:
         return esn_get_info(self.handle)
 
+    def stats(self) -> EsnStats:
+        return esn_get_stats(self.handle)
+
     def setpts(self, sources, targets):
         torch = self.torch
         if len(sources) != self.dim or len(targets) != self.dim:

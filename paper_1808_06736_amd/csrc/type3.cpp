@@ -146,6 +146,14 @@ int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan*
     delete p;
     return ESN_ERR_ALLOC;
   }
+  if (o.debug) {
+    for (auto& e : p->ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        t3_destroy(p);
+        delete p;
+        return ESN_ERR_HIP;
+      }
+  }
   *out = p;
   return st;
 }
@@ -165,6 +173,7 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
   p->M = -1;
   p->t3_N = -1;
   const int dim = p->dim, w = p->par.w;
+  if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[5], st));
   const double sigma = p->opts.upsampfac;
 
   // ---- centres, half-widths, grid sizes and dilations (steps 0 and 1) ----
@@ -199,7 +208,6 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
     if (p->t3_inner) esn_destroy(p->t3_inner);
     p->t3_spread = p->t3_inner = nullptr;
     esn_opts o = p->opts;
-    o.debug = 0;
     o.modeord = 1;   // the inner type 2 reads the grid as modes in FFT order
     int64_t half[3] = {1, 1, 1};
     for (int m = 0; m < dim; m++) half[m] = n[m] / 2;   // its fine grid is then n
@@ -267,6 +275,13 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
   if (rc != ESN_OK) return rc;
   p->M = M;
   p->t3_N = N;
+  if (p->opts.debug) {
+    ESN_HIP(hipEventRecord(p->ev[0], st));
+    ESN_HIP(hipEventSynchronize(p->ev[0]));
+    float ms = 0;
+    ESN_HIP(hipEventElapsedTime(&ms, p->ev[5], p->ev[0]));
+    p->stats.t_setpts = ms;
+  }
   return ESN_OK;
 }
 
@@ -276,15 +291,32 @@ int t3_execute(esn_plan p, void* c, void* f) {
   ESN_HIP(hipSetDevice(p->device));
   hipStream_t st = p->stream;
   if (p->t3_N == 0) return p->warn;
+  const bool dbg = p->opts.debug != 0;
+  if (dbg) ESN_HIP(hipEventRecord(p->ev[0], st));
   // step 1: prephased strengths spread onto the type 3 grid
   ESN_HIP(launch_cmul(p->prec, c, p->d_t3_pre, p->d_t3_c, p->M, p->ntransf, st));
+  if (dbg) ESN_HIP(hipEventRecord(p->ev[1], st));
   int rc = esn_spread(p->t3_spread, p->d_t3_c, p->d_t3_grid);
   if (rc >= 2) return rc;
+  if (dbg) ESN_HIP(hipEventRecord(p->ev[2], st));
   // step 2: the grid as Fourier coefficients, evaluated at the rescaled targets
   rc = esn_execute(p->t3_inner, f, p->d_t3_grid);
   if (rc >= 2) return rc;
+  if (dbg) ESN_HIP(hipEventRecord(p->ev[3], st));
   // step 3: correction and postphase
   ESN_HIP(launch_cmul(p->prec, f, p->d_t3_post, f, p->t3_N, p->ntransf, st));
+  if (dbg) {
+    ESN_HIP(hipEventRecord(p->ev[4], st));
+    ESN_HIP(hipEventSynchronize(p->ev[4]));
+    float sp = 0, in = 0, tot = 0;
+    ESN_HIP(hipEventElapsedTime(&sp, p->ev[1], p->ev[2]));
+    ESN_HIP(hipEventElapsedTime(&in, p->ev[2], p->ev[3]));
+    ESN_HIP(hipEventElapsedTime(&tot, p->ev[0], p->ev[4]));
+    p->stats.t_spread_or_interp = sp;   // step 1 spreading
+    p->stats.t_fft = in;                // step 2: the inner type 2 transform
+    p->stats.t_deconv_or_amplify = p->t3_inner->stats.t_spread_or_interp;   // its interpolation
+    p->stats.t_execute = tot;
+  }
   return p->warn;
 }
 

@@ -179,6 +179,14 @@ class Workload:
         shape = (self.ntransf, self.M) if self.ntransf > 1 else (self.M,)
         return complex_normal(shape, self.seed + 1000, dt)
 
+    def targets(self, dtype=None):
+        """Type 3 target frequencies: iid uniform in [-S, S)^d (extra['S'],
+        extra['targets'] of them)."""
+        dt = dtype or (np.float32 if self.prec == "f32" else np.float64)
+        g = rng(self.seed + 3000)
+        S = float(self.extra["S"])
+        return [g.uniform(-S, S, int(self.extra["targets"])).astype(dt) for _ in range(self.dim)]
+
     def coefficients(self):
         dt = np.complex64 if self.prec == "f32" else np.complex128
         Nrev = tuple(reversed(self.N[: self.dim]))        # slowest first
@@ -186,8 +194,8 @@ class Workload:
         return complex_normal(shape, self.seed + 2000, dt)
 
 
-# The named workloads: a small 1D case, the large 2D and 3D cases, the batched
-# radial 2D case.  (The serving mix draws its requests in serve_mix below.)
+# The named workloads: a small 1D case, the large 2D and 3D cases, a 3D type 3
+# case, the batched radial 2D case.  (The serving mix draws its requests in serve_mix below.)
 WORKLOADS = {
     "1d_t1_small": Workload("1d_t1_small", 1, (1,), (1000, 1, 1), 10_000, 1e-6,
                             "f64", "uniform", seed=1),
@@ -198,6 +206,10 @@ WORKLOADS = {
     "3d_clustered": Workload("3d_clustered", 3, (1, 2), (128, 128, 128),
                              10_000_000, 1e-6, "f32", "wrapped_gaussian", seed=3,
                              extra={"sigma": 0.3}),
+    # type 3: sources iid uniform in [-pi, pi)^3, target frequencies iid uniform
+    # in [-32, 32)^3 (space-frequency product X S = 32 pi per dimension)
+    "3d_type3": Workload("3d_type3", 3, (3,), (1, 1, 1), 10_000_000, 1e-6, "f32",
+                         "uniform", seed=6, extra={"targets": 10_000_000, "S": 32.0}),
     "2d_t2_batched_radial": Workload("2d_t2_batched_radial", 2, (2,),
                                      (256, 256, 1), 400 * 512, 1e-4, "f32",
                                      "radial", ntransf=32, seed=4,
