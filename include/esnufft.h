@@ -1,5 +1,5 @@
 /*
- * esnufft — type 1 and type 2 nonuniform FFTs on one AMD MI355X (gfx950) GPU
+ * esnufft — type 1, 2 and 3 nonuniform FFTs on one AMD MI355X (gfx950) GPU
  * with the "exponential of semicircle" (ES) spreading kernel.
  *
  * The transforms approximate, to a requested relative tolerance eps, the
@@ -9,6 +9,9 @@
  *
  *   type 1 (eq. (1)):  f_k = sum_{j=1..M} c_j exp(isign * i k.x_j),  k in I
  *   type 2 (eq. (2)):  c_j = sum_{k in I} f_k exp(isign * i k.x_j),  j = 1..M
+ *   type 3 (eq. (3)):  f_k = sum_{j=1..M} c_j exp(isign * i s_k.x_j), k = 1..N
+ *                      (any real sources x_j and target frequencies s_k; see
+ *                      esn_setpts3)
  *
  * with d = 1, 2 or 3, mode set I = I_{N1} x ... x I_{Nd},
  * I_N = {-floor(N/2), ..., -floor(N/2) + N - 1}, points x_j anywhere in
@@ -126,10 +129,11 @@ typedef struct esn_plan_s* esn_plan;
 
 /* Make a plan for ntransf transforms of one type that share one point set
  * (Sec. 2, remark on repeated small problems: a plan stage and multiple
- * inputs).  type 1 or 2; dim 1..3; nmodes host[3] (N_i >= 1); isign +1/-1;
- * ntransf >= 1; prec ESN_SINGLE/ESN_DOUBLE; opts may be NULL (defaults);
- * stream is a hipStream_t or NULL.  Computes the correction factors p_k
- * (eqs. (pk1), (quad), (pk)) on the GPU in FP64 and builds the rocFFT plan.
+ * inputs).  type 1, 2 or 3; dim 1..3; nmodes host[3] (N_i >= 1; not read
+ * for type 3); isign +1/-1; ntransf >= 1; prec ESN_SINGLE/ESN_DOUBLE; opts
+ * may be NULL (defaults); stream is a hipStream_t or NULL.  Types 1 and 2:
+ * computes the correction factors p_k (eqs. (pk1), (quad), (pk)) on the GPU
+ * in FP64 and builds the rocFFT plan; type 3 sizes its grids in esn_setpts3.
  * Synchronises the stream before returning.  *out is NULL on error. */
 int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntransf,
                  double eps, int prec, esn_plan* out, const esn_opts* opts,
