@@ -22,6 +22,26 @@ struct Coord {
   T f;
 };
 
+// Window shift sh in {0, 1} of a coordinate whose offset in its cell is
+// fr 2^-fbits (fixed point) or f (FP64): w even: f > 0; w odd: f > 1/2 (see
+// the window comment below), decided exactly on the stored bits.
+__host__ __device__ __forceinline__ int window_shift_fixed(uint32_t fr, int fbits, int w) {
+  return (w & 1) ? (fr > (1u << (fbits - 1)) ? 1 : 0) : (fr != 0u ? 1 : 0);
+}
+__host__ __device__ __forceinline__ int window_shift_f64(double f, int w) {
+  return (w & 1) ? (f > 0.5 ? 1 : 0) : (f > 0.0 ? 1 : 0);
+}
+
+// Window cell of a coordinate: c + sh wrapped into [0, n).  Its window starts
+// floor(w/2) cells before it, so points are binned by it: a bin's windows all
+// start in the bin's cells moved back by floor(w/2).  (c = n - 1 with sh = 1
+// wraps to 0; the window n - floor(w/2) .. is then taken as -floor(w/2) ..,
+// the same cells of the periodic grid.)
+__host__ __device__ __forceinline__ int window_cell(int cell, int sh, int64_t n) {
+  const int k = cell + sh;
+  return k >= n ? k - (int)n : k;
+}
+
 // Coordinate m of sorted point i from its record.
 template <typename T>
 __device__ __forceinline__ Coord<T> decode_coord(const unsigned char* pts, int code, int fbits,
@@ -35,17 +55,14 @@ __device__ __forceinline__ Coord<T> decode_coord(const unsigned char* pts, int c
     // the fraction fr * 2^-fbits (exact in float when fbits <= 24)
     if constexpr (sizeof(T) == 4) r.f = ldexpf((float)fr, -fbits);
     else r.f = ldexp((double)fr, -fbits);
-    // window shift sh (see the window comment below), decided on the exact bits
-    if (w & 1) *sh_out = fr > (1u << (fbits - 1)) ? 1 : 0;
-    else *sh_out = fr != 0u ? 1 : 0;
+    *sh_out = window_shift_fixed(fr, fbits, w);
   } else {
     const double t = reinterpret_cast<const double*>(pts + i * 32)[m];
     const double c = floor(t);
     const double f = t - c;                      // exact in FP64
     r.cell = (int)c;
     r.f = (T)f;
-    if (w & 1) *sh_out = f > 0.5 ? 1 : 0;
-    else *sh_out = f > 0.0 ? 1 : 0;
+    *sh_out = window_shift_f64(f, w);
   }
   return r;
 }

@@ -84,6 +84,8 @@ struct SortArgs {
   int b[3], nb[3], fbits[3];
   int pts_code;
   int chkbnds;
+  int w;                    // kernel width (decides each point's window cell)
+  int blocked;              // 3D cell order by 2 x 2 column blocks (even b[0], b[1])
   uint32_t* key;            // [M] cell key of each point
   int32_t* slot;            // [M] rank of the point within its cell (counting sort)
   int32_t* count;           // [ncells + 1] points per cell (counting sort)

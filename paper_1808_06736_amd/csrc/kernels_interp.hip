@@ -56,7 +56,7 @@ interp_lds_kernel(const GeomArgs g, const T* __restrict__ grid, cplx_t<T>* __res
     for (int m = 0; m < D; m++) {
       int sh;
       Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
-      L[m] = cd.cell - bi[m] * g.b[m] + sh;
+      L[m] = window_cell(cd.cell, sh, g.n[m]) - bi[m] * g.b[m];
       es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
     }
     const int64_t orig = point_perm(g.pts, g.pts_code, j);

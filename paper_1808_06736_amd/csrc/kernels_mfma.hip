@@ -2,11 +2,16 @@
 // w <= 7), one wave per subproblem (a run of at most maxsub bin-sorted points
 // of one bin, Sec. 4.2).
 //
-// Within a bin the points are sorted by column (x, y cell) and then by z cell.
-// Every point of a column has its window inside the 8 x 8 footprint of cells
-// x_c - floor(w/2) .. x_c - floor(w/2) + 7 (same for y), and every point of
-// one cell inside the 8 planes from z_c - floor(w/2).  Spreading the points of
-// a column, eq. (bl), is then a dense contraction over the points,
+// Points are binned by window cell (the cell floor(w/2) after the first cell
+// of the point's window), so a point in window cell l has its w window cells
+// at l - floor(w/2) .. l - floor(w/2) + w - 1.  Two neighbouring window cells
+// 2j, 2j + 1 then have all their windows inside the 8 cells from
+// 2j - floor(w/2): a point of cell 2j + (l & 1) puts its weights at slots
+// (l & 1) .. (l & 1) + w - 1 of that 8-wide footprint.  Within a bin the
+// points are sorted by 2 x 2 block of (x, y) columns and then by z cell, so
+// every such block is a run of sorted points sharing one 8 x 8 footprint.
+// Spreading the points of a column block, eq. (bl), is then a dense
+// contraction over the points,
 //
 //     B[(z, x), (y, re/im)] = sum_p  kz_p(z) kx_p(x)  *  ky_p(y) c_p,
 //
@@ -14,20 +19,20 @@
 // strength.  The wave runs it with v_mfma_f32_16x16x4_f32: the 64 rows are
 // four 16-row tiles (two z planes x 8 x cells each), each instruction takes 4
 // points.  The 8 planes form a ring (tile-relative plane r -> slot r mod 8):
-// once the wave moves on to a later z cell of the column, the planes below it
-// receive nothing more, so they are added into the wave's LDS tile of the bin
-// (bin + 7 cells per dim) and their slots reused; a plane lives in half the
-// lanes of one row tile, so this costs 4 read-modify-writes on those lanes.
-// The wave owns the tile, so these adds are plain read-modify-writes; the tile
-// goes to the fine grid once at the end (global atomics on the touched cells
-// only).
+// once the wave moves on to a later pair of z cells of the block, the planes
+// below it receive nothing more, so they are added into the wave's LDS tile
+// of the bin (bin + 6 cells per dim) and their slots reused; a plane lives in
+// half the lanes of one row tile, so this costs 4 read-modify-writes on those
+// lanes.  The wave owns the tile, so these adds are plain read-modify-writes;
+// the tile goes to the fine grid once at the end (global atomics on the
+// touched cells only).
 //
 // Interpolation, eq. (interp), runs the same contraction the other way: for
-// the points of one cell, T[z, p] = sum_(x,y) B[z, (x, y)] kx_p(x) ky_p(y) on
-// the matrix cores (8 planes (re, im) x 64 footprint cells x 16 points), then
-// c_p = sum_z kz_p(z) T[z, p] in registers and across the four lane groups
-// that hold a point's planes, with the bin's grid tile (bin + 7 cells per
-// dim) copied into LDS first.
+// the points of one 2 x 2 x 2 block of window cells, T[z, p] = sum_(x,y)
+// B[z, (x, y)] kx_p(x) ky_p(y) on the matrix cores (8 planes (re, im) x 64
+// footprint cells x 16 points), then c_p = sum_z kz_p(z) T[z, p] in registers
+// and across the four lane groups that hold a point's planes, with the bin's
+// grid tile (bin + 6 cells per dim) copied into LDS first.
 #include "device_common.hpp"
 
 namespace esn {
@@ -123,19 +128,19 @@ constexpr int kSpreadStage = 80;
 // row 79; rows past the batch only feed output columns that are not stored.
 constexpr int kInterpRows = 80;
 
-// LDS layouts.  Both start with the bin tile (bin + 7 cells per dim, planes of
+// LDS layouts.  Both start with the bin tile (bin + 6 cells per dim, planes of
 // plane_floats) and end with the wrapped grid offsets of the tile's z planes
 // (int64), per-point ints and the offsets of the tile's x and y lines.
 // Spreading stages [67][8] x and z weights and [67][16] B operands;
 // interpolation [64][8] x and y weights, [80][8] z weights and a float2 result
 // per point.
 static inline size_t mfma_tail_bytes(const int* b, int nint) {
-  const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
+  const size_t T0 = b[0] + 6, T1 = b[1] + 6, T2 = b[2] + 6;
   return T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) + (T0 + T1) * sizeof(int);
 }
 
 static inline size_t mfma_tile_bytes(const int* b) {
-  const size_t T0 = b[0] + 7, T1 = b[1] + 7, T2 = b[2] + 7;
+  const size_t T0 = b[0] + 6, T1 = b[1] + 6, T2 = b[2] + 6;
   return T2 * plane_floats((int)T0, (int)T1) * sizeof(float);
 }
 
@@ -188,6 +193,26 @@ struct TileWalk {
   }
 };
 
+// Kernel values k[0 .. w-1] of one fixed-point coordinate q (fbits fraction
+// bits) at its window cells, and its window cell relative to the bin origin o
+// (in [0, b)); the window shift is decided on the exact fraction bits, as
+// everywhere else.
+template <int W>
+__device__ __forceinline__ int window_weights(uint32_t q, int fbits, int n, int o, float bl,
+                                              float* k) {
+  const uint32_t fr = q & ((1u << fbits) - 1u);
+  const int sh = window_shift_fixed(fr, fbits, W);
+  es_weights_hw<W>(sh, ldexpf((float)fr, -fbits), bl, k);
+  return window_cell((int)(q >> fbits), sh, n) - o;
+}
+
+// Window cell of a fixed-point coordinate relative to the bin origin o.
+template <int W>
+__device__ __forceinline__ int rel_window_cell(uint32_t q, int fbits, int n, int o) {
+  return window_cell((int)(q >> fbits), window_shift_fixed(q & ((1u << fbits) - 1u), fbits, W),
+                     n) - o;
+}
+
 // Two waves per subproblem share the bin tile and the staged weights.  Wave
 // wv accumulates row tiles 2 wv and 2 wv + 1, i.e. ring slots 4 wv .. 4 wv + 3;
 // a tile plane always lives in the same ring slot (plane r -> slot r mod 8),
@@ -200,7 +225,8 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   constexpr int H = W / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b0 = g.b[0], b1 = g.b[1], b2 = g.b[2];
-  const int T0 = b0 + 7, T1 = b1 + 7, T2 = b2 + 7;   // 8-wide footprints for every w
+  // 8-wide footprints from even window cells of the bin (even bin sizes)
+  const int T0 = b0 + 6, T1 = b1 + 6, T2 = b2 + 6;
   const int tc = T0 * T1 * T2;
   const int ps = plane_floats(T0, T1);               // floats per tile plane
   constexpr int NS = kSpreadStage;
@@ -292,17 +318,11 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
       float k[W], v[8];
       if (wv == 0) {
         // x weights by footprint slot, z weights by ring slot
-        uint32_t fr = r0.x & ((1u << g.fbits[0]) - 1u);
-        // window shift decided on the exact fraction bits (see decode_coord)
-        int sh = (W & 1) ? (fr > (1u << (g.fbits[0] - 1))) : (fr != 0u);
-        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[0]), bl, k);
-        slots8<W>(k, sh, v);
+        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, k);
+        slots8<W>(k, lx & 1, v);
         store8(skx + lane * 8, v);
-        fr = r0.z & ((1u << g.fbits[2]) - 1u);
-        sh = (W & 1) ? (fr > (1u << (g.fbits[2] - 1))) : (fr != 0u);
-        const int zr = (int)(r0.z >> g.fbits[2]) - bz0;
-        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[2]), bl, k);
-        slots8<W>(k, sh, v);   // planes zr .. zr + 7 of the tile
+        const int zr = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, k);
+        slots8<W>(k, 0, v);    // planes zr .. zr + 7 of the tile
         rotate8(v, zr & 7);    // -> ring slots
         float vz[8];
 #pragma unroll
@@ -313,38 +333,37 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
         store8(skz + lane * 8, vz);
       } else {
         // B operand: y weight times strength, column 2 y + (re, im)
-        const uint32_t fr = r0.y & ((1u << g.fbits[1]) - 1u);
-        const int sh = (W & 1) ? (fr > (1u << (g.fbits[1] - 1))) : (fr != 0u);
-        es_weights_hw<W>(sh, ldexpf((float)fr, -g.fbits[1]), bl, k);
-        slots8<W>(k, sh, v);
+        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, k);
+        slots8<W>(k, ly & 1, v);
         float4* b4 = reinterpret_cast<float4*>(sb + lane * 16);
 #pragma unroll
         for (int i = 0; i < 4; i++)
           b4[i] = make_float4(v[2 * i] * cc0.x, v[2 * i] * cc0.y, v[2 * i + 1] * cc0.x,
                               v[2 * i + 1] * cc0.y);
-        scol[lane] = ((int)(r0.x >> g.fbits[0]) - bx0) + b0 * ((int)(r0.y >> g.fbits[1]) - by0);
-        szr[lane] = (int)(r0.z >> g.fbits[2]) - bz0;
+        const int lx = rel_window_cell<W>(r0.x, g.fbits[0], n0, bx0);
+        scol[lane] = (lx >> 1) + b0 * (ly >> 1);
+        szr[lane] = rel_window_cell<W>(r0.z, g.fbits[2], n2, bz0);
       }
     }
     r0 = r1;
     r1 = r2;
     cc0 = cc1;
     __syncthreads();
-    // runs of points with the same column and z cell
-    const bool starts = lane < nbatch &&
-                        (lane == 0 || szr[lane] != szr[lane - 1] || scol[lane] != scol[lane - 1]);
+    // runs of points with the same column block and pair of z cells
+    const bool starts = lane < nbatch && (lane == 0 || (szr[lane] >> 1) != (szr[lane - 1] >> 1) ||
+                                          scol[lane] != scol[lane - 1]);
     uint64_t runs = __ballot(starts);
     while (runs) {
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
       const int col = scol[q0];
-      const int zr = szr[q0];
+      const int zr = szr[q0] & ~1;   // the run's planes: zr .. zr + 7
       if (col != cur) {
         if (cur >= 0) flush(0xffu);
         cur = col;
         const int clx = col % b0, cly = col / b0;
-        colbase = ((cly + yl) * T0 + clx + x0) * 2 + reim;
+        colbase = ((2 * cly + yl) * T0 + 2 * clx + x0) * 2 + reim;
         pend = zr;
       } else if (zr > pend) {
         // planes pend .. zr - 1 receive nothing more
@@ -412,22 +431,10 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   }
 }
 
-// Weights of one coordinate at the 8 footprint slots from its fixed-point
-// value q (fbits fraction bits): the window shift is decided on the exact
-// fraction bits, as everywhere else.
-template <int W>
-__device__ __forceinline__ void slot_weights(uint32_t q, int fbits, float bl, float* v) {
-  const uint32_t fr = q & ((1u << fbits) - 1u);
-  const int sh = (W & 1) ? (fr > (1u << (fbits - 1))) : (fr != 0u);
-  float k[W];
-  es_weights_hw<W>(sh, ldexpf((float)fr, -fbits), bl, k);
-  slots8<W>(k, sh, v);
-}
-
 // Two waves per subproblem share the grid tile and the staged weights: in
 // each batch wave 0 computes the x and y weights and wave 1 the z weights and
 // each point's footprint origin in the tile; the waves then take alternate
-// runs (points of one cell).
+// runs (points of one 2 x 2 x 2 block of window cells).
 //
 // Matrix layout of a step (16 points q .. q + 15 of a run):
 //   A[m][k] = G[x, y, z(m), re/im(m)]   grid tile, m = lane & 15, k = lane >> 4,
@@ -445,7 +452,8 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   constexpr int H = W / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b0 = g.b[0], b1 = g.b[1], b2 = g.b[2];
-  const int T0 = b0 + 7, T1 = b1 + 7, T2 = b2 + 7;   // 8-wide footprints for every w
+  // 8-wide footprints from even window cells of the bin (even bin sizes)
+  const int T0 = b0 + 6, T1 = b1 + 6, T2 = b2 + 6;
   const int tc = T0 * T1 * T2;
   const int ps = plane_floats(T0, T1);               // floats per tile plane
   float* gtf = reinterpret_cast<float*>(smem_raw);                 // [T2][ps]: [T1][T0][2]
@@ -512,19 +520,24 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
     {
       float v[8];
       if (wv == 0) {
-        slot_weights<W>(r0.x, g.fbits[0], bl, v);
+        float k[W];
+        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, k);
+        slots8<W>(k, lx & 1, v);
         store8(skx + lane * 8, v);
-        slot_weights<W>(r0.y, g.fbits[1], bl, v);
+        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, k);
+        slots8<W>(k, ly & 1, v);
         store8(sky + lane * 8, v);
       } else {
-        slot_weights<W>(r0.z, g.fbits[2], bl, v);
+        float k[W];
+        const int lz = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, k);
+        slots8<W>(k, lz & 1, v);
         store8(skz + lane * 8, v);
-        // footprint origin of the point's cell: tile cell (lx, ly, lz), since the
-        // tile starts H cells before the bin
-        const int lx = (int)(r0.x >> g.fbits[0]) - bx0;
-        const int ly = (int)(r0.y >> g.fbits[1]) - by0;
-        const int lz = (int)(r0.z >> g.fbits[2]) - bz0;
-        sorg[lane] = lz * ps + 2 * (ly * T0 + lx);
+        // footprint origin of the point's 2 x 2 x 2 block of window cells:
+        // tile cell (lx & ~1, ly & ~1, lz & ~1), since the tile starts H cells
+        // before the bin
+        const int lx = rel_window_cell<W>(r0.x, g.fbits[0], n0, bx0);
+        const int ly = rel_window_cell<W>(r0.y, g.fbits[1], n1, by0);
+        sorg[lane] = (lz & ~1) * ps + 2 * ((ly & ~1) * T0 + (lx & ~1));
         sperm[lane] = (int)r0.w;
       }
     }

@@ -2,10 +2,12 @@
 // spreading (Sec. 4.2).
 //
 //   sort_keys : fold each coordinate into [0, 2pi), rescale to fine-grid units
-//               t = x n / 2pi (FP64), take the cell floor(t); write the cell
-//               key and the point's record (coordinates and index) in input
+//               t = x n / 2pi (FP64), take the window cell floor(t) + sh (the
+//               cell floor(w/2) after the window start); write the cell key
+//               and the point's record (coordinates and index) in input
 //               order.  Cells are numbered bin-major, so every bin (and, in
-//               3D, every column of a bin) is a run of keys.
+//               3D, every column or 2 x 2 column block of a bin) is a run of
+//               keys.
 //   sort      : stable LSD radix sort of the records by key (rocPRIM), so
 //               points of one cell keep their input order.
 //   ends      : where the sorted keys move on to another bin gives that bin's
@@ -41,8 +43,9 @@ __device__ __forceinline__ double fold_rescale(double x, int64_t n) {
   return t;
 }
 
-// Encode t for storage; returns the cell floor(t) that the stored value decodes to.
-__device__ __forceinline__ int encode_t(double t, int64_t n, int code, int fbits,
+// Encode t for storage; returns the window cell (c + sh wrapped into [0, n),
+// see window_cell) of the stored value.
+__device__ __forceinline__ int encode_t(double t, int64_t n, int code, int fbits, int w,
                                         uint32_t* q_out, double* t_out) {
   if (code == kPtsFixed32) {
     // n 2^fbits <= 2^32, so the rounded value (ties to even) is an exact
@@ -52,10 +55,12 @@ __device__ __forceinline__ int encode_t(double t, int64_t n, int code, int fbits
     if (v >= span) v -= span;
     const uint32_t q = (uint32_t)v;
     *q_out = q;
-    return (int)(q >> fbits);
+    return window_cell((int)(q >> fbits), window_shift_fixed(q & ((1u << fbits) - 1u), fbits, w),
+                       n);
   }
   *t_out = t;
-  return (int)floor(t);
+  const double c = floor(t);
+  return window_cell((int)c, window_shift_f64(t - c, w), n);
 }
 
 template <typename CTy>
@@ -64,7 +69,11 @@ __device__ __forceinline__ double load_coord(const void* p, int64_t j) {
 }
 
 // Cell key of a point with coordinates xs[0 .. dim-1] (see SortArgs); also
-// returns the encoded coordinates.
+// returns the encoded coordinates.  Cells are window cells.  In 3D the cells
+// of a bin are ordered by z within each (x, y) column; with a.blocked the
+// columns come in 2 x 2 blocks and a block's four columns are merged in z
+// order (cell (lx, ly, lz) at 4 (lz + b2 (block)) + 2 (ly & 1) + (lx & 1)),
+// so that each block's points with z cells 2j, 2j + 1 are one run.
 __device__ __forceinline__ int point_key_of(const SortArgs& a, const double* xs, int* flag,
                                             uint32_t* q, double* t) {
   int cell[3] = {0, 0, 0};
@@ -75,15 +84,22 @@ __device__ __forceinline__ int point_key_of(const SortArgs& a, const double* xs,
     if (!isfinite(x)) *flag |= 1;
     else if (a.chkbnds && fabs(x) > kThreePi) *flag |= 2;
     const double tt = isfinite(x) ? fold_rescale(x, a.n[m]) : 0.0;
-    cell[m] = encode_t(tt, a.n[m], a.pts_code, a.fbits[m], &q[m], &t[m]);
+    cell[m] = encode_t(tt, a.n[m], a.pts_code, a.fbits[m], a.w, &q[m], &t[m]);
   }
   const int bx = cell[0] / a.b[0], by = cell[1] / a.b[1], bz = cell[2] / a.b[2];
   const int lx = cell[0] - bx * a.b[0], ly = cell[1] - by * a.b[1], lz = cell[2] - bz * a.b[2];
   const int bin = bx + a.nb[0] * (by + a.nb[1] * bz);
   const int cpb = a.b[0] * a.b[1] * a.b[2];
   int local;
-  if (a.dim == 3) local = lz + a.b[2] * (lx + a.b[0] * ly);
-  else local = lx + a.b[0] * ly;
+  if (a.dim == 3) {
+    if (a.blocked)
+      local = (lx & 1) + 2 * (ly & 1) +
+              4 * (lz + a.b[2] * ((lx >> 1) + (a.b[0] >> 1) * (ly >> 1)));
+    else
+      local = lz + a.b[2] * (lx + a.b[0] * ly);
+  } else {
+    local = lx + a.b[0] * ly;
+  }
   return bin * cpb + local;
 }
 

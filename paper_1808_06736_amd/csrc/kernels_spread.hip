@@ -68,7 +68,7 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
       for (int m = 0; m < D; m++) {
         int sh;
         Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
-        st->loc[lane][m] = cd.cell - bi[m] * g.b[m] + sh;
+        st->loc[lane][m] = window_cell(cd.cell, sh, g.n[m]) - bi[m] * g.b[m];
         es_weights_t<W, T>(sh, cd.f, beta, st->ker[lane][m]);
       }
       const int64_t orig = point_perm(g.pts, g.pts_code, j);

@@ -281,9 +281,10 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   p->block = o.block > 0 ? o.block : 256;
   const bool tile_fits = tile_lds_bytes(prec, dim, w, p->bin, 1) <= budget;
   // matrix-core spreading / interpolation: 3D single precision, w <= 7,
-  // fixed-point coordinates, one transform per launch (method 3)
+  // fixed-point coordinates, even bin sizes, one transform per launch (method 3)
   const bool mfma_ok = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
-                       p->pts_code == kPtsFixed32 &&
+                       p->pts_code == kPtsFixed32 && p->bin[0] % 2 == 0 &&
+                       p->bin[1] % 2 == 0 && p->bin[2] % 2 == 0 &&
                        mfma_spread_lds_bytes(w, p->bin) <= budget &&
                        mfma_interp_lds_bytes(p->bin) <= budget;
   p->spread_method = o.spread_method ? o.spread_method : (mfma_ok ? 3 : (tile_fits ? 1 : 2));
@@ -461,6 +462,8 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   }
   a.pts_code = p->pts_code;
   a.chkbnds = p->opts.chkbnds;
+  a.w = p->par.w;
+  a.blocked = p->dim == 3 && p->bin[0] % 2 == 0 && p->bin[1] % 2 == 0;
   a.key = p->d_key[0];
   a.slot = p->d_slot;
   a.count = p->d_count;

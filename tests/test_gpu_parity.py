@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_1808_06736_amd import binding as B
 from paper_1808_06736_amd import inputs as I
 from tests.gpu_helpers import coord_np, run_type1, run_type2
 
@@ -166,3 +167,52 @@ def test_matrix_core_matches_lds_tiles_on_many_small_problems(type_):
                 outs[m], _ = run_type2(coords, f, N, eps, "f32", interp_method=m)
         err = O.rel_l2(outs[3], outs[1])
         assert err < 1e-5, (N, M, points, eps, err)
+
+
+SEAM_CASES = [
+    # dim, N, prec, eps, method (0 = automatic)
+    (3, (16, 20, 24), "f32", 1e-6, 3),
+    (3, (16, 20, 24), "f32", 1e-6, 1),
+    (3, (13, 9, 11), "f64", 1e-9, 0),
+    (2, (30, 17), "f32", 1e-5, 0),
+    (1, (45,), "f64", 1e-12, 0),
+]
+
+
+@pytest.mark.parametrize("case", SEAM_CASES, ids=[f"{c[0]}d-{c[2]}-m{c[4]}" for c in SEAM_CASES])
+@pytest.mark.parametrize("type_", [1, 2])
+def test_points_at_the_fine_grid_seam(case, type_):
+    """Points in the last and first fine-grid cells of every dimension (x just
+    below and just above 0, i.e. t near n and near 0 after the fold): those in
+    the upper half of cell n - 1 have their window start wrap past n and are
+    binned with the first cells.  Every method meets the bar there."""
+    dim, N, prec, eps, method = case
+    st, par = B.esn_choose_params(eps, B.ESN_SINGLE if prec == "f32" else B.ESN_DOUBLE, dim,
+                                  tuple(N) + (1,) * (3 - dim))
+    assert st == 0
+    rng = np.random.default_rng(77 + dim)
+    M = 6000
+    dt = np.float32 if prec == "f32" else np.float64
+    coords = []
+    for m in range(dim):
+        h = 2 * np.pi / par.nf[m]
+        x = rng.uniform(-h, h, M)
+        x[: M // 4] = rng.uniform(-np.pi, np.pi, M // 4)   # some spread-out points too
+        coords.append(x.astype(dt))
+    coords = [np.ascontiguousarray(a) for a in coords]
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    opts = {}
+    if type_ == 1:
+        if method:
+            opts["spread_method"] = method
+        c = I.complex_normal(M, 78, cdt)
+        f, _ = run_type1(coords, c, N, eps, prec, **opts)
+        err = O.rel_l2(f, O.type1(coord_np(coords, prec), c, +1, N=N))
+    else:
+        if method:
+            opts["interp_method"] = method
+        f = I.complex_normal(int(np.prod(N)), 79, cdt).reshape(tuple(reversed(N)))
+        c, _ = run_type2(coords, f, N, eps, prec, **opts)
+        err = O.rel_l2(c, O.type2(coord_np(coords, prec), f, -1))
+    print(f"seam {dim}d {prec} method {method} type {type_}: rel l2 {err:.2e}")
+    assert err <= 10 * eps
