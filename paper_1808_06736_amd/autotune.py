@@ -58,7 +58,8 @@ def candidates(type_, dim, prec, w, ntransf):
             for ch in chunks:
                 out.append({"bin": b, "maxsubprob": ms, "ntransf_chunk": ch, mkey: 1})
     if dim == 3 and prec == B.ESN_SINGLE and w <= 7:
-        for b in ((2, 2, 4), (2, 2, 8), (4, 4, 4), (2, 4, 8)):
+        # matrix-core kernels: bins of even sizes (2 x 2 column blocks)
+        for b in ((4, 4, 4), (8, 4, 4), (8, 8, 4), (16, 8, 8)):
             for ms in (512, 1024, 2048):
                 out.append({"bin": b, "maxsubprob": ms, mkey: 3})
     return out

@@ -160,6 +160,9 @@ size_t mfma_interp_lds_bytes(const int* b);
 size_t tile_lds_bytes(int prec, int dim, int w, const int* b, int ntr, bool staging = true);
 
 // ---- type 3 (kernels_type3.hip, type3.cpp) ----
+// Chebyshev coefficients per dimension of the type 3 correction sum (see
+// T3Args::cheb).
+constexpr int kT3Cheb = 24;
 // Per-point (sources) or per-target work of Sec. 3.3 on n values.
 struct T3Args {
   int dim, isign, w;
@@ -168,20 +171,32 @@ struct T3Args {
   double inv_gam[3];            // 1 / gamma: sources x'' = (x - x0) / gamma
   double hgam[3];               // h gamma: targets s'' = h gamma (s - s0)
   double* out[3];               // rescaled coordinates (FP64, n each)
+  // The correction sum g(u) = sum_q w_q phi(z_q) cos(u z_q) at u = (w/2) s''
+  // as sum_k cheb[m][k] T_k(u^2 cscale[m] - 1) over |u| <= U_m, the largest
+  // |u| of the targets (cscale = 2 / U_m^2; 0 and cheb = {g(0), 0, ...} when
+  // U_m = 0).
+  double cheb[3][kT3Cheb];
+  double cscale[3];
 };
-// Per-block (min, max) pairs of n coordinates into part[2 * t3_minmax_blocks(n)];
-// a NaN shows as the maximum.
+// Coordinate arrays (device) whose bounds one launch finds.
+struct MinMaxSets {
+  const void* x[6];
+  int64_t n[6];
+  int count;
+};
+// Bounds of each array i < a.count into out[2 i] (min), out[2 i + 1] (max; NaN
+// if any value is NaN or infinite); part holds
+// 2 a.count t3_minmax_blocks(max n) doubles of per-block partials.
 int t3_minmax_blocks(int64_t n);
-hipError_t launch_minmax(const void* x, int coord_prec, int64_t n, double* part, hipStream_t s);
+hipError_t launch_minmax(const MinMaxSets& a, int coord_prec, double* part, double* out,
+                         hipStream_t s);
 // Rescaled sources into a.out and prephase factors exp(isign i s0.(x - x0)) into pre.
 hipError_t launch_t3_sources(const T3Args& a, int coord_prec, int prec, const void* const* x,
                              void* pre, hipStream_t s);
 // Rescaled targets into a.out and per-target factors (correction of step 3 times
-// the postphase exp(isign i s.x0)) into post; zq, wphi: the nq positive
-// quadrature nodes and weights times phi at the nodes.
+// the postphase exp(isign i s.x0)) into post.
 hipError_t launch_t3_targets(const T3Args& a, int coord_prec, int prec, const void* const* sx,
-                             const double* zq, const double* wphi, int nq, void* post,
-                             hipStream_t s);
+                             void* post, hipStream_t s);
 // out[t][i] = in[t][i] * fac[i], i < n, t < ntr (complex of precision prec).
 hipError_t launch_cmul(int prec, const void* in, const void* fac, void* out, int64_t n, int ntr,
                        hipStream_t s);
@@ -313,7 +328,7 @@ struct esn_plan_s {
   void* d_t3_grid = nullptr;     // [ntransf][n1 n2 n3] spread grid = inner modes
   void* d_t3_c = nullptr;        // [ntransf][M] prephased strengths
   double* d_t3_xy = nullptr;     // [3][cap] rescaled coordinates (setpts scratch)
-  double* d_t3_q = nullptr;      // [2 nquad] quadrature nodes, weights * phi
+  std::vector<double> t3_zq, t3_wphi;   // quadrature nodes, weights * phi at them
   double* d_t3_mm = nullptr;     // min/max partials
   double* h_t3_mm = nullptr;     // pinned copy of the partials
   int64_t t3_cap_M = 0, t3_cap_N = 0, t3_cap_grid = 0, t3_cap_xy = 0;

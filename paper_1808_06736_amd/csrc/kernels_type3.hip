@@ -1,12 +1,14 @@
 // Type 3 (Sec. 3.3): the per-point and per-target work around the inner
 // spreading and type 2 steps, all in FP64.
 //
-//   minmax   : bounds of a coordinate array (per-block partials), for the
-//              centres x0, s0 and half-widths X, S of eqs. (XS) and (trans)
+//   minmax   : bounds of up to six coordinate arrays in one launch (per-block
+//              partials, then one block per array), for the centres x0, s0
+//              and half-widths X, S of eqs. (XS) and (trans)
 //   sources  : rescaled source x'' = (x - x0) / gamma (Sec. 3.3 step 1) and the
 //              prephase exp(isign i s0.(x - x0)) of eq. (trans)
 //   targets  : rescaled target s'' = h gamma (s - s0) (step 2) and one complex
-//              factor per target: the correction of step 3 times the
+//              factor per target: the correction of step 3 (its quadrature
+//              sum from a Chebyshev series built on the host) times the
 //              postphase exp(isign i s.x0) of eq. (trans)
 //   cmul     : out[t][i] = in[t][i] * fac[i] over the transforms
 #include "device_common.hpp"
@@ -18,48 +20,88 @@ constexpr int kT3Block = 256;
 __device__ __forceinline__ float2 cmake(float a, float b) { return make_float2(a, b); }
 __device__ __forceinline__ double2 cmake(double a, double b) { return make_double2(a, b); }
 
+// Stage 1: per-block (min, max) partials of array blockIdx.y; a NaN or an
+// infinity shows as a NaN maximum.
 template <typename CT>
 __global__ void __launch_bounds__(kT3Block)
-minmax_kernel(const CT* __restrict__ x, int64_t n, double* __restrict__ part) {
+minmax_kernel(const MinMaxSets a, double* __restrict__ part, int nb) {
   __shared__ double smin[kT3Block], smax[kT3Block];
+  const int arr = blockIdx.y;
+  const CT* __restrict__ x = static_cast<const CT*>(a.x[arr]);
+  const int64_t n = a.n[arr];
   double lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * kT3Block + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kT3Block) {
+       i += (int64_t)nb * kT3Block) {
     const double v = (double)x[i];
     lo = fmin(lo, v);
     hi = fmax(hi, v);
-    if (v != v) hi = v;   // NaN is reported through the maximum
+    bad |= !isfinite(v);
   }
   smin[threadIdx.x] = lo;
-  smax[threadIdx.x] = hi;
+  smax[threadIdx.x] = bad ? NAN : hi;
   __syncthreads();
   for (int o = kT3Block / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
-      const double a = smax[threadIdx.x], b = smax[threadIdx.x + o];
-      smax[threadIdx.x] = (a != a || b != b) ? NAN : fmax(a, b);
+      const double u = smax[threadIdx.x], v = smax[threadIdx.x + o];
+      smax[threadIdx.x] = (u != u || v != v) ? NAN : fmax(u, v);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = smin[0];
-    part[2 * blockIdx.x + 1] = smax[0];
+    part[2 * ((int64_t)arr * nb + blockIdx.x)] = smin[0];
+    part[2 * ((int64_t)arr * nb + blockIdx.x) + 1] = smax[0];
+  }
+}
+
+// Stage 2: one block per array folds its nb partials into out[2 arr], [2 arr + 1].
+__global__ void __launch_bounds__(kT3Block)
+minmax_fold_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double smin[kT3Block], smax[kT3Block];
+  const int arr = blockIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
+  for (int q = threadIdx.x; q < nb; q += kT3Block) {
+    lo = fmin(lo, part[2 * ((int64_t)arr * nb + q)]);
+    const double h = part[2 * ((int64_t)arr * nb + q) + 1];
+    bad |= (h != h);
+    hi = fmax(hi, h);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = bad ? NAN : hi;
+  __syncthreads();
+  for (int o = kT3Block / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      const double u = smax[threadIdx.x], v = smax[threadIdx.x + o];
+      smax[threadIdx.x] = (u != u || v != v) ? NAN : fmax(u, v);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * arr] = smin[0];
+    out[2 * arr + 1] = smax[0];
   }
 }
 
 int t3_minmax_blocks(int64_t n) {
-  const int64_t b = (n + kT3Block - 1) / kT3Block;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+  const int64_t b = (n + 8 * kT3Block - 1) / (8 * kT3Block);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 512));
 }
 
-hipError_t launch_minmax(const void* x, int coord_prec, int64_t n, double* part, hipStream_t s) {
-  const int nb = t3_minmax_blocks(n);
+hipError_t launch_minmax(const MinMaxSets& a, int coord_prec, double* part, double* out,
+                         hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  int64_t nmax = 0;
+  for (int i = 0; i < a.count; i++) nmax = std::max(nmax, a.n[i]);
+  const int nb = t3_minmax_blocks(nmax);
+  const dim3 g(nb, a.count);
   if (coord_prec == ESN_SINGLE)
-    hipLaunchKernelGGL(minmax_kernel<float>, dim3(nb), dim3(kT3Block), 0, s,
-                       static_cast<const float*>(x), n, part);
+    hipLaunchKernelGGL(minmax_kernel<float>, g, dim3(kT3Block), 0, s, a, part, nb);
   else
-    hipLaunchKernelGGL(minmax_kernel<double>, dim3(nb), dim3(kT3Block), 0, s,
-                       static_cast<const double*>(x), n, part);
+    hipLaunchKernelGGL(minmax_kernel<double>, g, dim3(kT3Block), 0, s, a, part, nb);
+  hipLaunchKernelGGL(minmax_fold_kernel, dim3(a.count), dim3(kT3Block), 0, s, part, nb, out);
   return hipGetLastError();
 }
 
@@ -83,33 +125,40 @@ __global__ void t3_sources_kernel(const T3Args a, const CT* __restrict__ x,
   pre[j] = cmake((T)cs, (T)sn);
 }
 
-// One factor of the step 3 correction per dimension, eqs. (pk1) and (quad):
-// 1 / (w sum_q wq phi(zq) cos(u zq)) with u = alpha gamma (s - s0) = (w/2) s''.
-__device__ __forceinline__ double t3_corr(double u, int w, const double* __restrict__ zq,
-                                          const double* __restrict__ wphi, int nq) {
-  double acc = 0.0;
-  for (int q = 0; q < nq; q++) acc += wphi[q] * cos(u * zq[q]);
-  return 1.0 / ((double)w * acc);
+// The step 3 correction sum of dimension m, eqs. (pk1) and (quad):
+// g(u) = sum_q wq phi(zq) cos(u zq) at u = alpha gamma (s - s0) = (w/2) s'',
+// from its Chebyshev series in u^2 (Clenshaw's recurrence, FP64).
+__device__ __forceinline__ double t3_gsum(const double* __restrict__ a, double cscale, double u) {
+  const double x = u * u * cscale - 1.0;
+  const double x2 = 2.0 * x;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kT3Cheb - 1; k >= 1; k--) {
+    const double b0 = fma(x2, b1, a[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(x, b1, a[0] - b2);
 }
 
 template <typename CT, typename T>
 __global__ void t3_targets_kernel(const T3Args a, const CT* __restrict__ s,
                                   const CT* __restrict__ t, const CT* __restrict__ u,
-                                  const double* __restrict__ zq, const double* __restrict__ wphi,
-                                  int nq, cplx_t<T>* __restrict__ post) {
+                                  cplx_t<T>* __restrict__ post) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.n) return;
   const CT* ss[3] = {s, t, u};
-  double corr = 1.0, ph = 0.0;
+  double g = 1.0, ph = 0.0;
 #pragma unroll
   for (int m = 0; m < 3; m++) {
     if (m >= a.dim) break;
     const double sk = (double)ss[m][k];
     const double sr = (sk - a.s0[m]) * a.hgam[m];   // s'' = h gamma (s - s0)
     a.out[m][k] = sr;
-    corr *= t3_corr(0.5 * a.w * sr, a.w, zq, wphi, nq);
+    g *= (double)a.w * t3_gsum(a.cheb[m], a.cscale[m], 0.5 * a.w * sr);
     ph += sk * a.x0[m];
   }
+  const double corr = 1.0 / g;   // the product of 1 / (w g(u)) over the dimensions
   double sn, cs;
   sincos((double)a.isign * ph, &sn, &cs);
   post[k] = cmake((T)(corr * cs), (T)(corr * sn));
@@ -157,28 +206,27 @@ hipError_t launch_t3_sources(const T3Args& a, int coord_prec, int prec, const vo
 }
 
 hipError_t launch_t3_targets(const T3Args& a, int coord_prec, int prec, const void* const* sx,
-                             const double* zq, const double* wphi, int nq, void* post,
-                             hipStream_t s) {
+                             void* post, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const dim3 g(t3_blocks(a.n)), b(kT3Block);
   if (coord_prec == ESN_SINGLE) {
     const float* c[3] = {static_cast<const float*>(sx[0]), static_cast<const float*>(sx[1]),
                          static_cast<const float*>(sx[2])};
     if (prec == ESN_SINGLE)
-      hipLaunchKernelGGL((t3_targets_kernel<float, float>), g, b, 0, s, a, c[0], c[1], c[2], zq,
-                         wphi, nq, static_cast<float2*>(post));
+      hipLaunchKernelGGL((t3_targets_kernel<float, float>), g, b, 0, s, a, c[0], c[1], c[2],
+                         static_cast<float2*>(post));
     else
-      hipLaunchKernelGGL((t3_targets_kernel<float, double>), g, b, 0, s, a, c[0], c[1], c[2], zq,
-                         wphi, nq, static_cast<double2*>(post));
+      hipLaunchKernelGGL((t3_targets_kernel<float, double>), g, b, 0, s, a, c[0], c[1], c[2],
+                         static_cast<double2*>(post));
   } else {
     const double* c[3] = {static_cast<const double*>(sx[0]), static_cast<const double*>(sx[1]),
                           static_cast<const double*>(sx[2])};
     if (prec == ESN_SINGLE)
-      hipLaunchKernelGGL((t3_targets_kernel<double, float>), g, b, 0, s, a, c[0], c[1], c[2], zq,
-                         wphi, nq, static_cast<float2*>(post));
+      hipLaunchKernelGGL((t3_targets_kernel<double, float>), g, b, 0, s, a, c[0], c[1], c[2],
+                         static_cast<float2*>(post));
     else
       hipLaunchKernelGGL((t3_targets_kernel<double, double>), g, b, 0, s, a, c[0], c[1], c[2],
-                         zq, wphi, nq, static_cast<double2*>(post));
+                         static_cast<double2*>(post));
   }
   return hipGetLastError();
 }

@@ -245,14 +245,14 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   // ---- bins, subproblems, methods, chunk ----
   default_bins(dim, p->bin);
   // the matrix-core kernels (3D single precision, w <= 7) work best on small
-  // bins (measured on clustered and uniform points at N = 128^3, M = 1e7):
-  // 4 x 4 x 4 for spreading, 2 x 2 x 4 for interpolation
+  // bins: 8 x 4 x 4 (measured at M = 1e7 on 256^3 and 288^3 fine grids, with
+  // clustered, uniform and half-box uniform points, for both kernels)
   const bool mfma_candidate = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
                               o.spread_method != 1 && o.spread_method != 2 &&
                               o.interp_method != 1 && o.interp_method != 2;
   if (mfma_candidate) {
-    p->bin[0] = type == 1 ? 4 : 2;
-    p->bin[1] = type == 1 ? 4 : 2;
+    p->bin[0] = 8;
+    p->bin[1] = 4;
     p->bin[2] = 4;
   }
   for (int m = 0; m < dim; m++) {

@@ -69,31 +69,78 @@ int64_t next_smooth_even(int64_t n) {
   }
 }
 
-// Bounds [lo, hi] of each of dim coordinate arrays of n values (device); false
-// if a value is NaN or infinite.
-int coord_bounds(esn_plan_s* p, const void* const* x, int coord_prec, int64_t n, double* lo,
-                 double* hi) {
+// Bounds [xlo, xhi] of the dim source coordinate arrays (M values each) and
+// [slo, shi] of the target arrays (N values each), from one launch and one
+// copy to the host; ESN_ERR_NAN_PTS if a value is NaN or infinite.
+int coord_bounds(esn_plan_s* p, const void* const* x, int64_t M, const void* const* sx, int64_t N,
+                 int coord_prec, double* xlo, double* xhi, double* slo, double* shi) {
   hipStream_t s = p->stream;
+  MinMaxSets a;
+  std::memset(&a, 0, sizeof(a));
+  int slot[6] = {-1, -1, -1, -1, -1, -1};
   for (int m = 0; m < p->dim; m++) {
-    lo[m] = hi[m] = 0.0;
-    if (n == 0) continue;
-    const int nb = t3_minmax_blocks(n);
-    if (launch_minmax(x[m], coord_prec, n, p->d_t3_mm, s) != hipSuccess) return ESN_ERR_HIP;
-    if (hipMemcpyAsync(p->h_t3_mm, p->d_t3_mm, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
-                       s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return ESN_ERR_HIP;
-    double a = INFINITY, b = -INFINITY;
-    for (int q = 0; q < nb; q++) {
-      a = std::min(a, p->h_t3_mm[2 * q]);
-      b = std::isnan(p->h_t3_mm[2 * q + 1]) ? NAN : std::max(b, p->h_t3_mm[2 * q + 1]);
-      if (std::isnan(b)) break;
+    xlo[m] = xhi[m] = slo[m] = shi[m] = 0.0;
+    if (M > 0) {
+      slot[m] = a.count;
+      a.x[a.count] = x[m];
+      a.n[a.count++] = M;
     }
-    if (!std::isfinite(a) || !std::isfinite(b)) return ESN_ERR_NAN_PTS;
-    lo[m] = a;
-    hi[m] = b;
+    if (N > 0) {
+      slot[3 + m] = a.count;
+      a.x[a.count] = sx[m];
+      a.n[a.count++] = N;
+    }
   }
+  if (a.count == 0) return ESN_OK;
+  double* out = p->d_t3_mm + 2 * (int64_t)6 * t3_minmax_blocks(kMaxPoints);
+  if (launch_minmax(a, coord_prec, p->d_t3_mm, out, s) != hipSuccess ||
+      hipMemcpyAsync(p->h_t3_mm, out, sizeof(double) * 2 * a.count, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ESN_ERR_HIP;
+  for (int m = 0; m < p->dim; m++)
+    for (int set = 0; set < 2; set++) {
+      const int i = slot[3 * set + m];
+      if (i < 0) continue;
+      const double lo = p->h_t3_mm[2 * i], hi = p->h_t3_mm[2 * i + 1];
+      if (!std::isfinite(lo) || !std::isfinite(hi)) return ESN_ERR_NAN_PTS;
+      (set ? slo : xlo)[m] = lo;
+      (set ? shi : xhi)[m] = hi;
+    }
   return ESN_OK;
+}
+
+// Chebyshev coefficients a[0 .. kT3Cheb-1] of the correction sum
+// g(u) = sum_q wphi_q cos(u z_q) (eqs. (pk1), (quad)) on |u| <= U, as a series
+// in x = 2 (u / U)^2 - 1 (g is even): the interpolant at the kT3Cheb
+// Chebyshev points, with cscale = 2 / U^2.  For w <= 16 and U <= pi w / 4 (the
+// largest |u| that the dilation of eq. (ng) allows) its terms fall below FP64
+// rounding relative to g well before the last.  U = 0 gives the constant g(0).
+void t3_cheb(const std::vector<double>& zq, const std::vector<double>& wphi, double U, double* a,
+             double* cscale) {
+  auto g = [&](double u) {
+    double s = 0.0;
+    for (size_t q = 0; q < zq.size(); q++) s += wphi[q] * std::cos(u * zq[q]);
+    return s;
+  };
+  for (int k = 0; k < kT3Cheb; k++) a[k] = 0.0;
+  if (!(U > 0.0)) {
+    a[0] = g(0.0);
+    *cscale = 0.0;
+    return;
+  }
+  constexpr int K = kT3Cheb;
+  double G[K];
+  for (int j = 0; j < K; j++) {
+    const double x = std::cos(kPi * (j + 0.5) / K);
+    G[j] = g(U * std::sqrt(0.5 * (x + 1.0)));
+  }
+  for (int k = 0; k < K; k++) {
+    double s = 0.0;
+    for (int j = 0; j < K; j++) s += G[j] * std::cos(kPi * k * (j + 0.5) / K);
+    a[k] = (k == 0 ? 1.0 : 2.0) * s / K;
+  }
+  *cscale = 2.0 / (U * U);
 }
 
 }  // namespace
@@ -128,19 +175,16 @@ int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan*
   }
   for (int m = 0; m < 3; m++) p->N[m] = p->nf[m] = 1;
   // quadrature of the correction factors: nodes and weights * phi(node), FP64
-  std::vector<double> zq, wq;
-  gauss_legendre_positive(par.nquad, &zq, &wq);
-  std::vector<double> q(2 * par.nquad);
-  for (int j = 0; j < par.nquad; j++) {
-    q[j] = zq[j];
-    q[par.nquad + j] = wq[j] * std::exp(par.beta * (std::sqrt(1.0 - zq[j] * zq[j]) - 1.0));
-  }
+  std::vector<double> wq;
+  gauss_legendre_positive(par.nquad, &p->t3_zq, &wq);
+  p->t3_wphi.resize(par.nquad);
+  for (int j = 0; j < par.nquad; j++)
+    p->t3_wphi[j] =
+        wq[j] * std::exp(par.beta * (std::sqrt(1.0 - p->t3_zq[j] * p->t3_zq[j]) - 1.0));
+  // per-block partials of up to six arrays, then the six (min, max) pairs
   const int nb = t3_minmax_blocks(kMaxPoints);
-  if (t3_alloc(p, (void**)&p->d_t3_q, sizeof(double) * q.size()) ||
-      t3_alloc(p, (void**)&p->d_t3_mm, sizeof(double) * 2 * nb) ||
-      hipHostMalloc((void**)&p->h_t3_mm, sizeof(double) * 2 * nb, hipHostMallocDefault) !=
-          hipSuccess ||
-      hipMemcpy(p->d_t3_q, q.data(), sizeof(double) * q.size(), hipMemcpyHostToDevice) !=
+  if (t3_alloc(p, (void**)&p->d_t3_mm, sizeof(double) * 2 * 6 * (nb + 1)) ||
+      hipHostMalloc((void**)&p->h_t3_mm, sizeof(double) * 2 * 6, hipHostMallocDefault) !=
           hipSuccess) {
     t3_destroy(p);
     delete p;
@@ -178,16 +222,16 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
 
   // ---- centres, half-widths, grid sizes and dilations (steps 0 and 1) ----
   double xlo[3], xhi[3], slo[3], shi[3];
-  int rc = coord_bounds(p, xs, coord_prec, M, xlo, xhi);
-  if (rc == ESN_OK) rc = coord_bounds(p, ss, coord_prec, N, slo, shi);
+  int rc = coord_bounds(p, xs, M, ss, N, coord_prec, xlo, xhi, slo, shi);
   if (rc != ESN_OK) return rc;
   int64_t n[3] = {1, 1, 1};
-  double gam[3] = {1, 1, 1}, x0[3] = {0, 0, 0}, s0[3] = {0, 0, 0};
+  double gam[3] = {1, 1, 1}, x0[3] = {0, 0, 0}, s0[3] = {0, 0, 0}, Sh[3] = {0, 0, 0};
   int64_t cells = 1;
   for (int m = 0; m < dim; m++) {
     x0[m] = 0.5 * (xlo[m] + xhi[m]);
     s0[m] = 0.5 * (slo[m] + shi[m]);
     const double X = 0.5 * (xhi[m] - xlo[m]), S = 0.5 * (shi[m] - slo[m]);
+    Sh[m] = S;
     const double want = std::max(2.0 * sigma / kPi * X * S + w, 2.0 * w);
     if (!(want < (double)kT3MaxGrid)) return ESN_ERR_BUDGET;
     n[m] = next_smooth_even((int64_t)std::ceil(want));
@@ -259,6 +303,9 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
     a.inv_gam[m] = 1.0 / gam[m];
     a.hgam[m] = 2.0 * kPi / (double)p->t3_n[m] * gam[m];
     a.out[m] = p->d_t3_xy + m * p->t3_cap_xy;
+    // the targets' u = (w/2) s'' lie in [-U, U]
+    t3_cheb(p->t3_zq, p->t3_wphi, m < dim ? 0.5 * w * a.hgam[m] * Sh[m] : 0.0, a.cheb[m],
+            &a.cscale[m]);
   }
   a.n = M;
   ESN_HIP(launch_t3_sources(a, coord_prec, p->prec, xs, p->d_t3_pre, st));
@@ -268,8 +315,7 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
 
   // ---- targets: rescale, correction and postphase, sort (steps 2 and 3) ----
   a.n = N;
-  ESN_HIP(launch_t3_targets(a, coord_prec, p->prec, ss, p->d_t3_q, p->d_t3_q + p->par.nquad,
-                            p->par.nquad, p->d_t3_post, st));
+  ESN_HIP(launch_t3_targets(a, coord_prec, p->prec, ss, p->d_t3_post, st));
   rc = esn_setpts(p->t3_inner, N, ESN_DOUBLE, a.out[0], dim > 1 ? a.out[1] : nullptr,
                   dim > 2 ? a.out[2] : nullptr);
   if (rc != ESN_OK) return rc;
@@ -330,7 +376,6 @@ void t3_destroy(esn_plan p) {
   t3_free(&p->d_t3_grid);
   t3_free(&p->d_t3_c);
   t3_free((void**)&p->d_t3_xy);
-  t3_free((void**)&p->d_t3_q);
   t3_free((void**)&p->d_t3_mm);
   if (p->h_t3_mm) (void)hipHostFree(p->h_t3_mm);
   p->h_t3_mm = nullptr;
