@@ -150,6 +150,10 @@ void destroy_all(esn_plan_s* p) {
   fft_destroy(&p->fft_adj_tail);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  // anything still tracked (none is expected)
+  for (auto& a : p->allocs) (void)hipFree(a.first);
+  p->allocs.clear();
+  p->device_bytes = 0;
 }
 
 }  // namespace

@@ -323,3 +323,37 @@ def test_execute_adjoint(type_, dim, prec, eps, ntr):
     assert err <= 10 * eps
     assert O.rel_l2(bw, other) <= (2 * eps if prec == "f32" else 1e-11)
     assert adj < (2e-5 if prec == "f32" else 1e-12)
+
+
+def test_plans_return_their_device_memory():
+    """Making, using and destroying plans of all types (including type 3 and
+    its inner plans) leaves the device's free memory where it was."""
+    t = torch()
+    rng = np.random.default_rng(501)
+    xs = [dev(rng.uniform(-np.pi, np.pi, 200000).astype(np.float32)) for _ in range(3)]
+    ss = [dev(rng.uniform(-30, 30, 50000).astype(np.float32)) for _ in range(3)]
+    c = dev(I.complex_normal(200000, 502, np.complex64))
+
+    def cycle():
+        for type_ in (1, 2):
+            p = B.Plan(type_, (48, 40, 32), 1e-6, dtype=t.complex64)
+            p.setpts(*xs)
+            if type_ == 1:
+                p.type1(c)
+            else:
+                p.type2(dev(I.complex_normal(48 * 40 * 32, 503, np.complex64)).reshape(32, 40, 48))
+            p.close()
+        q = B.Plan3(3, 1e-6, dtype=t.complex64)
+        q.setpts(xs, ss)
+        q.execute(c)
+        q.close()
+        t.cuda.synchronize()
+
+    cycle()   # first use: library and rocFFT set-up
+    t.cuda.empty_cache()
+    free0 = t.cuda.mem_get_info()[0]
+    for _ in range(5):
+        cycle()
+    t.cuda.empty_cache()
+    free1 = t.cuda.mem_get_info()[0]
+    assert free0 - free1 < 64 << 20, (free0, free1)
