@@ -91,6 +91,10 @@ typedef struct esn_opts {
                          type 2, 1024 otherwise) */
   int ntransf_chunk;  /* transforms per fused launch; 0 = as many as fit */
   int block;          /* threads per workgroup for spread/interp; 0 = 256 */
+  int kerevalmeth;    /* kernel evaluation: 0 auto (the table in double
+                         precision, exp and sqrt in single); 1 exp and sqrt
+                         at every weight (eq. (ES)); 2 piecewise polynomial
+                         table (Sec. 4.3, esn_kernel_poly) */
 } esn_opts;
 
 /* Fill *o with the defaults (debug 0, chkbnds 1, modeord 0, upsampfac 2.0,
@@ -123,6 +127,15 @@ int esn_gauss_legendre(int p, double* nodes, double* weights);
  * alpha = pi w / nf, p = nquad (eqs. (pk1), (quad)).  out: host array of
  * floor(N/2) + 1 doubles.  Host only; used to check the GPU values. */
 int esn_correction_factors(int w, double beta, int nquad, int64_t nf, int64_t N, double* out);
+
+/* Piecewise polynomial form of the kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1))
+ * (Sec. 4.3): w equal intervals of [-1, 1], one per window cell, each a
+ * polynomial of degree w + 3 in a local t in [-1, 1], with
+ * z = (k + (t + 1) / 2 - w / 2) (2 / w) on interval k.  coeffs: host array of
+ * w (w + 4) doubles, coefficient of t^j on interval k at coeffs[k (w + 4) + j]
+ * (Chebyshev interpolation converted to monomials).  w in 2..16, beta > 0;
+ * ESN_ERR_BAD_ARG otherwise.  Host only. */
+int esn_kernel_poly(int w, double beta, double* coeffs);
 
 /* ---- plan interface -------------------------------------------------------- */
 typedef struct esn_plan_s* esn_plan;
@@ -202,6 +215,7 @@ typedef struct esn_info {
   int spread_method, interp_method, point_code; /* point_code 1: fixed point u32, 2: f64 */
   int64_t device_bytes;  /* device memory the plan holds */
   int ndense_units;      /* subproblems run on the matrix cores (method 3) */
+  int kerevalmeth;       /* 1 exp and sqrt, 2 piecewise polynomial table */
 } esn_info;
 
 /* Describe a plan (host struct filled). */

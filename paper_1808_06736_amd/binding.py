@@ -37,7 +37,8 @@ cd = ctypes.c_double
 class EsnOpts(ctypes.Structure):
     _fields_ = [("debug", ci), ("chkbnds", ci), ("modeord", ci), ("upsampfac", cd),
                 ("sort", ci), ("spread_method", ci), ("interp_method", ci),
-                ("bin", ci * 3), ("maxsubprob", ci), ("ntransf_chunk", ci), ("block", ci)]
+                ("bin", ci * 3), ("maxsubprob", ci), ("ntransf_chunk", ci), ("block", ci),
+                ("kerevalmeth", ci)]
 
 
 class EsnParams(ctypes.Structure):
@@ -50,7 +51,8 @@ class EsnInfo(ctypes.Structure):
                 ("nmodes", i64 * 3), ("nf", i64 * 3), ("M", i64), ("bin", ci * 3),
                 ("maxsubprob", ci), ("nsubprob", ci), ("nbins_nonempty", ci),
                 ("ntransf_chunk", ci), ("spread_method", ci), ("interp_method", ci),
-                ("point_code", ci), ("device_bytes", i64), ("ndense_units", ci)]
+                ("point_code", ci), ("device_bytes", i64), ("ndense_units", ci),
+                ("kerevalmeth", ci)]
 
 
 class EsnStats(ctypes.Structure):
@@ -106,6 +108,7 @@ _SIGS = {
     "esn_strerror": ([ci], ctypes.c_char_p),
     "esn_gauss_legendre": ([ci, vp, vp], ci),
     "esn_correction_factors": ([ci, cd, ci, i64, i64, vp], ci),
+    "esn_kernel_poly": ([ci, cd, vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
     "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
     "esn_server_submit": ([vp, ctypes.POINTER(EsnRequest), ctypes.POINTER(ctypes.c_longlong)], ci),
@@ -234,6 +237,15 @@ def esn_correction_factors(w, beta, nquad, nf, N):
     out = np.zeros(int(N) // 2 + 1)
     check(lib().esn_correction_factors(int(w), float(beta), int(nquad), int(nf), int(N),
                                        out.ctypes.data), "esn_correction_factors")
+    return out
+
+
+def esn_kernel_poly(w, beta):
+    """Piecewise polynomial kernel table (Sec. 4.3): array [w, w + 4], row k the
+    monomial coefficients (t^0 first) of interval k's polynomial in t in [-1, 1]."""
+    import numpy as np
+    out = np.zeros((int(w), int(w) + 4))
+    check(lib().esn_kernel_poly(int(w), float(beta), out.ctypes.data), "esn_kernel_poly")
     return out
 
 

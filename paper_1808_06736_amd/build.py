@@ -33,10 +33,12 @@ SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "type3.cpp", "serve.cpp",
            "kernels_interp.hip", "kernels_mfma.hip", "kernels_type3.hip"]
 
 
-# Per-source extra flags.  The matrix-core kernels keep their MFMA accumulators
-# in ordinary VGPRs (gfx950 accepts them there), which saves the copies between
-# accumulator and vector registers around the data-dependent flushes.
-EXTRA = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# Per-source extra flags (none).  The matrix-core kernels keep their MFMA
+# accumulators in the accumulation registers, the compiler's default: its
+# option to place them in ordinary VGPRs gave MFMA instructions whose result
+# registers partly overlap their accumulator input, whose values then depend
+# on timing.
+EXTRA = {}
 
 
 def _compile(src: str) -> str:

@@ -113,6 +113,32 @@ __device__ __forceinline__ void es_weights_t(int sh, T f, T beta, T* ker) {
   else es_weights_f64<W>(sh, f, beta, ker);
 }
 
+// The same from the piecewise polynomial table c[W][W + kPolyExtra + 1]
+// (Sec. 4.3): window cell k lies in interval k at the local coordinate
+// t = 2 u - 1, u = l0 - t_point + W/2 in [0, 1) (the same for all k), and its
+// weight is interval k's polynomial at t (Horner's scheme).  c is the same for
+// every thread, so its values come through scalar loads.
+template <int W, typename T>
+__device__ __forceinline__ void es_weights_poly(int sh, T f, const T* __restrict__ c, T* ker) {
+  constexpr int P = W + kPolyExtra;
+  const T u = (T)sh - f + ((W & 1) ? (T)0.5 : (T)0);
+  const T t = (T)2 * u - (T)1;
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    T acc = c[k * (P + 1) + P];
+#pragma unroll
+    for (int j = P - 1; j >= 0; j--) acc = fma(acc, t, c[k * (P + 1) + j]);
+    ker[k] = acc;
+  }
+}
+
+// Kernel values by the plan's method: the table when ktab is set, else exp and sqrt.
+template <int W, typename T>
+__device__ __forceinline__ void es_weights_any(int sh, T f, T beta, const void* ktab, T* ker) {
+  if (ktab) es_weights_poly<W, T>(sh, f, static_cast<const T*>(ktab), ker);
+  else es_weights_t<W, T>(sh, f, beta, ker);
+}
+
 // Periodic wrap of an index that lies in [-n, 2n).
 __device__ __forceinline__ int64_t wrap_once(int64_t g, int64_t n) {
   if (g < 0) g += n;

@@ -35,6 +35,9 @@ inline int pts_record_bytes(int code) { return code == kPtsFixed32 ? 16 : 32; }
 
 // Everything a spread/interp kernel needs about the geometry and the sorted
 // points.  Passed by value.
+// Piecewise polynomial kernel (Sec. 4.3): degree w + kPolyExtra per interval.
+constexpr int kPolyExtra = 3;
+
 struct GeomArgs {
   int64_t n[3];          // fine grid per dim (1 for unused dims)
   int b[3];              // bin size per dim (1 for unused dims)
@@ -51,6 +54,9 @@ struct GeomArgs {
   const int32_t* sub_start;  // subproblem -> first sorted position
   const int32_t* sub_len;    // subproblem -> number of points
   int nsub;                  // number of subproblems
+  // piecewise polynomial kernel table [w][w + kPolyExtra + 1] in the plan's
+  // precision (esn_kernel_poly), or null: exp and sqrt at every weight
+  const void* ktab;
 };
 
 // ---- kernel launchers (kernels_*.hip) ----
@@ -280,6 +286,8 @@ struct esn_plan_s {
   int64_t nbins = 1;
   int maxsub = 1024;
   int spread_method = 1, interp_method = 1;
+  int kerevalmeth = 1;           // 1 exp and sqrt, 2 polynomial table (d_ktab)
+  void* d_ktab = nullptr;        // [w][w + kPolyExtra + 1] in the plan precision
   int block = 256;
   int pts_code = esn::kPtsFixed32;
   int fbits[3] = {0, 0, 0};

@@ -57,7 +57,7 @@ interp_lds_kernel(const GeomArgs g, const T* __restrict__ grid, cplx_t<T>* __res
       int sh;
       Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
       L[m] = window_cell(cd.cell, sh, g.n[m]) - bi[m] * g.b[m];
-      es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
+      es_weights_any<W, T>(sh, cd.f, beta, g.ktab, ker[m]);
     }
     const int64_t orig = point_perm(g.pts, g.pts_code, j);
     for (int tr = 0; tr < ntr; tr++) {
@@ -123,7 +123,7 @@ interp_gm_kernel(const GeomArgs g, const T* __restrict__ grid, cplx_t<T>* __rest
     int sh;
     Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
     l0[m] = (int64_t)cd.cell - W / 2 + sh;
-    es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
+    es_weights_any<W, T>(sh, cd.f, beta, g.ktab, ker[m]);
   }
   int64_t idx0[W];
 #pragma unroll

@@ -199,10 +199,11 @@ struct TileWalk {
 // everywhere else.
 template <int W>
 __device__ __forceinline__ int window_weights(uint32_t q, int fbits, int n, int o, float bl,
-                                              float* k) {
+                                              const float* ktab, float* k) {
   const uint32_t fr = q & ((1u << fbits) - 1u);
   const int sh = window_shift_fixed(fr, fbits, W);
-  es_weights_hw<W>(sh, ldexpf((float)fr, -fbits), bl, k);
+  if (ktab) es_weights_poly<W, float>(sh, ldexpf((float)fr, -fbits), ktab, k);
+  else es_weights_hw<W>(sh, ldexpf((float)fr, -fbits), bl, k);
   return window_cell((int)(q >> fbits), sh, n) - o;
 }
 
@@ -252,6 +253,7 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
+  const float* ktab = static_cast<const float*>(g.ktab);    // kernel table or null
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
   {
@@ -282,9 +284,11 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
 
   // add this wave's ring slots in mask fm (block-uniform) into the bin tile and clear them
   auto flush = [&](unsigned fm) {
-    // the accumulators were written by matrix instructions in another block:
-    // 16 wait states cover their latency before vector instructions read them
-    asm volatile("s_nop 15");
+    // 16 wait states on top of the compiler's own between the matrix products
+    // and the reads of their results (tied to the accumulators, so the nop
+    // sits between them): with the compiler's count alone, rare results were
+    // read before the products had landed
+    asm volatile("s_nop 15" : "+a"(acc[0]), "+a"(acc[1]));
 #pragma unroll
     for (int u = 0; u < 2; u++) {
       const int t = 2 * wv + u;
@@ -318,10 +322,10 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
       float k[W], v[8];
       if (wv == 0) {
         // x weights by footprint slot, z weights by ring slot
-        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, k);
+        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, ktab, k);
         slots8<W>(k, lx & 1, v);
         store8(skx + lane * 8, v);
-        const int zr = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, k);
+        const int zr = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, ktab, k);
         slots8<W>(k, 0, v);    // planes zr .. zr + 7 of the tile
         rotate8(v, zr & 7);    // -> ring slots
         float vz[8];
@@ -333,7 +337,7 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
         store8(skz + lane * 8, vz);
       } else {
         // B operand: y weight times strength, column 2 y + (re, im)
-        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, k);
+        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, ktab, k);
         slots8<W>(k, ly & 1, v);
         float4* b4 = reinterpret_cast<float4*>(sb + lane * 16);
 #pragma unroll
@@ -479,6 +483,7 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const float bl = (float)(g.beta * 1.4426950408889634);   // beta log2(e)
+  const float* ktab = static_cast<const float*>(g.ktab);    // kernel table or null
   const int n0 = (int)g.n[0], n1 = (int)g.n[1], n2 = (int)g.n[2];
 
   // (record loads are unconditional, at indices clamped into the subproblem,
@@ -521,15 +526,15 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       float v[8];
       if (wv == 0) {
         float k[W];
-        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, k);
+        const int lx = window_weights<W>(r0.x, g.fbits[0], n0, bx0, bl, ktab, k);
         slots8<W>(k, lx & 1, v);
         store8(skx + lane * 8, v);
-        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, k);
+        const int ly = window_weights<W>(r0.y, g.fbits[1], n1, by0, bl, ktab, k);
         slots8<W>(k, ly & 1, v);
         store8(sky + lane * 8, v);
       } else {
         float k[W];
-        const int lz = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, k);
+        const int lz = window_weights<W>(r0.z, g.fbits[2], n2, bz0, bl, ktab, k);
         slots8<W>(k, lz & 1, v);
         store8(skz + lane * 8, v);
         // footprint origin of the point's 2 x 2 x 2 block of window cells:
@@ -573,28 +578,19 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       float4 kya_n = *reinterpret_cast<const float4*>(wy + 8 * q0);
       float4 kyb_n = *reinterpret_cast<const float4*>(wy + 8 * q0 + 4);
       float kz0_n = wx[8 * q0 + 1024], kz4_n = wx[8 * q0 + 1028];
-      // A step's z-weighted sums are formed right after its products (the
-      // matrix results are read by vector instructions only in the block that
-      // wrote them); their cross-lane reduction and store run in the next
-      // step, behind its matrix work.
+      // A step's z-weighted sums are formed right after its products; their
+      // cross-lane reduction and store run in the next step, behind its
+      // matrix work.
       float rep = 0.f, imp = 0.f;
       int qp = q0 - 16;   // the pending step (none before the first)
       auto finish = [&](float re, float im, int qb) {
-        // lanes 32..63 of re <-> lanes 0..31 of im: the lower half then sums
-        // re over lane groups (0, 2) and (1, 3), the upper half im
-        const auto h = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, re),
-                                                        __builtin_bit_cast(unsigned, im), false,
-                                                        false);
-        // (elements copied out first: a bit cast taken straight from a vector
-        // element reads element 0)
-        const unsigned h0 = h[0], h1 = h[1];
-        const float u = __builtin_bit_cast(float, h0) + __builtin_bit_cast(float, h1);
-        // odd rows <-> even rows: every row then holds the sum of its row pair
-        const auto g2 = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, u),
-                                                         __builtin_bit_cast(unsigned, u), false,
-                                                         false);
-        const unsigned g0 = g2[0], g1 = g2[1];
-        const float v = __builtin_bit_cast(float, g0) + __builtin_bit_cast(float, g1);
+        // the lower half of the wave sums re over lane groups (0, 2) and
+        // (1, 3), the upper half im: each lane sends the part it does not
+        // keep to the lane 32 away
+        const bool lo = kq < 2;
+        const float u = (lo ? re : im) + __shfl_xor(lo ? im : re, 32);
+        // every row of 16 lanes then adds its neighbour row
+        const float v = u + __shfl_xor(u, 16);
         const int pt = qb + n;
         // row 0 stores re, row 2 im
         if ((kq & 1) == 0 && pt >= q0 && pt < q1)
@@ -620,10 +616,9 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], ((s & 1) ? kxb : kxa) * ky[s >> 1],
                                                      acc, 0, 0, 0);
         finish(rep, imp, qp);
-        // 8 wait states on top of the compiler's own before vector
-        // instructions read the matrix results (margin over the latency; the
-        // accumulator operand ties the nop between the products and the reads)
-        asm volatile("s_nop 7" : "+v"(acc));
+        // 8 wait states on top of the compiler's own before the results are
+        // read (as in the spreading kernel's flush)
+        asm volatile("s_nop 7" : "+a"(acc));
         // output rows 4 kq + i: plane kq + 4 (i >> 1), part i & 1
         rep = fmaf(kz4, acc[2], kz0 * acc[0]);
         imp = fmaf(kz4, acc[3], kz0 * acc[1]);

@@ -69,7 +69,7 @@ spread_lds_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restri
         int sh;
         Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
         st->loc[lane][m] = window_cell(cd.cell, sh, g.n[m]) - bi[m] * g.b[m];
-        es_weights_t<W, T>(sh, cd.f, beta, st->ker[lane][m]);
+        es_weights_any<W, T>(sh, cd.f, beta, g.ktab, st->ker[lane][m]);
       }
       const int64_t orig = point_perm(g.pts, g.pts_code, j);
       for (int tr = 0; tr < ntr; tr++) stc[lane * ntr + tr] = c[tr * g.cstride + orig];
@@ -169,7 +169,7 @@ spread_gm_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restric
     int sh;
     Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], j, m, &sh, W);
     l0[m] = (int64_t)cd.cell - W / 2 + sh;   // in [-W/2, n)
-    es_weights_t<W, T>(sh, cd.f, beta, ker[m]);
+    es_weights_any<W, T>(sh, cd.f, beta, g.ktab, ker[m]);
   }
   int64_t idx0[W];
 #pragma unroll

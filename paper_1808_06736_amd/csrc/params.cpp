@@ -1,5 +1,6 @@
 // Host-side plan arithmetic: kernel width and shape, fine-grid sizes and the
 // Gauss-Legendre rule behind the kernel's Fourier transform.  All FP64.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -133,3 +134,54 @@ extern "C" int esn_correction_factors(int w, double beta, int nquad, int64_t nf,
   }
   return ESN_OK;
 }
+
+// Piecewise polynomial form of the ES kernel (Sec. 4.3): the support [-1, 1]
+// of phi(z) = exp(beta (sqrt(1 - z^2) - 1)) is split into w equal intervals,
+// one per window cell, and each is replaced by a polynomial of degree w + 3
+// in the local variable t in [-1, 1], z = (k + (t + 1) / 2 - w / 2) (2 / w) on
+// interval k.  The polynomial interpolates phi at the degree + 1 Chebyshev
+// points of the interval (FP64 values) and is converted to monomials in t in
+// long double.  A window's w ordinates share one t, so its w weights are w
+// Horner evaluations with the same argument.
+extern "C" int esn_kernel_poly(int w, double beta, double* coeffs) {
+  if (w < 2 || w > 16 || !(beta > 0.0) || !coeffs) return ESN_ERR_BAD_ARG;
+  const int P = w + esn::kPolyExtra;   // degree
+  const int n = P + 1;                 // interpolation points
+  std::vector<double> vals(n);
+  std::vector<long double> cheb(n), mono(n), tkm1(n), tk(n), tkp1(n);
+  for (int k = 0; k < w; k++) {
+    for (int i = 0; i < n; i++) {
+      const double t = std::cos(M_PI * (i + 0.5) / n);
+      const double z = (k + 0.5 * (t + 1.0) - 0.5 * w) * (2.0 / w);
+      const double a = std::max(0.0, 1.0 - z * z);
+      vals[i] = std::abs(z) <= 1.0 ? std::exp(beta * (std::sqrt(a) - 1.0)) : 0.0;
+    }
+    // Chebyshev coefficients of the interpolant (discrete cosine transform)
+    for (int j = 0; j < n; j++) {
+      long double acc = 0.0L;
+      for (int i = 0; i < n; i++)
+        acc += (long double)vals[i] * std::cos((long double)M_PI * j * (i + 0.5L) / n);
+      cheb[j] = (j == 0 ? 1.0L : 2.0L) * acc / n;
+    }
+    // sum_j cheb[j] T_j(t) in monomials, with T_{j+1} = 2 t T_j - T_{j-1}
+    std::fill(mono.begin(), mono.end(), 0.0L);
+    std::fill(tkm1.begin(), tkm1.end(), 0.0L);
+    std::fill(tk.begin(), tk.end(), 0.0L);
+    tkm1[0] = 1.0L;   // T_0
+    tk[1] = 1.0L;     // T_1
+    mono[0] += cheb[0];
+    if (n > 1)
+      for (int i = 0; i < n; i++) mono[i] += cheb[1] * tk[i];
+    for (int j = 2; j < n; j++) {
+      std::fill(tkp1.begin(), tkp1.end(), 0.0L);
+      for (int i = 0; i + 1 < n; i++) tkp1[i + 1] += 2.0L * tk[i];
+      for (int i = 0; i < n; i++) tkp1[i] -= tkm1[i];
+      for (int i = 0; i < n; i++) mono[i] += cheb[j] * tkp1[i];
+      tkm1.swap(tk);
+      tk.swap(tkp1);
+    }
+    for (int i = 0; i < n; i++) coeffs[k * n + i] = (double)mono[i];
+  }
+  return ESN_OK;
+}
+

@@ -106,6 +106,7 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
   g.sub_start = p->d_sub_start;
   g.sub_len = p->d_sub_len;
   g.nsub = p->nsub;
+  g.ktab = p->kerevalmeth == 2 ? p->d_ktab : nullptr;
   return g;
 }
 
@@ -142,6 +143,7 @@ void destroy_all(esn_plan_s* p) {
   dfree(p, (void**)&p->d_nsub);
   dfree(p, (void**)&p->d_tiles);
   dfree(p, (void**)&p->d_flags);
+  dfree(p, &p->d_ktab);
   if (p->h_pinned) (void)hipHostFree(p->h_pinned);
   p->h_pinned = nullptr;
   fft_destroy(&p->fft);
@@ -214,7 +216,8 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   if (o.bin[0] < 0 || o.bin[1] < 0 || o.bin[2] < 0 || o.maxsubprob < 0 ||
       o.ntransf_chunk < 0 || o.block < 0 || o.block > 1024 ||
       (o.block != 0 && o.block % 64 != 0) || o.spread_method < 0 || o.spread_method > 3 ||
-      o.interp_method < 0 || o.interp_method > 3 || o.sort < 0 || o.sort > 3)
+      o.interp_method < 0 || o.interp_method > 3 || o.sort < 0 || o.sort > 3 ||
+      o.kerevalmeth < 0 || o.kerevalmeth > 2)
     return ESN_ERR_BAD_ARG;
 
   esn_plan_s* p = new (std::nothrow) esn_plan_s();
@@ -334,6 +337,28 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
     delete p;
     return code;
   };
+
+  // ---- kernel evaluation: exp and sqrt at every weight, or the piecewise
+  // polynomial table of Sec. 4.3.  Automatic: the table in double precision,
+  // where exp and sqrt are long FP64 instruction sequences, and exp and sqrt
+  // in single precision, where each is one hardware instruction.
+  p->kerevalmeth = o.kerevalmeth ? o.kerevalmeth : (prec == ESN_DOUBLE ? 2 : 1);
+  if (p->kerevalmeth == 2) {
+    std::vector<double> tab((size_t)w * (w + kPolyExtra + 1));
+    if (esn_kernel_poly(w, par.beta, tab.data()) != ESN_OK) return fail(ESN_ERR_BAD_ARG);
+    if (prec == ESN_DOUBLE) {
+      if (dalloc(p, &p->d_ktab, tab.size() * sizeof(double)) != ESN_OK ||
+          hipMemcpy(p->d_ktab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+              hipSuccess)
+        return fail(ESN_ERR_ALLOC);
+    } else {
+      const std::vector<float> tf(tab.begin(), tab.end());
+      if (dalloc(p, &p->d_ktab, tf.size() * sizeof(float)) != ESN_OK ||
+          hipMemcpy(p->d_ktab, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice) !=
+              hipSuccess)
+        return fail(ESN_ERR_ALLOC);
+    }
+  }
 
   // ---- correction factors p(k) per dim (FP64 quadrature on the GPU) ----
   {
@@ -748,6 +773,7 @@ extern "C" int esn_get_info(esn_plan p, esn_info* o) {
   o->device_bytes = p->device_bytes;
   o->ndense_units = ((p->type == 1 && p->spread_method == 3) ||
                      (p->type == 2 && p->interp_method == 3)) ? p->nsub : 0;
+  o->kerevalmeth = p->kerevalmeth;
   return ESN_OK;
 }
 

@@ -180,3 +180,46 @@ def test_phi_hat_semicircle_asymptote(w):
         asym = math.sqrt(2 * math.pi / beta) * (1 - r * r) ** -0.75 * math.exp(
             beta * (math.sqrt(1 - r * r) - 1))
         assert abs(phihat[kk] / asym - 1) < 3.0 / beta
+
+
+def _phi(beta, z):
+    """eq. (ES): exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1, 0 outside."""
+    z = np.asarray(z, dtype=float)
+    return np.where(np.abs(z) <= 1, np.exp(beta * (np.sqrt(np.maximum(1 - z * z, 0)) - 1)), 0.0)
+
+
+@pytest.mark.parametrize("w", range(2, 17))
+def test_kernel_poly_table_matches_kernel(w):
+    """Sec. 4.3: w intervals, degree w + 3.  The table reproduces phi on every
+    interval to well below the tolerance the width is chosen for
+    (eps = 10^-(w-1); FP64 rounding bounds it at w = 15, 16), and a point's w
+    window weights (window cells l0 .. l0 + w - 1, l0 = ceil(t - w/2)) come out
+    of one shared local coordinate."""
+    beta = 2.30 * w
+    c = B.esn_kernel_poly(w, beta)
+    assert c.shape == (w, w + 4)
+    t = np.linspace(-1, 1, 2001)
+    err = 0.0
+    for k in range(w):
+        z = (k + (t + 1) / 2 - w / 2) * (2 / w)
+        approx = np.polynomial.polynomial.polyval(t, c[k])
+        err = max(err, float(np.max(np.abs(approx - _phi(beta, z)))))
+    assert err <= max(0.1 * 10.0 ** (-(w - 1)), 1e-14), err
+    # window weights of a few points from the definition of the window
+    for tp in (3.0, 3.25, 3.5, 3.5 + 1e-9, 3.75, 3.999):
+        l0 = math.ceil(tp - w / 2)
+        direct = _phi(beta, (l0 + np.arange(w) - tp) / (w / 2))
+        u = l0 - tp + w / 2                  # in [0, 1)
+        tt = 2 * u - 1
+        table = np.array([np.polynomial.polynomial.polyval(tt, c[k]) for k in range(w)])
+        assert np.max(np.abs(table - direct)) <= max(0.1 * 10.0 ** (-(w - 1)), 1e-14)
+
+
+def test_kernel_poly_bad_args():
+    for w, beta in ((1, 2.3), (17, 39.1), (7, 0.0)):
+        with pytest.raises(B.EsnError):
+            B.esn_kernel_poly(w, beta)
+    o = B.esn_default_opts()
+    assert o.kerevalmeth == 0
+    o.kerevalmeth = 3   # rejected before any GPU use
+    assert B.esn_makeplan(1, 1, (10,), 1, 1, 1e-6, B.ESN_DOUBLE, opts=o)[0] == B.ESN_ERR_BAD_ARG

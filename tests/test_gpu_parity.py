@@ -216,3 +216,49 @@ def test_points_at_the_fine_grid_seam(case, type_):
         err = O.rel_l2(c, O.type2(coord_np(coords, prec), f, -1))
     print(f"seam {dim}d {prec} method {method} type {type_}: rel l2 {err:.2e}")
     assert err <= 10 * eps
+
+
+KEREVAL_CASES = [
+    # dim, N, M, points, prec, eps
+    (1, (500,), 20000, "uniform", "f64", 1e-12),
+    (2, (64, 48), 50000, "wrapped_gaussian", "f64", 1e-9),
+    (3, (24, 20, 16), 60000, "uniform", "f64", 1e-9),
+    (3, (32, 28, 24), 200000, "wrapped_gaussian", "f32", 1e-6),
+    (2, (100, 80), 100000, "uniform", "f32", 1e-5),
+    (3, (20, 20, 20), 50000, "uniform", "f32", 1e-3),
+]
+
+
+@pytest.mark.parametrize("case", KEREVAL_CASES,
+                         ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in KEREVAL_CASES])
+@pytest.mark.parametrize("type_", [1, 2])
+def test_kernel_table_and_direct_evaluation(case, type_):
+    """Both kernel evaluations (exp and sqrt at every weight, and the piecewise
+    polynomial table of Sec. 4.3) meet the bar with every spreading or
+    interpolation method, and agree with each other to eps (double precision)
+    or to the single precision rounding floor."""
+    dim, N, M, points, prec, eps = case
+    coords, c, f = _inputs(dim, N, M, points, prec, 600 + dim)
+    cn = coord_np(coords, prec)
+    ref = O.type1(cn, c, +1, N=N) if type_ == 1 else O.type2(cn, f, -1)
+    mkey = "spread_method" if type_ == 1 else "interp_method"
+    methods = [0, 1, 2]
+    if dim == 3 and prec == "f32" and eps >= 1e-6:
+        methods.append(3)
+    for m in methods:
+        outs = {}
+        for kev in (1, 2):
+            opts = {"kerevalmeth": kev}
+            if m:
+                opts[mkey] = m
+            if type_ == 1:
+                out, info = run_type1(coords, c, N, eps, prec, **opts)
+            else:
+                out, info = run_type2(coords, f, N, eps, prec, **opts)
+            assert info.kerevalmeth == kev
+            err = O.rel_l2(out, ref)
+            print(f"{dim}d {prec} type {type_} method {m} kerevalmeth {kev}: rel l2 {err:.2e}")
+            assert err <= 10 * eps
+            outs[kev] = out
+        # (single precision: both sit on the FP32 rounding floor, about 1e-6)
+        assert O.rel_l2(outs[2], outs[1]) <= (eps if prec == "f64" else max(eps, 1e-5))
