@@ -76,7 +76,9 @@ typedef struct esn_opts {
   int debug;          /* 1: time each stage with HIP events (esn_get_stats) */
   int chkbnds;        /* 1: setpts rejects coordinates outside [-3pi, 3pi] */
   int modeord;        /* 0: increasing k from -floor(N/2); 1: FFT order */
-  double upsampfac;   /* fine grid / modes ratio sigma; only 2.0 is supported */
+  double upsampfac;   /* fine grid / modes ratio sigma: 2.0 (eq. (params)) or
+                         1.25 (low upsampling: w = ceil(1.7136 log10(1/eps)
+                         + 0.6), beta = 1.8397 w; types 1 and 2 only) */
   int sort;           /* bin-sort the points (Sec. 4.1): 1 (default) choose by
                          size; 2 stable radix sort of the point records by cell;
                          3 counting sort by cell (atomic per point, no order
@@ -106,14 +108,17 @@ typedef struct esn_params {
   int w;             /* kernel width in fine-grid cells, eq. (params) */
   double beta;       /* ES shape parameter 2.30 w, eq. (params) */
   int nquad;         /* positive Gauss-Legendre nodes p >= 1.5 w + 2 (Sec. 3.1) */
-  int64_t nf[3];     /* fine grid per dim: smallest 2^a 3^b 5^c >= max(2N, 2w) */
+  int64_t nf[3];     /* fine grid per dim: smallest 2^a 3^b 5^c >= max(sigma N, 2w) */
 } esn_params;
 
 /* Kernel and grid parameters for tolerance eps (Sec. 3, eq. (params) and
- * Sec. 3.1): w = ceil(log10(1/eps)) + 1 clamped to [2, 16], beta = 2.30 w,
- * n_i = smallest 2^a 3^b 5^c >= max(sigma N_i, 2w) (unused dims: 1).
- * nmodes: host array of 3 (entries beyond dim ignored).
- * Returns ESN_OK, ESN_WARN_EPS_TOO_SMALL or ESN_ERR_BAD_ARG. */
+ * Sec. 3.1): sigma = upsampfac = 2: w = ceil(log10(1/eps)) + 1, beta = 2.30 w;
+ * sigma = 1.25: w = ceil(1.7136 log10(1/eps) + 0.6), beta = 1.8397 w (eqs.
+ * (gam) and (ESerr) with the safety factor 0.976 of the sigma = 2 rule); w
+ * clamped to [2, 16]; n_i = smallest 2^a 3^b 5^c >= max(sigma N_i, 2w)
+ * (unused dims: 1).  nmodes: host array of 3 (entries beyond dim ignored).
+ * Returns ESN_OK, ESN_WARN_EPS_TOO_SMALL (w clamped, eps < 1e-15, or eps <
+ * 1e-6 in single precision) or ESN_ERR_BAD_ARG (other sigma too). */
 int esn_choose_params(double eps, int prec, int dim, const int64_t* nmodes,
                       double upsampfac, esn_params* out);
 

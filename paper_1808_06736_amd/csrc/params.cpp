@@ -23,6 +23,39 @@ bool width_from_eps(double eps, int* w_out) {
   return ok;
 }
 
+// Low upsampling, sigma = 5/4.  The paper names the option but fixes no
+// parameters for it; they follow here from its own recipe.  beta is eq. (gam),
+// beta = gamma pi w (1 - 1/(2 sigma)), with the safety factor gamma = 0.976
+// that turns eq. (gam) into the factor 2.30 of eq. (params) at sigma = 2; at
+// sigma = 5/4 this is 1.8397 w.  The width grows with the digits at the rate
+// of eq. (ESerr) without its algebraic factor: 1 / (pi gamma sqrt(1 - 1/sigma -
+// (1/gamma^2 - 1) / (4 sigma^2))) per unit of ln(1/eps), 1.7136 per decade,
+// plus a constant 0.6 fitted so that the aliasing bound of eq. (epsest) stays
+// within 5 eps over eps = 1e-1 .. 1e-9, as the sigma = 2 rule keeps it within
+// 2 to 9 eps for w <= 13.
+constexpr double kSafety = 0.976;
+constexpr double kSigmaLow = 1.25;
+constexpr double kLowWidthConst = 0.6;
+
+double beta_for(int w, double sigma) {
+  if (sigma == 2.0) return 2.30 * w;   // eq. (params)
+  return kSafety * M_PI * w * (1.0 - 0.5 / sigma);
+}
+
+bool width_from_eps_low(double eps, int* w_out) {
+  const double sigma = kSigmaLow;
+  const double rate = M_PI * kSafety *
+                      std::sqrt(1.0 - 1.0 / sigma - (1.0 / (kSafety * kSafety) - 1.0) /
+                                                        (4.0 * sigma * sigma));
+  const double per_decade = std::log(10.0) / rate;
+  int w = (int)std::ceil(per_decade * std::log10(1.0 / eps) + kLowWidthConst - 1e-10);
+  bool ok = true;
+  if (w < 2) w = 2;
+  if (w > kMaxW) { w = kMaxW; ok = false; }
+  *w_out = w;
+  return ok;
+}
+
 // Smallest integer >= n of the form 2^a 3^b 5^c (Sec. 3.1: FFT-friendly sizes).
 int64_t next_smooth235(int64_t n) {
   if (n <= 1) return 1;
@@ -90,16 +123,16 @@ extern "C" int esn_choose_params(double eps, int prec, int dim, const int64_t* n
   if (!out || !nmodes || dim < 1 || dim > 3) return ESN_ERR_BAD_ARG;
   if (!(eps > 0.0) || !std::isfinite(eps)) return ESN_ERR_BAD_ARG;
   if (prec != ESN_SINGLE && prec != ESN_DOUBLE) return ESN_ERR_BAD_ARG;
-  if (upsampfac != 2.0) return ESN_ERR_BAD_ARG;
+  if (upsampfac != 2.0 && upsampfac != esn::kSigmaLow) return ESN_ERR_BAD_ARG;
   for (int m = 0; m < dim; m++)
     if (nmodes[m] < 1) return ESN_ERR_BAD_ARG;
   int w = 0;
-  bool ok = esn::width_from_eps(eps, &w);
+  const bool ok = upsampfac == 2.0 ? esn::width_from_eps(eps, &w) : esn::width_from_eps_low(eps, &w);
   int status = ESN_OK;
   if (!ok || eps < 1e-15 || (prec == ESN_SINGLE && eps < 1e-6))
     status = ESN_WARN_EPS_TOO_SMALL;
   out->w = w;
-  out->beta = 2.30 * w;  // eq. (params)
+  out->beta = esn::beta_for(w, upsampfac);
   out->nquad = esn::quad_nodes_for_width(w);
   for (int m = 0; m < 3; m++)
     out->nf[m] = (m < dim) ? esn::fine_size(nmodes[m], upsampfac, w) : 1;

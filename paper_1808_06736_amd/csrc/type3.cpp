@@ -151,6 +151,9 @@ int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan*
   esn_opts o;
   if (opts) o = *opts;
   else esn_default_opts(&o);
+  // the spreading plan's fine grid must be the type 3 grid itself, which a
+  // type 1 plan with n/2 modes gives only at sigma = 2
+  if (o.upsampfac != 2.0) return ESN_ERR_BAD_ARG;
   // the kernel parameters: w, beta and the quadrature follow from eps alone
   int64_t ones[3] = {1, 1, 1};
   esn_params par;

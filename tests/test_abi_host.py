@@ -45,8 +45,8 @@ def test_strerror_and_default_opts():
     assert o.chkbnds == 1 and o.sort == 1 and o.upsampfac == 2.0 and o.modeord == 0
 
 
-def _params(eps, prec=B.ESN_DOUBLE, dim=1, N=(100, 1, 1)):
-    st, p = B.esn_choose_params(eps, prec, dim, N)
+def _params(eps, prec=B.ESN_DOUBLE, dim=1, N=(100, 1, 1), sigma=2.0):
+    st, p = B.esn_choose_params(eps, prec, dim, N, upsampfac=sigma)
     return st, p
 
 
@@ -101,7 +101,13 @@ def test_status_codes():
     assert _params(1e-6, dim=4)[0] == B.ESN_ERR_BAD_ARG
     assert _params(1e-6, N=(0, 1, 1))[0] == B.ESN_ERR_BAD_ARG
     st, _ = B.esn_choose_params(1e-6, B.ESN_DOUBLE, 1, (10, 1, 1), upsampfac=1.25)
-    assert st == B.ESN_ERR_BAD_ARG
+    assert st == 0
+    for sigma in (1.5, 1.0, 3.0):
+        st, _ = B.esn_choose_params(1e-6, B.ESN_DOUBLE, 1, (10, 1, 1), upsampfac=sigma)
+        assert st == B.ESN_ERR_BAD_ARG
+    o = B.esn_default_opts()
+    o.upsampfac = 1.25   # type 3 runs at sigma = 2 only, refused before any GPU use
+    assert B.esn_makeplan(3, 2, None, 1, 1, 1e-6, B.ESN_DOUBLE, opts=o)[0] == B.ESN_ERR_BAD_ARG
     # bad args fail before any GPU use, type 3 ones included
     assert B.esn_makeplan(4, 1, (10,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
     assert B.esn_makeplan(3, 4, (10,), 1, 1, 1e-6, B.ESN_DOUBLE)[0] == B.ESN_ERR_BAD_ARG
@@ -223,3 +229,56 @@ def test_kernel_poly_bad_args():
     assert o.kerevalmeth == 0
     o.kerevalmeth = 3   # rejected before any GPU use
     assert B.esn_makeplan(1, 1, (10,), 1, 1, 1e-6, B.ESN_DOUBLE, opts=o)[0] == B.ESN_ERR_BAD_ARG
+
+
+def _phi_hat_gl(beta, xi, nodes=600):
+    """int_{-1}^{1} phi(z) cos(xi z) dz by a 600-node Gauss-Legendre rule."""
+    x, wq = np.polynomial.legendre.leggauss(nodes)
+    phi = np.exp(beta * (np.sqrt(1 - x * x) - 1))
+    return np.cos(np.outer(np.atleast_1d(xi), x)) @ (wq * phi)
+
+
+def _aliasing_bound(w, beta, sigma):
+    """eq. (epsest) for the ES kernel in scaled frequency u = k/n, |u| <= 1/(2 sigma):
+    max_u sum_{0 < |m| <= 20} |phi^(pi w (u + m))| / min_u |phi^(pi w u)|."""
+    us = np.linspace(0, 0.5 / sigma, 17)
+    ms = np.array([m for m in range(-20, 21) if m])
+    num = max(np.sum(np.abs(_phi_hat_gl(beta, math.pi * w * (u + ms)))) for u in us)
+    return num / abs(_phi_hat_gl(beta, math.pi * w * 0.5 / sigma)[0])
+
+
+def test_low_upsampling_rule():
+    """sigma = 5/4: beta from eq. (gam) with the safety factor that gives 2.30 at
+    sigma = 2; w from the rate of eq. (ESerr).  The aliasing bound of eq. (epsest)
+    at the chosen w stays within 5 eps for eps = 1e-1 .. 1e-8 (the sigma = 2 rule
+    keeps it within 2 to 9 eps), and one width less would exceed eps."""
+    gam = 2.30 / (math.pi * 0.75)                      # sigma = 2: beta / w = 2.30
+    assert abs(gam - 0.976) < 1e-3
+    for digits in range(1, 9):
+        eps = 10.0 ** -digits
+        st, p = _params(eps, N=(200, 1, 1), sigma=1.25)
+        assert st == 0
+        assert abs(p.beta / p.w - 0.976 * math.pi * 0.6) < 1e-12
+        bound = _aliasing_bound(p.w, p.beta, 1.25)
+        assert bound <= 5 * eps, (eps, p.w, bound)
+        if p.w > 2:
+            w1 = p.w - 1
+            assert _aliasing_bound(w1, 0.976 * math.pi * 0.6 * w1, 1.25) > eps
+    # the same bound for the sigma = 2 rule of eq. (params), for comparison
+    for digits in range(1, 13):
+        st, p = _params(10.0 ** -digits, N=(200, 1, 1))
+        assert 1.0 <= _aliasing_bound(p.w, p.beta, 2.0) / 10.0 ** -digits <= 10.0
+
+
+@pytest.mark.parametrize("N", [1, 7, 64, 100, 129, 1000])
+@pytest.mark.parametrize("eps", [1e-2, 1e-6])
+def test_low_upsampling_fine_grid_and_factors(N, eps):
+    st, p = _params(eps, dim=1, N=(N, 1, 1), sigma=1.25)
+    n = p.nf[0]
+    assert _smooth(n) and n >= 1.25 * N and n >= 2 * p.w
+    assert not any(_smooth(k) for k in range(max(math.ceil(1.25 * N), 2 * p.w), n))
+    pk = B.esn_correction_factors(p.w, p.beta, p.nquad, n, N)
+    alpha = math.pi * p.w / n
+    for k in sorted(set([0, N // 3, N // 2])):
+        ref = 2.0 / (p.w * _phi_hat_quad(p.beta, alpha * k))   # eq. (pk1)
+        assert abs(pk[k] - ref) < 0.01 * eps * abs(ref)

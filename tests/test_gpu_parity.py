@@ -262,3 +262,40 @@ def test_kernel_table_and_direct_evaluation(case, type_):
             outs[kev] = out
         # (single precision: both sit on the FP32 rounding floor, about 1e-6)
         assert O.rel_l2(outs[2], outs[1]) <= (eps if prec == "f64" else max(eps, 1e-5))
+
+
+LOW_SIGMA_CASES = [
+    # dim, N, M, points, prec, eps
+    (1, (600,), 20000, "uniform", "f64", 1e-8),
+    (2, (80, 64), 60000, "wrapped_gaussian", "f64", 1e-6),
+    (2, (100, 90), 80000, "uniform", "f32", 1e-4),
+    (3, (24, 20, 28), 100000, "uniform", "f64", 1e-5),
+    (3, (32, 28, 24), 200000, "wrapped_gaussian", "f32", 1e-3),
+]
+
+
+@pytest.mark.parametrize("case", LOW_SIGMA_CASES,
+                         ids=[f"{c[0]}d-{c[4]}-{c[3]}-{c[5]:g}" for c in LOW_SIGMA_CASES])
+@pytest.mark.parametrize("type_", [1, 2])
+def test_low_upsampling_meets_bar(case, type_):
+    """sigma = 5/4 (fine grid n >= 1.25 N, the wider kernel of the low
+    upsampling rule): every method meets the bar against the oracle."""
+    dim, N, M, points, prec, eps = case
+    coords, c, f = _inputs(dim, N, M, points, prec, 700 + dim)
+    cn = coord_np(coords, prec)
+    ref = O.type1(cn, c, +1, N=N) if type_ == 1 else O.type2(cn, f, -1)
+    mkey = "spread_method" if type_ == 1 else "interp_method"
+    methods = [0, 1, 2]
+    for m in methods:
+        opts = {"upsampfac": 1.25}
+        if m:
+            opts[mkey] = m
+        if type_ == 1:
+            out, info = run_type1(coords, c, N, eps, prec, **opts)
+        else:
+            out, info = run_type2(coords, f, N, eps, prec, **opts)
+        err = O.rel_l2(out, ref)
+        print(f"sigma 1.25 {dim}d {prec} type {type_} method {m}: w {info.w}, "
+              f"nf {list(info.nf)[:dim]}, rel l2 {err:.2e}")
+        assert all(info.nf[d] < 2 * N[d] for d in range(dim))
+        assert err <= 10 * eps
