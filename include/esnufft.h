@@ -266,6 +266,30 @@ int esn_3d2(int64_t M, const double* x, const double* y, const double* z, void* 
             int isign, double eps, int64_t N1, int64_t N2, int64_t N3,
             const void* f, int prec, const esn_opts* opts, void* stream);
 
+/* ---- normal operator in Toeplitz form (inverse NUFFT by conjugate gradients
+ * on the normal equations, Sec. 1 remark on the inverse NUFFT) -------------- */
+typedef struct esn_toeplitz_s* esn_toeplitz;
+
+/* T = A^H W A for A the type 2 transform of sign isign with N modes on the M
+ * points x, y, z (eq. (2)), W = diag(weights): (T f)_k = sum_k' t_{k-k'} f_k',
+ * t_m = sum_j w_j exp(-isign i m.x_j).  Set-up runs one type 1 transform of the
+ * weights on 2 N_i modes per dimension (tolerance eps) and the FFT of the
+ * result; esn_toeplitz_apply then costs two FFTs of prod(2 N_i) points.
+ * dim 1..3; nmodes host[3]; prec ESN_SINGLE/ESN_DOUBLE; coordinates: device
+ * arrays of M values in coord_prec (as esn_setpts); weights: device array of M
+ * complex values in prec, or NULL for all ones; opts: modeord sets the order of
+ * the mode arrays of esn_toeplitz_apply (other fields as for esn_makeplan);
+ * stream: hipStream_t or NULL.  Synchronises the stream.  Returns ESN_OK or a
+ * warning with *out set, else an error code with *out NULL. */
+int esn_toeplitz_makeplan(int dim, const int64_t* nmodes, int isign, double eps, int prec,
+                          int64_t M, int coord_prec, const void* x, const void* y, const void* z,
+                          const void* weights, esn_toeplitz* out, const esn_opts* opts,
+                          void* stream);
+/* g = T f; f, g: device arrays of N1 N2 N3 complex values (may not alias).
+ * Enqueued on the plan's stream; ESN_ERR_BAD_ARG on NULL pointers. */
+int esn_toeplitz_apply(esn_toeplitz t, const void* f, void* g);
+int esn_toeplitz_destroy(esn_toeplitz t);
+
 /* ---- serving: a request loop for many independent transforms -------------
  * Not from the paper (its remark on repeated small problems, Sec. 2, is what
  * plan reuse answers); this is the library's own continuous-batching front

@@ -10,6 +10,7 @@ every call raises.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import warnings
 
@@ -109,6 +110,10 @@ _SIGS = {
     "esn_gauss_legendre": ([ci, vp, vp], ci),
     "esn_correction_factors": ([ci, cd, ci, i64, i64, vp], ci),
     "esn_kernel_poly": ([ci, cd, vp], ci),
+    "esn_toeplitz_makeplan": ([ci, ctypes.POINTER(i64), ci, cd, ci, i64, ci, vp, vp, vp, vp,
+                               ctypes.POINTER(vp), ctypes.POINTER(EsnOpts), vp], ci),
+    "esn_toeplitz_apply": ([vp, vp, vp], ci),
+    "esn_toeplitz_destroy": ([vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
     "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
     "esn_server_submit": ([vp, ctypes.POINTER(EsnRequest), ctypes.POINTER(ctypes.c_longlong)], ci),
@@ -534,6 +539,85 @@ class Plan3:
     def close(self):
         if getattr(self, "handle", None):
             esn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- normal operator in Toeplitz form --------------------------------------------
+def esn_toeplitz_makeplan(dim, nmodes, isign, eps, prec, M, coord_prec, xs, weights=None,
+                          opts=None, stream=None):
+    h = vp()
+    xs = list(xs) + [None] * (3 - len(xs))
+    st = lib().esn_toeplitz_makeplan(int(dim), _i64x3(nmodes), int(isign), float(eps), int(prec),
+                                     int(M), int(coord_prec), xs[0], xs[1], xs[2], weights,
+                                     ctypes.byref(h),
+                                     ctypes.byref(opts) if opts is not None else None, stream)
+    return st, h
+
+
+def esn_toeplitz_apply(t, f, g):
+    return lib().esn_toeplitz_apply(t, f, g)
+
+
+def esn_toeplitz_destroy(t):
+    return lib().esn_toeplitz_destroy(t)
+
+
+class Toeplitz:
+    """The normal operator T = A^H W A of a type 2 transform A (sign isign, modes
+    N) on given points, W = diag(weights), over torch CUDA tensors:
+    ``Toeplitz(coords, N, eps, dtype=torch.complex64, isign=-1, weights=None,
+    **opts)``; ``apply(f)`` -> T f (modes in the order of opts modeord).  Work is
+    enqueued on torch's current stream."""
+
+    def __init__(self, coords, N, eps, dtype=None, isign=-1, weights=None, **opts):
+        import torch
+        self.torch = torch
+        self.N = tuple(int(n) for n in N)
+        self.dim = len(self.N)
+        self.dtype = dtype or torch.complex64
+        if self.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        prec = ESN_SINGLE if self.dtype == torch.complex64 else ESN_DOUBLE
+        if len(coords) != self.dim:
+            raise ValueError(f"need {self.dim} coordinate arrays")
+        cdt = coords[0].dtype
+        M = coords[0].numel()
+        for a in coords:
+            if a.dtype != cdt or a.numel() != M or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("coordinates: same dtype and length, contiguous, on the GPU")
+        if weights is not None and (weights.dtype != self.dtype or weights.numel() != M or
+                                    not weights.is_cuda or not weights.is_contiguous()):
+            raise ValueError(f"weights: a contiguous {self.dtype} CUDA tensor of {M} values")
+        ptr = lambda a: vp(a.data_ptr()) if a is not None and a.numel() else None
+        self.opts = make_opts(**opts)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        st, h = esn_toeplitz_makeplan(self.dim, self.N, int(isign), eps, prec, M,
+                                      ESN_SINGLE if cdt == torch.float32 else ESN_DOUBLE,
+                                      [ptr(a) for a in coords], ptr(weights), self.opts,
+                                      _stream_handle(torch))
+        check(st, "esn_toeplitz_makeplan")
+        self.handle = h
+
+    def apply(self, f, out=None):
+        shape = tuple(reversed(self.N))
+        if f.dtype != self.dtype or not f.is_cuda or not f.is_contiguous() or \
+                f.numel() != math.prod(self.N):
+            raise ValueError(f"f: must be a contiguous {self.dtype} CUDA tensor of {shape}")
+        g = out if out is not None else self.torch.empty(shape, dtype=self.dtype,
+                                                         device=self.device)
+        check(esn_toeplitz_apply(self.handle, vp(f.data_ptr()), vp(g.data_ptr())),
+              "esn_toeplitz_apply")
+        return g
+
+    def close(self):
+        if getattr(self, "handle", None):
+            esn_toeplitz_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -207,6 +207,20 @@ hipError_t launch_t3_targets(const T3Args& a, int coord_prec, int prec, const vo
 hipError_t launch_cmul(int prec, const void* in, const void* fac, void* out, int64_t n, int ntr,
                        hipStream_t s);
 
+// ---- Toeplitz form of the normal operator (kernels_toeplitz.hip, toeplitz.cpp) ----
+struct ToepArgs {
+  int64_t N[3];    // modes per dim (1 for unused dims)
+  int64_t L[3];    // doubled grid 2 N (1 for unused dims)
+  int modeord;     // order of the caller's mode arrays
+};
+hipError_t launch_fill_ones(int prec, void* c, int64_t n, hipStream_t s);
+hipError_t launch_scale(int prec, void* v, int64_t n, double s, hipStream_t st);
+// grid (L) = the caller's modes f at positions k + floor(N/2), zeros elsewhere
+hipError_t launch_toep_pad(const ToepArgs& a, int prec, const void* f, void* grid, hipStream_t s);
+// f = the modes back out of grid positions k + floor(N/2)
+hipError_t launch_toep_extract(const ToepArgs& a, int prec, const void* grid, void* f,
+                               hipStream_t s);
+
 // Plan creation behind esn_makeplan for types 1 and 2; spread_only: no FFT
 // plans and no fine grid (a plan that sorts points and spreads into caller
 // grids, esn_spread).

@@ -282,3 +282,13 @@ def test_low_upsampling_fine_grid_and_factors(N, eps):
     for k in sorted(set([0, N // 3, N // 2])):
         ref = 2.0 / (p.w * _phi_hat_quad(p.beta, alpha * k))   # eq. (pk1)
         assert abs(pk[k] - ref) < 0.01 * eps * abs(ref)
+
+
+def test_toeplitz_bad_args_fail_before_gpu_use():
+    for dim, N, isign, M in ((4, (8,), 1, 10), (1, (0,), 1, 10), (1, (8,), 0, 10),
+                             (1, (8,), 1, -1)):
+        st, h = B.esn_toeplitz_makeplan(dim, N, isign, 1e-6, B.ESN_DOUBLE, M, B.ESN_DOUBLE,
+                                        [None])
+        assert st == B.ESN_ERR_BAD_ARG and not h.value
+    assert B.esn_toeplitz_apply(None, None, None) == B.ESN_ERR_BAD_ARG
+    assert B.esn_toeplitz_destroy(None) == 0
