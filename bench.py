@@ -169,47 +169,56 @@ def main():
         plans[t].setpts(*coords)
     torch.cuda.synchronize()
 
+    # Stage times come from the library's HIP events around each stage, recorded
+    # on the plan's stream during the timed loop and read after it (no host
+    # synchronisation inside the loop).
     def stage_rec(t, st_set, s):
         return (t, st_set, s.t_spread_or_interp, s.t_fft, s.t_deconv_or_amplify, s.t_execute)
 
-    def step_shared(record=None):
+    def step_shared():
         p = plans[1]
         p.setpts(*coords)
-        st_set = p.stats().t_setpts
         p.execute(c_in, outs[1])
-        if record is not None:
-            record.append(stage_rec(1, st_set, p.stats()))
         p.execute_adjoint(outs[2], f_in)
-        if record is not None:
-            record.append(stage_rec(2, 0.0, p.stats()))
 
-    def step_separate(pl, record=None):
+    def step_separate(pl):
         for t in wl.types:
             p = pl[t]
             p.setpts(*coords)
-            st_set = p.stats().t_setpts
             if t == 1:
                 p.execute(c_in, outs[1])
             else:
                 p.execute(outs[2], f_in)
-            if record is not None:
-                record.append(stage_rec(t, st_set, p.stats()))
+
+    def history(p, calls_per_step, types_of_execs):
+        """Per-step stage records from the plan's last steps: entries come as
+        setpts then the step's executes."""
+        h = p.stats_history(256)
+        n = min(args.steps, len(h) // calls_per_step)
+        h = h[len(h) - n * calls_per_step:]
+        rec = []
+        for k in range(n):
+            grp = h[k * calls_per_step:(k + 1) * calls_per_step]
+            for i, t in enumerate(types_of_execs):
+                rec.append(stage_rec(t, grp[0].t_setpts if i == 0 else 0.0, grp[1 + i]))
+        return rec
 
     def timed(step):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        rec = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(rec)
+            step()
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, rec
+        return time.perf_counter() - t0
 
     if shared:
-        elapsed, rec = timed(step_shared)
+        elapsed = timed(step_shared)
+        rec = history(plans[1], 3, [1, 2])
     else:
-        elapsed, rec = timed(lambda r=None: step_separate(plans, r))
+        elapsed = timed(lambda: step_separate(plans))
+        rec = [r for t in wl.types for r in history(plans[t], 2, [t])]
     ms_per_step = 1e3 * elapsed / args.steps
     pts_per_step = M * ntr * len(wl.types)
     value = pts_per_step / (elapsed / args.steps)
@@ -233,7 +242,8 @@ def main():
         sep_plans = {t: B.Plan(t, N, wl.eps, dtype=cdt, ntransf=ntr, debug=1) for t in wl.types}
         for p in sep_plans.values():
             p.setpts(*coords)
-        sep_elapsed, sep_rec = timed(lambda r=None: step_separate(sep_plans, r))
+        sep_elapsed = timed(lambda: step_separate(sep_plans))
+        sep_rec = [r for t in wl.types for r in history(sep_plans[t], 2, [t])]
         separate = {"ms_per_step": 1e3 * sep_elapsed / args.steps,
                     "value": pts_per_step / (sep_elapsed / args.steps),
                     "setpts_ms": {f"type{t}": float(np.mean([x[1] for x in sep_rec if x[0] == t]))

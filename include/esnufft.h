@@ -228,11 +228,21 @@ int esn_get_info(esn_plan p, esn_info* out);
 
 typedef struct esn_stats {
   /* milliseconds of the last setpts / execute, by stage (debug = 1 only).
+   * Types 1 and 2 record HIP events around the stages and read them only
+   * here, so timing adds no host synchronisation to the calls; reading waits
+   * for the calls timed.
    * Type 3 plans: t_spread_or_interp = spreading (step 1), t_fft = the inner
    * type 2 transform (step 2), t_deconv_or_amplify = that transform's
    * interpolation alone. */
   double t_setpts, t_spread_or_interp, t_fft, t_deconv_or_amplify, t_execute;
 } esn_stats;
+
+/* Stage times of the plan's most recent setpts and execute calls (types 1
+ * and 2, debug = 1), oldest first: up to max entries (at most 256 are kept)
+ * into out, their number into *count.  A setpts entry has t_setpts only, an
+ * execute entry the other fields.  Waits for the calls timed.  Lets a caller
+ * time a loop of calls without a synchronisation in it. */
+int esn_get_stats_history(esn_plan p, esn_stats* out, int max, int* count);
 
 /* Copy the plan's GPU-computed correction factors of dimension m (0-based,
  * floor(N_m/2) + 1 doubles) into the host array out of length len.

@@ -50,7 +50,7 @@ def candidates(type_, dim, prec, w, ntransf):
     if dim == 1:
         bins = [(256,), (1024,), (4096,)]
     elif dim == 2:
-        bins = [(8, 8), (16, 16), (32, 32)]
+        bins = [(8, 8), (16, 8), (16, 16), (32, 32)]
     else:
         bins = [(4, 4, 4), (8, 8, 8)]
     for b in bins:

@@ -113,6 +113,7 @@ _SIGS = {
     "esn_toeplitz_makeplan": ([ci, ctypes.POINTER(i64), ci, cd, ci, i64, ci, vp, vp, vp, vp,
                                ctypes.POINTER(vp), ctypes.POINTER(EsnOpts), vp], ci),
     "esn_toeplitz_apply": ([vp, vp, vp], ci),
+    "esn_get_stats_history": ([vp, ctypes.POINTER(EsnStats), ci, ctypes.POINTER(ci)], ci),
     "esn_toeplitz_destroy": ([vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
     "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
@@ -354,6 +355,10 @@ class Plan:
     def stats(self) -> EsnStats:
         return esn_get_stats(self.handle)
 
+    def stats_history(self, max_entries=256):
+        """Stage times of the latest setpts / execute calls, oldest first (debug plans)."""
+        return esn_get_stats_history(self.handle, max_entries)
+
     def setpts(self, *coords):
         torch = self.torch
         if len(coords) != self.dim:
@@ -549,6 +554,15 @@ class Plan3:
 
 
 # ---- normal operator in Toeplitz form --------------------------------------------
+def esn_get_stats_history(plan, max_entries=256):
+    """Stage times of the plan's latest setpts / execute calls, oldest first."""
+    buf = (EsnStats * int(max_entries))()
+    n = ci()
+    check(lib().esn_get_stats_history(plan, buf, int(max_entries), ctypes.byref(n)),
+          "esn_get_stats_history")
+    return [buf[k] for k in range(n.value)]
+
+
 def esn_toeplitz_makeplan(dim, nmodes, isign, eps, prec, M, coord_prec, xs, weights=None,
                           opts=None, stream=None):
     h = vp()

@@ -35,6 +35,18 @@ inline int pts_record_bytes(int code) { return code == kPtsFixed32 ? 16 : 32; }
 
 // Everything a spread/interp kernel needs about the geometry and the sorted
 // points.  Passed by value.
+// Stage events of one setpts or execute of a debug plan (types 1 and 2).
+// kind 1: setpts (e0 start, e1 end); kind 2 / 3: single-chunk execute in the
+// type 1 / type 2 direction (e5 start, e0 .. e3 around the stage before the
+// FFT, the FFT and the stage after it, e4 end); kind 4: values computed at the
+// call (multi-chunk execute).
+struct TimingRec {
+  int kind = 0;
+  hipEvent_t e[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  esn_stats vals{};
+};
+constexpr int kTimingRing = 256;
+
 // Piecewise polynomial kernel (Sec. 4.3): degree w + kPolyExtra per interval.
 constexpr int kPolyExtra = 3;
 
@@ -226,6 +238,8 @@ hipError_t launch_toep_extract(const ToepArgs& a, int prec, const void* grid, vo
 // grids, esn_spread).
 int make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntransf, double eps,
               int prec, esn_plan* out, const esn_opts* opts, void* stream, bool spread_only);
+// Stage times of a debug plan's latest setpts and execute (waits for them).
+int plan_stats(esn_plan p, esn_stats* o);
 // Type 3 plans (type3.cpp).
 int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan* out,
                 const esn_opts* opts, void* stream);
@@ -355,9 +369,14 @@ struct esn_plan_s {
   double* h_t3_mm = nullptr;     // pinned copy of the partials
   int64_t t3_cap_M = 0, t3_cap_N = 0, t3_cap_grid = 0, t3_cap_xy = 0;
 
-  // debug timing
+  // debug timing.  Type 3 plans time their steps with ev and keep the values
+  // in stats.  Types 1 and 2 record the stage events of each setpts and
+  // execute in a ring and read them only when asked (esn_get_stats), so that
+  // timing adds no host synchronisation to the calls.
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   esn_stats stats{};
+  std::vector<esn::TimingRec> ring;
+  int64_t ring_count = 0;        // calls recorded so far
   int64_t device_bytes = 0;
   std::vector<std::pair<void*, size_t>> allocs;   // live device allocations
 };

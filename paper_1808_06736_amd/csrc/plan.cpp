@@ -129,6 +129,56 @@ void free_subs(esn_plan_s* p) {
 
 
 
+// The next timing record of a debug plan (its events created on first use),
+// or null when timing is off or an event cannot be made.
+TimingRec* timing_next(esn_plan_s* p, int kind) {
+  if (!p->opts.debug) return nullptr;
+  if (p->ring.empty()) p->ring.resize(kTimingRing);
+  TimingRec& r = p->ring[p->ring_count % kTimingRing];
+  // timing-only events: no system-scope fence (cache writeback and
+  // invalidation) when they are reached
+  for (auto& e : r.e)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+      return nullptr;
+  r.kind = kind;
+  r.vals = esn_stats{};
+  p->ring_count++;
+  return &r;
+}
+
+// Stage times of one record (waits for its last event).
+int timing_values(TimingRec& r, esn_stats* out) {
+  *out = esn_stats{};
+  float a = 0, b = 0, c = 0, t = 0;
+  switch (r.kind) {
+    case 1:
+      if (hipEventSynchronize(r.e[1]) != hipSuccess ||
+          hipEventElapsedTime(&t, r.e[0], r.e[1]) != hipSuccess)
+        return ESN_ERR_HIP;
+      out->t_setpts = t;
+      return ESN_OK;
+    case 2:
+    case 3:
+      if (hipEventSynchronize(r.e[4]) != hipSuccess ||
+          hipEventElapsedTime(&a, r.e[0], r.e[1]) != hipSuccess ||
+          hipEventElapsedTime(&b, r.e[1], r.e[2]) != hipSuccess ||
+          hipEventElapsedTime(&c, r.e[2], r.e[3]) != hipSuccess ||
+          hipEventElapsedTime(&t, r.e[5], r.e[4]) != hipSuccess)
+        return ESN_ERR_HIP;
+      // type 1 direction: spread, FFT, deconvolve; type 2: amplify, FFT, interpolate
+      out->t_spread_or_interp = r.kind == 2 ? a : c;
+      out->t_deconv_or_amplify = r.kind == 2 ? c : a;
+      out->t_fft = b;
+      out->t_execute = t;
+      return ESN_OK;
+    case 4:
+      *out = r.vals;
+      return ESN_OK;
+    default:
+      return ESN_OK;
+  }
+}
+
 void destroy_all(esn_plan_s* p) {
   (void)hipStreamSynchronize(p->stream);
   free_points(p);
@@ -152,6 +202,9 @@ void destroy_all(esn_plan_s* p) {
   fft_destroy(&p->fft_adj_tail);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& r : p->ring)
+    for (auto& e : r.e)
+      if (e) (void)hipEventDestroy(e);
   // anything still tracked (none is expected)
   for (auto& a : p->allocs) (void)hipFree(a.first);
   p->allocs.clear();
@@ -251,6 +304,13 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
 
   // ---- bins, subproblems, methods, chunk ----
   default_bins(dim, p->bin);
+  // 2D tiles: small bins keep several waves per CU on the LDS tiles (measured
+  // on 1e7 uniform points, 2000^2 grids: 16 x 8 spreads in half the time of
+  // 32 x 32; interpolation is best at 16 x 16)
+  if (dim == 2) {
+    p->bin[0] = 16;
+    p->bin[1] = type == 1 ? 8 : 16;
+  }
   // the matrix-core kernels (3D single precision, w <= 7) work best on small
   // bins: 8 x 4 x 4 (measured at M = 1e7 on 256^3 and 288^3 fine grids, with
   // clustered, uniform and half-box uniform points, for both kernels)
@@ -419,10 +479,6 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   }
   if (hipHostMalloc((void**)&p->h_pinned, 4 * 8, hipHostMallocDefault) != hipSuccess)
     return fail(ESN_ERR_ALLOC);
-  if (o.debug) {
-    for (auto& e : p->ev)
-      if (hipEventCreate(&e) != hipSuccess) return fail(ESN_ERR_HIP);
-  }
   *out = p;
   return p->warn;
 }
@@ -438,7 +494,8 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   ESN_HIP(hipSetDevice(p->device));
   hipStream_t s = p->stream;
   p->M = -1;
-  if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+  TimingRec* tr = timing_next(p, 1);
+  if (tr) ESN_HIP(hipEventRecord(tr->e[0], s));
   // bin sort method: the radix sort's fixed cost dominates for small point
   // sets, the counting sort's scattered atomics for large ones
   int method = 0;
@@ -562,13 +619,7 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   }
   p->nsub = nsub;
   p->M = M;
-  if (p->opts.debug) {
-    ESN_HIP(hipEventRecord(p->ev[1], s));
-    ESN_HIP(hipEventSynchronize(p->ev[1]));
-    float ms = 0;
-    ESN_HIP(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
-    p->stats.t_setpts = ms;
-  }
+  if (tr) ESN_HIP(hipEventRecord(tr->e[1], s));
   return ESN_OK;
 }
 
@@ -647,7 +698,11 @@ static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
   const int64_t G = nf_total(p), Nt = n_total(p);
   const double* pf[3] = {p->d_pf[0], p->d_pf[1], p->d_pf[2]};
   double t_a = 0, t_fft = 0, t_b = 0;
-  if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[5], s));
+  // one chunk: events only, read when asked; several: timed chunk by chunk here
+  const bool multi = p->ntransf > chunk;
+  TimingRec* tr = timing_next(p, multi ? 4 : (dir == 1 ? 2 : 3));
+  hipEvent_t* e = tr ? tr->e : nullptr;
+  if (e) ESN_HIP(hipEventRecord(e[5], s));
   for (int c0 = 0; c0 < p->ntransf; c0 += chunk) {
     const int ntr = std::min(chunk, p->ntransf - c0);
     FFTPlan* fp = ntr == chunk ? fft_full : fft_last;
@@ -655,46 +710,44 @@ static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
     char* ff = static_cast<char*>(f) + (size_t)c0 * Nt * cs;
     if (dir == 1) {
       ESN_HIP(hipMemsetAsync(p->d_grid, 0, (size_t)ntr * G * cs, s));
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+      if (e) ESN_HIP(hipEventRecord(e[0], s));
       ESN_TRY(run_spread(p, ntr, cc, p->d_grid));
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
+      if (e) ESN_HIP(hipEventRecord(e[1], s));
       ESN_TRY(fft_exec(fp, p->d_grid));
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[2], s));
+      if (e) ESN_HIP(hipEventRecord(e[2], s));
       ESN_HIP(launch_deconv(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
                             Nt, pf, s));
     } else {
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[0], s));
+      if (e) ESN_HIP(hipEventRecord(e[0], s));
       ESN_HIP(launch_amplify(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
                              Nt, pf, s));
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[1], s));
+      if (e) ESN_HIP(hipEventRecord(e[1], s));
       ESN_TRY(fft_exec(fp, p->d_grid));
-      if (p->opts.debug) ESN_HIP(hipEventRecord(p->ev[2], s));
+      if (e) ESN_HIP(hipEventRecord(e[2], s));
       ESN_TRY(run_interp(p, ntr, p->d_grid, cc));
     }
-    if (p->opts.debug) {
-      ESN_HIP(hipEventRecord(p->ev[3], s));
-      ESN_HIP(hipEventSynchronize(p->ev[3]));
+    if (e) ESN_HIP(hipEventRecord(e[3], s));
+    if (e && multi) {
+      ESN_HIP(hipEventSynchronize(e[3]));
       float a = 0, b = 0, d = 0;
-      ESN_HIP(hipEventElapsedTime(&a, p->ev[0], p->ev[1]));
-      ESN_HIP(hipEventElapsedTime(&b, p->ev[1], p->ev[2]));
-      ESN_HIP(hipEventElapsedTime(&d, p->ev[2], p->ev[3]));
+      ESN_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+      ESN_HIP(hipEventElapsedTime(&b, e[1], e[2]));
+      ESN_HIP(hipEventElapsedTime(&d, e[2], e[3]));
       t_a += a; t_fft += b; t_b += d;
     }
   }
-  if (p->opts.debug) {
-    ESN_HIP(hipEventRecord(p->ev[4], s));
-    ESN_HIP(hipEventSynchronize(p->ev[4]));
-    float tot = 0;
-    ESN_HIP(hipEventElapsedTime(&tot, p->ev[5], p->ev[4]));
-    if (dir == 1) {
-      p->stats.t_spread_or_interp = t_a;   // spread kernel(s) only
-      p->stats.t_deconv_or_amplify = t_b;
-    } else {
-      p->stats.t_deconv_or_amplify = t_a;
-      p->stats.t_spread_or_interp = t_b;
+  if (e) {
+    ESN_HIP(hipEventRecord(e[4], s));
+    if (multi) {
+      ESN_HIP(hipEventSynchronize(e[4]));
+      float tot = 0;
+      ESN_HIP(hipEventElapsedTime(&tot, e[5], e[4]));
+      esn_stats& v = tr->vals;
+      v.t_spread_or_interp = dir == 1 ? t_a : t_b;
+      v.t_deconv_or_amplify = dir == 1 ? t_b : t_a;
+      v.t_fft = t_fft;
+      v.t_execute = tot;
     }
-    p->stats.t_fft = t_fft;
-    p->stats.t_execute = tot;
   }
   return p->warn;
 }
@@ -785,10 +838,55 @@ extern "C" int esn_plan_correction(esn_plan p, int m, double* out, int64_t len) 
   return ESN_OK;
 }
 
+namespace esn {
+
+// Stats of a plan's latest setpts and latest execute (types 1 and 2: read from
+// the timing ring, waiting for those calls' events).
+int plan_stats(esn_plan p, esn_stats* o) {
+  if (p->type == 3) {
+    *o = p->stats;
+    return ESN_OK;
+  }
+  *o = esn_stats{};
+  bool have_set = false, have_exec = false;
+  const int64_t n = std::min<int64_t>(p->ring_count, kTimingRing);
+  for (int64_t k = 0; k < n && !(have_set && have_exec); k++) {
+    TimingRec& r = p->ring[(p->ring_count - 1 - k) % kTimingRing];
+    esn_stats v;
+    if (r.kind == 1 && !have_set) {
+      if (timing_values(r, &v) != ESN_OK) return ESN_ERR_HIP;
+      o->t_setpts = v.t_setpts;
+      have_set = true;
+    } else if (r.kind >= 2 && !have_exec) {
+      if (timing_values(r, &v) != ESN_OK) return ESN_ERR_HIP;
+      o->t_spread_or_interp = v.t_spread_or_interp;
+      o->t_fft = v.t_fft;
+      o->t_deconv_or_amplify = v.t_deconv_or_amplify;
+      o->t_execute = v.t_execute;
+      have_exec = true;
+    }
+  }
+  return ESN_OK;
+}
+
+}  // namespace esn
+
 extern "C" int esn_get_stats(esn_plan p, esn_stats* o) {
   if (!p || !o) return ESN_ERR_BAD_ARG;
   if (!p->opts.debug) return ESN_ERR_BAD_ARG;
-  *o = p->stats;
+  return plan_stats(p, o);
+}
+
+extern "C" int esn_get_stats_history(esn_plan p, esn_stats* out, int max, int* count) {
+  if (!p || !out || !count || max < 0) return ESN_ERR_BAD_ARG;
+  *count = 0;
+  if (!p->opts.debug || p->type == 3) return ESN_ERR_BAD_ARG;
+  const int64_t n = std::min<int64_t>(std::min<int64_t>(p->ring_count, kTimingRing), max);
+  for (int64_t k = 0; k < n; k++) {
+    TimingRec& r = p->ring[(p->ring_count - n + k) % kTimingRing];
+    if (timing_values(r, &out[k]) != ESN_OK) return ESN_ERR_HIP;
+  }
+  *count = (int)n;
   return ESN_OK;
 }
 

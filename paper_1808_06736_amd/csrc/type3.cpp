@@ -195,7 +195,7 @@ int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan*
   }
   if (o.debug) {
     for (auto& e : p->ev)
-      if (hipEventCreate(&e) != hipSuccess) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
         t3_destroy(p);
         delete p;
         return ESN_ERR_HIP;
@@ -363,7 +363,9 @@ int t3_execute(esn_plan p, void* c, void* f) {
     ESN_HIP(hipEventElapsedTime(&tot, p->ev[0], p->ev[4]));
     p->stats.t_spread_or_interp = sp;   // step 1 spreading
     p->stats.t_fft = in;                // step 2: the inner type 2 transform
-    p->stats.t_deconv_or_amplify = p->t3_inner->stats.t_spread_or_interp;   // its interpolation
+    esn_stats inner;
+    if (plan_stats(p->t3_inner, &inner) != ESN_OK) return ESN_ERR_HIP;
+    p->stats.t_deconv_or_amplify = inner.t_spread_or_interp;   // its interpolation
     p->stats.t_execute = tot;
   }
   return p->warn;

@@ -360,3 +360,30 @@ def test_plans_return_their_device_memory():
     t.cuda.empty_cache()
     free1 = t.cuda.mem_get_info()[0]
     assert free0 - free1 < 64 << 20, (free0, free1)
+
+
+def test_stage_times_are_read_after_the_calls():
+    """A debug plan records its stage events without synchronising; the latest
+    calls' stage times are read afterwards, in call order."""
+    t = torch()
+    N = (32, 24, 16)
+    coords = I.uniform_points(50000, 3, 511, np.float32)
+    c = I.complex_normal(50000, 512, np.complex64)
+    f = I.complex_normal(tuple(reversed(N)), 513, np.complex64)
+    p = B.Plan(1, N, 1e-6, dtype=t.complex64, debug=1)
+    for _ in range(3):
+        p.setpts(*[dev(a) for a in coords])
+        p.type1(dev(c))
+        p.adjoint(dev(f))
+    h = p.stats_history(9)
+    assert len(h) == 9
+    for k in range(3):
+        st, e1, e2 = h[3 * k], h[3 * k + 1], h[3 * k + 2]
+        assert st.t_setpts > 0 and st.t_execute == 0
+        for e in (e1, e2):
+            assert e.t_setpts == 0 and e.t_spread_or_interp > 0 and e.t_fft > 0
+            assert e.t_execute >= e.t_spread_or_interp + e.t_fft
+    s = p.stats()
+    assert s.t_setpts == h[6].t_setpts and s.t_execute == h[8].t_execute
+    assert len(p.stats_history(1000)) == 9    # every call recorded, none other
+    p.close()
