@@ -437,8 +437,9 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
 
 // Two waves per subproblem share the grid tile and the staged weights: in
 // each batch wave 0 computes the x and y weights and wave 1 the z weights and
-// each point's footprint origin in the tile; the waves then take alternate
-// runs (points of one 2 x 2 x 2 block of window cells).
+// each point's footprint origin in the tile; the waves then share the runs
+// (points of one 2 x 2 x 2 block of window cells): alternate 16-point steps of
+// longer runs, and one-step runs in turn.
 //
 // Matrix layout of a step (16 points q .. q + 15 of a run):
 //   A[m][k] = G[x, y, z(m), re/im(m)]   grid tile, m = lane & 15, k = lane >> 4,
@@ -550,13 +551,17 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
     __syncthreads();
     const bool starts = lane < nbatch && (lane == 0 || sorg[lane] != sorg[lane - 1]);
     uint64_t runs = __ballot(starts);
-    // this wave takes every other run
-    if (wv == 1 && runs) runs &= runs - 1;
+    // Runs of more than one 16-point step are taken by both waves in
+    // alternate steps (a batch is often a single run); one-step runs go to the
+    // waves in turn.
+    int nshort = 0;
     while (runs) {
       const int q0 = __ffsll((unsigned long long)runs) - 1;
       runs &= runs - 1;
       const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-      if (runs) runs &= runs - 1;   // skip the other wave's run
+      const bool one_step = q1 - q0 <= 16;
+      if (one_step && (nshort++ & 1) != wv) continue;
+      const int qstride = one_step ? 16 : 32;
       const int org = __builtin_amdgcn_readfirstlane(sorg[q0]);
       // grid operand of the run: one address per footprint row y, the x halves
       // at +8 floats
@@ -574,15 +579,17 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       // most 64, inside the staged rows)
       const float* wx = skx + n * 8 + kq;   // + 8 q: x slots kq, kq + 4; z at + 1024
       const float* wy = sky + n * 8;        // + 8 q: y slots 0 .. 7
-      float kxa_n = wx[8 * q0], kxb_n = wx[8 * q0 + 4];
-      float4 kya_n = *reinterpret_cast<const float4*>(wy + 8 * q0);
-      float4 kyb_n = *reinterpret_cast<const float4*>(wy + 8 * q0 + 4);
-      float kz0_n = wx[8 * q0 + 1024], kz4_n = wx[8 * q0 + 1028];
+      const int qs = one_step ? q0 : q0 + 16 * wv;   // this wave's first step
+      const int qf = min(qs, 64);
+      float kxa_n = wx[8 * qf], kxb_n = wx[8 * qf + 4];
+      float4 kya_n = *reinterpret_cast<const float4*>(wy + 8 * qf);
+      float4 kyb_n = *reinterpret_cast<const float4*>(wy + 8 * qf + 4);
+      float kz0_n = wx[8 * qf + 1024], kz4_n = wx[8 * qf + 1028];
       // A step's z-weighted sums are formed right after its products; their
       // cross-lane reduction and store run in the next step, behind its
       // matrix work.
       float rep = 0.f, imp = 0.f;
-      int qp = q0 - 16;   // the pending step (none before the first)
+      int qp = qs - qstride;   // the pending step (none before the first)
       auto finish = [&](float re, float im, int qb) {
         // the lower half of the wave sums re over lane groups (0, 2) and
         // (1, 3), the upper half im: each lane sends the part it does not
@@ -596,11 +603,11 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
         if ((kq & 1) == 0 && pt >= q0 && pt < q1)
           reinterpret_cast<float*>(sout)[2 * pt + (kq >> 1)] = v;
       };
-      for (int q = q0; q < q1; q += 16) {
+      for (int q = qs; q < q1; q += qstride) {
         const float kxa = kxa_n, kxb = kxb_n, kz0 = kz0_n, kz4 = kz4_n;
         const float ky[8] = {kya_n.x, kya_n.y, kya_n.z, kya_n.w, kyb_n.x, kyb_n.y, kyb_n.z, kyb_n.w};
         {
-          int qn = min(q + 16, 64);
+          int qn = min(q + qstride, 64);
           opaque(qn);
           kxa_n = wx[8 * qn];
           kxb_n = wx[8 * qn + 4];
