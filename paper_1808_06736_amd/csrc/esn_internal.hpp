@@ -363,7 +363,9 @@ struct esn_plan_s {
   void* d_t3_post = nullptr;     // [N] correction times postphase
   void* d_t3_grid = nullptr;     // [ntransf][n1 n2 n3] spread grid = inner modes
   void* d_t3_c = nullptr;        // [ntransf][M] prephased strengths
-  double* d_t3_xy = nullptr;     // [3][cap] rescaled coordinates (setpts scratch)
+  double* d_t3_xy = nullptr;     // [2][3][cap] rescaled sources, targets (setpts scratch)
+  hipStream_t t3_side = nullptr; // second stream: the targets' sort beside the sources'
+  hipEvent_t t3_ready = nullptr; // rescaled targets written
   std::vector<double> t3_zq, t3_wphi;   // quadrature nodes, weights * phi at them
   double* d_t3_mm = nullptr;     // min/max partials
   double* h_t3_mm = nullptr;     // pinned copy of the partials

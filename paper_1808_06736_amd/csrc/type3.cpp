@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <vector>
 
 #include "esn_internal.hpp"
@@ -184,6 +185,13 @@ int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan*
   for (int j = 0; j < par.nquad; j++)
     p->t3_wphi[j] =
         wq[j] * std::exp(par.beta * (std::sqrt(1.0 - p->t3_zq[j] * p->t3_zq[j]) - 1.0));
+  // the side stream (default priority) and its ordering event for setpts3
+  if (hipStreamCreateWithFlags(&p->t3_side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->t3_ready, hipEventDisableTiming) != hipSuccess) {
+    t3_destroy(p);
+    delete p;
+    return ESN_ERR_HIP;
+  }
   // per-block partials of up to six arrays, then the six (min, max) pairs
   const int nb = t3_minmax_blocks(kMaxPoints);
   if (t3_alloc(p, (void**)&p->d_t3_mm, sizeof(double) * 2 * 6 * (nb + 1)) ||
@@ -290,7 +298,7 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
   }
   const int64_t nxy = std::max<int64_t>(std::max(M, N), 1);
   if (nxy > p->t3_cap_xy) {
-    if (t3_alloc(p, (void**)&p->d_t3_xy, sizeof(double) * 3 * nxy)) return ESN_ERR_ALLOC;
+    if (t3_alloc(p, (void**)&p->d_t3_xy, sizeof(double) * 6 * nxy)) return ESN_ERR_ALLOC;
     p->t3_cap_xy = nxy;
   }
 
@@ -312,16 +320,29 @@ extern "C" int esn_setpts3(esn_plan p, int64_t M, int coord_prec, const void* x,
   }
   a.n = M;
   ESN_HIP(launch_t3_sources(a, coord_prec, p->prec, xs, p->d_t3_pre, st));
-  rc = esn_setpts(p->t3_spread, M, ESN_DOUBLE, a.out[0], dim > 1 ? a.out[1] : nullptr,
-                  dim > 2 ? a.out[2] : nullptr);
-  if (rc != ESN_OK) return rc;
 
-  // ---- targets: rescale, correction and postphase, sort (steps 2 and 3) ----
-  a.n = N;
-  ESN_HIP(launch_t3_targets(a, coord_prec, p->prec, ss, p->d_t3_post, st));
-  rc = esn_setpts(p->t3_inner, N, ESN_DOUBLE, a.out[0], dim > 1 ? a.out[1] : nullptr,
-                  dim > 2 ? a.out[2] : nullptr);
-  if (rc != ESN_OK) return rc;
+  // ---- targets: rescale, correction and postphase (steps 2 and 3) ----
+  T3Args b = a;
+  b.n = N;
+  for (int m = 0; m < 3; m++) b.out[m] = p->d_t3_xy + (3 + m) * p->t3_cap_xy;
+  ESN_HIP(launch_t3_targets(b, coord_prec, p->prec, ss, p->d_t3_post, st));
+
+  // ---- both sorts at once: the sources' on the plan's stream, the targets'
+  // on the side stream from a second host thread (each setpts waits for its
+  // own stream at its end) ----
+  ESN_HIP(hipEventRecord(p->t3_ready, st));
+  ESN_HIP(hipStreamWaitEvent(p->t3_side, p->t3_ready, 0));
+  if (plan_set_stream(p->t3_inner, p->t3_side) != ESN_OK) return ESN_ERR_FFT_PLAN;
+  std::future<int> inner = std::async(std::launch::async, [&]() {
+    return esn_setpts(p->t3_inner, N, ESN_DOUBLE, b.out[0], dim > 1 ? b.out[1] : nullptr,
+                      dim > 2 ? b.out[2] : nullptr);
+  });
+  const int rc_src = esn_setpts(p->t3_spread, M, ESN_DOUBLE, a.out[0],
+                                dim > 1 ? a.out[1] : nullptr, dim > 2 ? a.out[2] : nullptr);
+  const int rc_tgt = inner.get();
+  if (plan_set_stream(p->t3_inner, st) != ESN_OK) return ESN_ERR_FFT_PLAN;
+  if (rc_src != ESN_OK) return rc_src;
+  if (rc_tgt != ESN_OK) return rc_tgt;
   p->M = M;
   p->t3_N = N;
   if (p->opts.debug) {
@@ -382,6 +403,10 @@ void t3_destroy(esn_plan p) {
   t3_free(&p->d_t3_c);
   t3_free((void**)&p->d_t3_xy);
   t3_free((void**)&p->d_t3_mm);
+  if (p->t3_ready) (void)hipEventDestroy(p->t3_ready);
+  if (p->t3_side) (void)hipStreamDestroy(p->t3_side);
+  p->t3_ready = nullptr;
+  p->t3_side = nullptr;
   if (p->h_t3_mm) (void)hipHostFree(p->h_t3_mm);
   p->h_t3_mm = nullptr;
 }
