@@ -84,44 +84,80 @@ __device__ __forceinline__ int64_t pos_of(int64_t k, int64_t N, int modeord) {
   return k >= 0 ? k : k + N;
 }
 
+// Mode index k of fine-grid position g in one dimension (n cells, N modes), or
+// false where g holds no mode.
+__device__ __forceinline__ bool mode_at(int64_t g, int64_t N, int64_t n, int64_t* k) {
+  if (g < N - N / 2) {  // k = 0 .. ceil(N/2) - 1
+    *k = g;
+    return true;
+  }
+  if (g >= n - N / 2) {  // k = -floor(N/2) .. -1
+    *k = g - n;
+    return true;
+  }
+  return false;
+}
+
+// Threads walk the x positions of a fine-grid row; the launch grid walks the
+// rows (y from blockIdx.y, z from blockIdx.z), several per block, so no index
+// is divided.  Rows that hold no mode are only cleared, with no loads.
 template <typename T>
 __global__ void amplify_kernel(const CorrArgs a, cplx_t<T>* __restrict__ grid,
                                const cplx_t<T>* __restrict__ f) {
-  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ntot = a.nf[0] * a.nf[1] * a.nf[2];
-  if (gi >= ntot) return;
-  int64_t g[3];
-  g[0] = gi % a.nf[0];
-  const int64_t r = gi / a.nf[0];
-  g[1] = r % a.nf[1];
-  g[2] = r / a.nf[1];
-  bool inside = true;
-  int64_t k[3];
-  for (int m = 0; m < 3; m++) {
-    const int64_t N = a.N[m], n = a.nf[m];
-    if (g[m] < N - N / 2) k[m] = g[m];                // k = 0 .. ceil(N/2) - 1
-    else if (g[m] >= n - N / 2) k[m] = g[m] - n;      // k = -floor(N/2) .. -1
-    else { inside = false; k[m] = 0; }
+  cplx_t<T> zero;
+  zero.x = 0;
+  zero.y = 0;
+  for (int64_t g2 = blockIdx.z; g2 < a.nf[2]; g2 += gridDim.z) {
+    int64_t k2 = 0;
+    const bool in2 = mode_at(g2, a.N[2], a.nf[2], &k2);
+    for (int64_t g1 = blockIdx.y; g1 < a.nf[1]; g1 += gridDim.y) {
+      int64_t k1 = 0;
+      const bool row_in = mode_at(g1, a.N[1], a.nf[1], &k1) && in2;
+      const int64_t grow = a.nf[0] * (g1 + a.nf[1] * g2);
+      if (!row_in) {
+        for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < a.nf[0];
+             g0 += (int64_t)gridDim.x * blockDim.x)
+          for (int tr = 0; tr < a.ntr; tr++) grid[tr * a.gstride + grow + g0] = zero;
+        continue;
+      }
+      const double p12 = a.pf[1][k1 < 0 ? -k1 : k1] * a.pf[2][k2 < 0 ? -k2 : k2];
+      const int64_t frow =
+          a.N[0] * (pos_of(k1, a.N[1], a.modeord) + a.N[1] * pos_of(k2, a.N[2], a.modeord));
+      for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < a.nf[0];
+           g0 += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k0 = 0;
+        if (!mode_at(g0, a.N[0], a.nf[0], &k0)) {
+          for (int tr = 0; tr < a.ntr; tr++) grid[tr * a.gstride + grow + g0] = zero;
+          continue;
+        }
+        const T pt = (T)(a.pf[0][k0 < 0 ? -k0 : k0] * p12);
+        const int64_t fi = frow + pos_of(k0, a.N[0], a.modeord);
+        for (int tr = 0; tr < a.ntr; tr++) {
+          cplx_t<T> v = f[tr * a.fstride + fi];
+          v.x *= pt;
+          v.y *= pt;
+          grid[tr * a.gstride + grow + g0] = v;
+        }
+      }
+    }
   }
-  if (!inside) {
-    cplx_t<T> z;
-    z.x = 0;
-    z.y = 0;
-    for (int tr = 0; tr < a.ntr; tr++) grid[tr * a.gstride + gi] = z;
-    return;
-  }
-  const double p = a.pf[0][k[0] < 0 ? -k[0] : k[0]] * a.pf[1][k[1] < 0 ? -k[1] : k[1]] *
-                   a.pf[2][k[2] < 0 ? -k[2] : k[2]];
-  const T pt = (T)p;
-  const int64_t fi = pos_of(k[0], a.N[0], a.modeord) +
-                     a.N[0] * (pos_of(k[1], a.N[1], a.modeord) +
-                               a.N[1] * pos_of(k[2], a.N[2], a.modeord));
-  for (int tr = 0; tr < a.ntr; tr++) {
-    cplx_t<T> v = f[tr * a.fstride + fi];
-    v.x *= pt;
-    v.y *= pt;
-    grid[tr * a.gstride + gi] = v;
-  }
+}
+
+// Threads per block of the row kernels: 256, or the row length rounded up to
+// whole waves for shorter rows.
+static int row_block(int64_t n0) {
+  return n0 >= 256 ? 256 : (int)std::max<int64_t>(64, (n0 + 63) / 64 * 64);
+}
+
+// Launch grid over rows of n0 cells: about 8 x-steps of a row per block,
+// blocks spread over the y rows until about 8192 blocks are in flight.
+static dim3 row_grid(int64_t n0, int64_t n1, int64_t n2) {
+  const int64_t step = 8 * (int64_t)row_block(n0);
+  const int64_t gx = std::min<int64_t>((n0 + step - 1) / step, 65535);
+  const int64_t gz = std::min<int64_t>(n2, 65535);
+  const int64_t gy = std::min<int64_t>(std::max<int64_t>(n1, 1),
+                                       std::max<int64_t>(1, 8192 / (gx * gz)));
+  return dim3((unsigned)gx, (unsigned)std::min<int64_t>(gy, 65535), (unsigned)gz);
 }
 
 static CorrArgs make_corr(int dim, const int64_t* N, const int64_t* nf, int modeord, int ntr,
@@ -158,13 +194,12 @@ hipError_t launch_amplify(int prec, int dim, const int64_t* N, const int64_t* nf
                           int ntr, void* grid, int64_t gstride, const void* f, int64_t fstride,
                           const double* const* pf, hipStream_t s) {
   CorrArgs a = make_corr(dim, N, nf, modeord, ntr, gstride, fstride, pf);
-  const int64_t tot = a.nf[0] * a.nf[1] * a.nf[2];
-  const unsigned nb = (unsigned)((tot + 255) / 256);
+  const dim3 g = row_grid(a.nf[0], a.nf[1], a.nf[2]);
   if (prec == ESN_SINGLE)
-    hipLaunchKernelGGL(amplify_kernel<float>, dim3(nb), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(amplify_kernel<float>, g, dim3(row_block(a.nf[0])), 0, s, a,
                        static_cast<float2*>(grid), static_cast<const float2*>(f));
   else
-    hipLaunchKernelGGL(amplify_kernel<double>, dim3(nb), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(amplify_kernel<double>, g, dim3(row_block(a.nf[0])), 0, s, a,
                        static_cast<double2*>(grid), static_cast<const double2*>(f));
   return hipGetLastError();
 }
