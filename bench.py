@@ -21,7 +21,9 @@ One JSON line is printed.  Besides the contract fields it carries
   the timed region (the library's debug stage events);
 * ``cpu_baseline``: the FP64 oracle (direct sums) timed on a bounded sample of
   the same workload on the host cores, scaled to the metric's unit;
-* ``parity``: the GPU output's relative l2 error on that oracle sample.
+* ``parity``: the GPU output's relative l2 error on that oracle sample;
+* ``sort_ablation`` (both types on one point set): execute with the points
+  left unsorted against the bin-sorted execute, alone and with the sort.
 """
 from __future__ import annotations
 
@@ -63,6 +65,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, nargs="+", default=[0.8, 2.0],
                     help="offered loads as fractions of the plain serial throughput")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-sort-ablation", action="store_true",
+                    help="skip the unsorted-points comparison (Sec. 4.1)")
     ap.add_argument("--traffic", default="",
                     help="JSON with measured HBM bytes per launch of the dominant "
                          "kernel ({\"kernel\": ..., \"bytes\": ...}) for roofline.traffic")
@@ -319,6 +323,8 @@ def main():
                                       for t, o in tuned.items()}
     if ntr > 1:
         out["batched_vs_plain"] = batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt)
+    if shared and not args.no_sort_ablation:
+        out["sort_ablation"] = sort_ablation(wl, N, coords, c_in, f_in, outs, cdt, stages)
 
     if args.serve_requests > 0 and args.workload == "3d_clustered":
         out["serving"] = serve_bench(args.serve_requests, args.serve_load, args.serve_slots)
@@ -415,6 +421,43 @@ def bench_type3(args, wl):
         res["parity"] = {"rel_l2": O.rel_l2(out.cpu().numpy()[idx], ref), "bar": 10 * wl.eps}
     p.close()
     print(json.dumps(res))
+
+
+def sort_ablation(wl, N, coords, c_in, f_in, outs, cdt, stages, reps=3):
+    """The bin sort's effect (Sec. 4.1): execute with the points in the caller's
+    order (sort 0: one thread per point, global atomics for type 1, direct
+    gathers for type 2) against the bin-sorted execute of the timed loop, alone
+    and with the sort (setpts) added."""
+    import torch
+    from paper_1808_06736_amd import binding as B
+    res = {}
+    sort_ms = stages["type1"]["setpts_ms"]
+    for t in wl.types:
+        p = B.Plan(t, N, wl.eps, dtype=cdt, sort=0)
+        p.setpts(*coords)
+        out = torch.empty_like(outs[t])   # the timed loop's outputs stay for the parity check
+        if t == 1:
+            def run():
+                p.execute(c_in, out)
+        else:
+            def run():
+                p.execute(out, f_in)
+        run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        e1.synchronize()
+        unsorted = e0.elapsed_time(e1) / reps
+        p.close()
+        srt = stages[f"type{t}"]["execute_ms"]
+        res[f"type{t}"] = {"unsorted_execute_ms": unsorted, "sorted_execute_ms": srt,
+                           "sort_ms": sort_ms, "speedup_execute": unsorted / srt,
+                           "speedup_with_sort": unsorted / (srt + sort_ms)}
+    return res
 
 
 def serve_bench(nreq, loads, nslots, seed=5):
