@@ -252,6 +252,19 @@ void t3_destroy(esn_plan p);
 // other columns are never read, and before the x pass of a type 2 transform
 // they are zero.  Such a plan runs one batched x pass and, per transform and
 // kept run, a 2D (y, z) FFT batched over the run's columns.
+// One pass of column FFTs (kernels_fft.hip): DFTs of length L along a stride
+// of estride elements, for blocks of 32 neighbouring x columns of each of
+// nplanes planes (pstride apart) and each transform (tstride apart).  Column
+// blocks 0 .. chunks_a - 1 come first, then the blocks from chunk_b0 on.
+constexpr int kColWidth = 32;
+struct ColFFTArgs {
+  int64_t estride = 0, pstride = 0, tstride = 0, nplanes = 0;
+  int chunks_a = 0, chunk_b0 = 0;
+  int sign = 1;
+};
+hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
+                           int nchunks, int ntr, hipStream_t s);
+
 struct FFTPlan {
   rocfft_plan plan = nullptr;          // the whole transform, or the x pass
   rocfft_plan yz[2] = {nullptr, nullptr};   // (y, z) FFTs of the kept x runs
@@ -261,6 +274,13 @@ struct FFTPlan {
   int64_t grid = 0;                    // elements per transform
   int elem = 8;                        // bytes per complex element
   int x_first = 1;                     // type 1: x pass first; type 2: last
+  // pruned single-precision transforms with y and z lengths in 32 .. 512: the
+  // kept columns' y and z passes run as column FFTs instead of rocFFT plans
+  int cols = 0;
+  ColFFTArgs cy, cz;
+  int ly = 0, lz = 0, nchunks = 0;
+  double2* d_tw = nullptr;             // twiddles of length ly, then of length lz
+  hipStream_t stream = nullptr;
   rocfft_execution_info info = nullptr;
   void* work = nullptr;
   size_t work_bytes = 0;
@@ -271,6 +291,8 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
              int prec, int sign, hipStream_t s);
 int fft_exec(FFTPlan* p, void* data);
 void fft_destroy(FFTPlan* p);
+// Move an FFT plan's work to another stream.
+int fft_set_stream(FFTPlan* p, hipStream_t s);
 
 // Move a plan (and its rocFFT execution info) to another stream.  The caller
 // makes sure no work of the plan is pending on the old stream.

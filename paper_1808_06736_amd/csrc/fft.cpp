@@ -7,9 +7,13 @@
 // 3D transforms skip the y and z FFTs of the x columns that hold no mode
 // (k1 mod n1 outside I_N1): half the grid or more for sigma = 2.  The result
 // at the kept columns is that of the full 3D FFT, since the y and z FFTs act
-// on each x column by itself.
+// on each x column by itself.  In single precision with y and z lengths of 32
+// to 512 those two passes are the column FFT kernels (kernels_fft.hip), one
+// launch per pass over both kept runs; otherwise rocFFT's strided 2D plans.
 #include <algorithm>
+#include <cmath>
 #include <mutex>
+#include <vector>
 
 #include "esn_internal.hpp"
 
@@ -59,7 +63,54 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
   auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
   const bool prune = dim == 3 && lo + hi < nf[0] && pow2(nf[0]) && pow2(nf[1]) && pow2(nf[2]);
   size_t work = 0;
-  if (prune) {
+  p->stream = s;
+  auto col_len = [](int64_t v) { return v >= 32 && v <= 512; };
+  if (prune && prec == ESN_SINGLE && nf[0] % kColWidth == 0 && col_len(nf[1]) &&
+      col_len(nf[2])) {
+    const size_t lx[1] = {(size_t)nf[0]};
+    p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
+    // column blocks of 32 covering x = 0 .. lo - 1 and x = nf0 - hi .. nf0 - 1;
+    // blocks that would cover a column twice merge into one range
+    const int all = (int)(nf[0] / kColWidth);
+    int ca = (int)((lo + kColWidth - 1) / kColWidth);
+    int cb0 = (int)((nf[0] - hi) / kColWidth);
+    if (hi == 0) cb0 = all;
+    if (cb0 < ca) {
+      ca = all;
+      cb0 = all;
+    }
+    p->nchunks = ca + (all - cb0);
+    p->cols = 1;
+    p->ly = (int)nf[1];
+    p->lz = (int)nf[2];
+    ColFFTArgs a;
+    a.chunks_a = ca;
+    a.chunk_b0 = cb0;
+    a.sign = sign;
+    a.tstride = p->grid;
+    p->cy = a;
+    p->cy.estride = nf[0];
+    p->cy.pstride = nf[0] * nf[1];
+    p->cy.nplanes = nf[2];
+    p->cz = a;
+    p->cz.estride = nf[0] * nf[1];
+    p->cz.pstride = nf[0];
+    p->cz.nplanes = nf[1];
+    std::vector<double2> tw((size_t)(p->ly + p->lz));
+    for (int i = 0; i < p->ly + p->lz; i++) {
+      const int len = i < p->ly ? p->ly : p->lz;
+      const int e = i < p->ly ? i : i - p->ly;
+      const double ang = 2.0 * M_PI * (double)e / (double)len;
+      tw[(size_t)i] = make_double2(std::cos(ang), std::sin(ang));
+    }
+    if (hipMalloc(&p->d_tw, tw.size() * sizeof(double2)) != hipSuccess) {
+      p->d_tw = nullptr;
+      return ESN_ERR_ALLOC;
+    }
+    if (hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return ESN_ERR_HIP;
+  } else if (prune) {
     const size_t lx[1] = {(size_t)nf[0]};
     p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
     const size_t lyz[2] = {(size_t)nf[1], (size_t)nf[2]};
@@ -106,6 +157,17 @@ int fft_exec(FFTPlan* p, void* data) {
     void* in[1] = {ptr};
     return rocfft_execute(q, in, nullptr, p->info) == rocfft_status_success;
   };
+  if (p->cols) {
+    float2* g = static_cast<float2*>(data);
+    if (p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+    if (launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, p->batch, p->stream) !=
+            hipSuccess ||
+        launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, p->batch, p->stream) !=
+            hipSuccess)
+      return ESN_ERR_HIP;
+    if (!p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+    return ESN_OK;
+  }
   if (!p->nyz) return run(p->plan, data) ? ESN_OK : ESN_ERR_FFT_PLAN;
   if (p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
   for (int t = 0; t < p->batch; t++)
@@ -122,7 +184,15 @@ void fft_destroy(FFTPlan* p) {
   for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]})
     if (q) rocfft_plan_destroy(q);
   if (p->work) (void)hipFree(p->work);
+  if (p->d_tw) (void)hipFree(p->d_tw);
   *p = FFTPlan();
+}
+
+int fft_set_stream(FFTPlan* p, hipStream_t s) {
+  p->stream = s;
+  if (p->info && rocfft_execution_info_set_stream(p->info, (void*)s) != rocfft_status_success)
+    return ESN_ERR_FFT_PLAN;
+  return ESN_OK;
 }
 
 }  // namespace esn

@@ -895,14 +895,8 @@ namespace esn {
 int plan_set_stream(esn_plan p, hipStream_t s) {
   if (!p) return ESN_ERR_BAD_ARG;
   p->stream = s;
-  if (p->fft.info && rocfft_execution_info_set_stream(p->fft.info, (void*)s) != rocfft_status_success)
-    return ESN_ERR_FFT_PLAN;
-  if (p->fft_tail.info &&
-      rocfft_execution_info_set_stream(p->fft_tail.info, (void*)s) != rocfft_status_success)
-    return ESN_ERR_FFT_PLAN;
-  for (FFTPlan* f : {&p->fft_adj, &p->fft_adj_tail})
-    if (f->info && rocfft_execution_info_set_stream(f->info, (void*)s) != rocfft_status_success)
-      return ESN_ERR_FFT_PLAN;
+  for (FFTPlan* f : {&p->fft, &p->fft_tail, &p->fft_adj, &p->fft_adj_tail})
+    if (fft_set_stream(f, s) != ESN_OK) return ESN_ERR_FFT_PLAN;
   return ESN_OK;
 }
 

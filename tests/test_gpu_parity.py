@@ -299,3 +299,38 @@ def test_low_upsampling_meets_bar(case, type_):
               f"nf {list(info.nf)[:dim]}, rel l2 {err:.2e}")
         assert all(info.nf[d] < 2 * N[d] for d in range(dim))
         assert err <= 10 * eps
+
+
+COLUMN_FFT_CASES = [
+    # N, sigma, ntransf, fine grid: powers of two with y and z lengths in 32 .. 512
+    ((31, 127, 16), 2.0, 1, (64, 256, 32)),   # odd N1: kept x runs of 16 and 15 columns
+    ((16, 16, 256), 2.0, 1, (32, 32, 512)),   # radix-2 last stage in y (32) and z (512)
+    ((101, 25, 25), 1.25, 1, (128, 32, 32)),  # kept runs reach every block of 32 columns
+    ((31, 127, 16), 2.0, 3, (64, 256, 32)),   # three transforms per launch
+]
+
+
+@pytest.mark.parametrize("case", COLUMN_FFT_CASES,
+                         ids=[f"{c[0]}-s{c[1]:g}-t{c[2]}" for c in COLUMN_FFT_CASES])
+def test_column_fft_grids(case):
+    """3D single-precision plans on power-of-two fine grids run the y and z
+    passes of the FFT as column FFTs over the kept x columns: type 1 and type 2
+    meet the bar against the oracle, for each transform of a batch."""
+    N, sigma, ntr, nf = case
+    eps, M = 1e-5, 3000
+    coords = coord_np(I.uniform_points(M, 3, 901, np.float32), "f32")
+    c = I.complex_normal((ntr, M) if ntr > 1 else M, 902, np.complex64)
+    f = I.complex_normal(((ntr,) if ntr > 1 else ()) + tuple(reversed(N)), 903, np.complex64)
+    opts = {"upsampfac": sigma} if sigma != 2.0 else {}
+    out1, info = run_type1(coords, c, N, eps, "f32", ntransf=ntr, **opts)
+    assert tuple(int(info.nf[m]) for m in range(3)) == nf
+    out2, _ = run_type2(coords, f, N, eps, "f32", ntransf=ntr, **opts)
+    cs = c.reshape(ntr, M)
+    fs = f.reshape((ntr,) + tuple(reversed(N)))
+    o1 = out1.reshape((ntr,) + tuple(reversed(N)))
+    o2 = out2.reshape(ntr, M)
+    for t in range(ntr):
+        e1 = O.rel_l2(o1[t], O.type1(coords, cs[t], +1, N=N))
+        e2 = O.rel_l2(o2[t], O.type2(coords, fs[t], -1))
+        print(f"column FFTs {N} sigma {sigma} transform {t}: type 1 {e1:.2e}, type 2 {e2:.2e}")
+        assert e1 <= 10 * eps and e2 <= 10 * eps
