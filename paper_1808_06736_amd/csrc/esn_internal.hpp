@@ -264,6 +264,8 @@ struct ColFFTArgs {
 };
 hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
                            int nchunks, int ntr, hipStream_t s);
+// Lengths the column FFTs take: 2^a 3^b 5^c with a >= 5, up to 512.
+bool fft_cols_supported(int64_t L);
 
 struct FFTPlan {
   rocfft_plan plan = nullptr;          // the whole transform, or the x pass
@@ -274,8 +276,8 @@ struct FFTPlan {
   int64_t grid = 0;                    // elements per transform
   int elem = 8;                        // bytes per complex element
   int x_first = 1;                     // type 1: x pass first; type 2: last
-  // pruned single-precision transforms with y and z lengths in 32 .. 512: the
-  // kept columns' y and z passes run as column FFTs instead of rocFFT plans
+  // pruned single-precision transforms whose y and z lengths the column FFTs
+  // take: the kept columns' y and z passes run as column FFTs
   int cols = 0;
   ColFFTArgs cy, cz;
   int ly = 0, lz = 0, nchunks = 0;

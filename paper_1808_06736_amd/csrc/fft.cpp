@@ -7,9 +7,11 @@
 // 3D transforms skip the y and z FFTs of the x columns that hold no mode
 // (k1 mod n1 outside I_N1): half the grid or more for sigma = 2.  The result
 // at the kept columns is that of the full 3D FFT, since the y and z FFTs act
-// on each x column by itself.  In single precision with y and z lengths of 32
-// to 512 those two passes are the column FFT kernels (kernels_fft.hip), one
-// launch per pass over both kept runs; otherwise rocFFT's strided 2D plans.
+// on each x column by itself.  In single precision, with y and z lengths
+// 2^a 3^b 5^c (a >= 5) up to 512 and x a multiple of 32, those two passes are
+// the column FFT kernels (kernels_fft.hip), one launch per pass over both kept
+// runs; otherwise, on power-of-two grids, rocFFT's strided 2D plans, and on
+// other grids the full 3D rocFFT plan.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -61,12 +63,14 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
   // (on a 256^3 grid x pass + kept runs take 153 us against 191 us for the full
   // 3D plan; on 288^3 789 us against 487 us), so other sizes take the full plan
   auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
-  const bool prune = dim == 3 && lo + hi < nf[0] && pow2(nf[0]) && pow2(nf[1]) && pow2(nf[2]);
+  const bool cols = dim == 3 && lo + hi < nf[0] && prec == ESN_SINGLE &&
+                    nf[0] % kColWidth == 0 && fft_cols_supported(nf[1]) &&
+                    fft_cols_supported(nf[2]) && p->grid < ((int64_t)1 << 28);
+  const bool prune =
+      cols || (dim == 3 && lo + hi < nf[0] && pow2(nf[0]) && pow2(nf[1]) && pow2(nf[2]));
   size_t work = 0;
   p->stream = s;
-  auto col_len = [](int64_t v) { return v >= 32 && v <= 512; };
-  if (prune && prec == ESN_SINGLE && nf[0] % kColWidth == 0 && col_len(nf[1]) &&
-      col_len(nf[2])) {
+  if (cols) {
     const size_t lx[1] = {(size_t)nf[0]};
     p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
     // column blocks of 32 covering x = 0 .. lo - 1 and x = nf0 - hi .. nf0 - 1;

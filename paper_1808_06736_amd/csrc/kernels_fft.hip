@@ -9,11 +9,12 @@
 // * Reads and writes move 32 consecutive complex values (256 bytes) per grid
 //   row, so every access is coalesced whatever the stride between the DFT's
 //   points.
-// * Self-sorting (Stockham) radix-4 stages with a final radix-2 stage when
-//   log2 L is odd.  The first stage reads the grid, the last writes it; the
-//   stages in between exchange through one LDS array of L x 32 values (each
-//   thread holds all inputs of its butterflies before the barrier that
-//   precedes the writes).
+// * Self-sorting (Stockham) mixed-radix stages: radix 4 while it divides, one
+//   radix 2 for an odd power of two, then radix 3 and radix 5 (lengths
+//   L = 2^a 3^b 5^c with a >= 5, up to 512).  The first stage reads the grid,
+//   the last writes it; the stages in between exchange through one LDS array
+//   of L x 32 values (each thread holds all inputs of its butterflies before
+//   the barrier that precedes the writes).
 // * Twiddle factors exp(2 pi i e / L) come from a table computed in FP64 on the
 //   host, staged in LDS.
 #include "device_common.hpp"
@@ -28,7 +29,49 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Radix-4 butterfly in place: v[r] = sum_m v[m] (sgn i)^(m r).
+__device__ __forceinline__ float2 caddf(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csubf(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a (sgn i)
+__device__ __forceinline__ float2 crotf(float2 a, float sgn) {
+  return make_float2(-sgn * a.y, sgn * a.x);
+}
+
+// Radix-R butterflies in place: v[r] = sum_m v[m] exp(sgn 2 pi i m r / R).
+__device__ __forceinline__ void bfly2(float2* v) {
+  const float2 a = v[0];
+  v[0] = caddf(a, v[1]);
+  v[1] = csubf(a, v[1]);
+}
+
+__device__ __forceinline__ void bfly3(float2* v, float sgn) {
+  constexpr float kS3 = 0.86602540378443864676f;   // sin(2 pi / 3)
+  const float2 t1 = caddf(v[1], v[2]);
+  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  const float2 d = csubf(v[1], v[2]);
+  const float2 t3 = crotf(make_float2(kS3 * d.x, kS3 * d.y), sgn);
+  v[0] = caddf(v[0], t1);
+  v[1] = caddf(t2, t3);
+  v[2] = csubf(t2, t3);
+}
+
+__device__ __forceinline__ void bfly5(float2* v, float sgn) {
+  constexpr float c1 = 0.30901699437494742410f;    // cos(2 pi / 5)
+  constexpr float c2 = -0.80901699437494742410f;   // cos(4 pi / 5)
+  constexpr float s1 = 0.95105651629515357212f;    // sin(2 pi / 5)
+  constexpr float s2 = 0.58778525229247312917f;    // sin(4 pi / 5)
+  const float2 t1 = caddf(v[1], v[4]), t2 = caddf(v[2], v[3]);
+  const float2 t3 = csubf(v[1], v[4]), t4 = csubf(v[2], v[3]);
+  const float2 b1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+  const float2 b2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+  const float2 d1 = crotf(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), sgn);
+  const float2 d2 = crotf(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), sgn);
+  v[0] = caddf(v[0], caddf(t1, t2));
+  v[1] = caddf(b1, d1);
+  v[4] = csubf(b1, d1);
+  v[2] = caddf(b2, d2);
+  v[3] = csubf(b2, d2);
+}
+
 __device__ __forceinline__ void bfly4(float2* v, float sgn) {
   const float2 t0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
   const float2 t1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
@@ -54,73 +97,63 @@ struct ColPtr {
   }
 };
 
-// Stages from sub-transform length LS on.  A radix-4 stage combines, for
-// j = q LS + k (k < LS), the points q LS + k + m L/4 (m = 0..3), twiddled by
-// w^(k m L / (4 LS)), into q 4 LS + k + r LS (r = 0..3); w = exp(sgn 2 pi i / L).
-// Thread (c, g) takes j = g + 8 b; for LS >= 8, k = g + (8 b mod LS) and
-// q = 8 b / LS, so the grid points of the first and last stages are g plus a
-// uniform part.
-template <int L, int LS>
+// Stages from sub-transform length LS on, radices R, Rest... .  A radix-R
+// stage combines, for j = q LS + k (k < LS), the points q LS + k + m L/R
+// (m < R), twiddled by w^(k m L / (R LS)), into q R LS + k + r LS (r < R);
+// w = exp(sgn 2 pi i / L).  Thread (c, g) takes j = g + 8 b; where LS is a
+// multiple of 8, k = g + (8 b mod LS) and q = 8 b / LS, so the grid points of
+// the first and the last stage are g plus a uniform part.
+template <int L, int LS, int R, int... Rest>
 __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2* __restrict__ tw,
                                            float sgn, const ColPtr& gp, int c, int g) {
-  if constexpr (4 * LS <= L) {
-    constexpr bool first = LS == 1;
-    constexpr bool last = 4 * LS == L;
-    static_assert(!last || LS >= kColGroups, "last radix-4 stage from LS >= 8");
-    constexpr int B = L / 4 / kColGroups;   // butterflies per thread
-    float2 v[B][4];
+  constexpr bool first = LS == 1;
+  constexpr bool last = sizeof...(Rest) == 0;
+  static_assert((L / R) % kColGroups == 0, "butterflies split evenly over the groups");
+  static_assert(!last || (LS % kColGroups == 0 && LS * R == L), "last stage");
+  constexpr int B = L / R / kColGroups;   // butterflies per thread
+  float2 v[B][R];
 #pragma unroll
-    for (int b = 0; b < B; b++) {
-      const int j = g + kColGroups * b, k = j % LS, q = j / LS;
+  for (int b = 0; b < B; b++) {
+    const int j = g + kColGroups * b, k = j % LS, q = j / LS;
 #pragma unroll
-      for (int m = 0; m < 4; m++) {
-        if constexpr (first)
-          v[b][m] = gp.at(kColGroups * b + m * (L / 4));
-        else
-          v[b][m] = s[(q * LS + k + m * (L / 4)) * kColW + c];
-      }
-      if constexpr (!first) {
-#pragma unroll
-        for (int m = 1; m < 4; m++) v[b][m] = cmulf(v[b][m], tw[k * m * (L / (4 * LS))]);
-      }
-      bfly4(v[b], sgn);
+    for (int m = 0; m < R; m++) {
+      if constexpr (first)
+        v[b][m] = gp.at(kColGroups * b + m * (L / R));
+      else
+        v[b][m] = s[(q * LS + k + m * (L / R)) * kColW + c];
     }
-    if constexpr (!first) __syncthreads();   // every read of s is done
+    if constexpr (!first) {
 #pragma unroll
-    for (int b = 0; b < B; b++) {
-      const int j = g + kColGroups * b, k = j % LS, q = j / LS;
+      for (int m = 1; m < R; m++) v[b][m] = cmulf(v[b][m], tw[k * m * (L / (R * LS))]);
+    }
+    if constexpr (R == 2) bfly2(v[b]);
+    else if constexpr (R == 3) bfly3(v[b], sgn);
+    else if constexpr (R == 4) bfly4(v[b], sgn);
+    else bfly5(v[b], sgn);
+  }
+  if constexpr (!first) __syncthreads();   // every read of s is done
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        if constexpr (last)
-          gp.at((kColGroups * b / LS) * 4 * LS + (kColGroups * b) % LS + r * LS) = v[b][r];
-        else
-          s[(q * 4 * LS + k + r * LS) * kColW + c] = v[b][r];
-      }
-    }
-    if constexpr (!last) {
-      __syncthreads();
-      col_stages<L, 4 * LS>(s, tw, sgn, gp, c, g);
-    }
-  } else {
-    // radix 2, LS = L / 2: points k and k + L/2, twiddle w^k
-    static_assert(2 * LS == L, "stage lengths");
-    constexpr int B = L / 2 / kColGroups;
+  for (int b = 0; b < B; b++) {
+    const int j = g + kColGroups * b, k = j % LS, q = j / LS;
 #pragma unroll
-    for (int b = 0; b < B; b++) {
-      const int k = g + kColGroups * b;
-      const float2 a0 = s[k * kColW + c];
-      const float2 a1 = cmulf(s[(k + L / 2) * kColW + c], tw[k]);
-      gp.at(kColGroups * b) = make_float2(a0.x + a1.x, a0.y + a1.y);
-      gp.at(kColGroups * b + LS) = make_float2(a0.x - a1.x, a0.y - a1.y);
+    for (int r = 0; r < R; r++) {
+      if constexpr (last)
+        gp.at((kColGroups * b / LS) * R * LS + (kColGroups * b) % LS + r * LS) = v[b][r];
+      else
+        s[(q * R * LS + k + r * LS) * kColW + c] = v[b][r];
     }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+    col_stages<L, LS * R, Rest...>(s, tw, sgn, gp, c, g);
   }
 }
 
-template <int L>
+template <int L, int... Rs>
 __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restrict__ data,
                                                                const ColFFTArgs a,
                                                                const double2* __restrict__ twd) {
-  static_assert(L >= 32 && (L & (L - 1)) == 0, "power-of-two lengths from 32");
+  static_assert(L >= 32 && L <= 512, "lengths 32 .. 512");
   __shared__ float2 s[L * kColW];
   __shared__ float2 tw[L];
   const int c = threadIdx.x % kColW, g = threadIdx.x / kColW;
@@ -136,24 +169,47 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   for (int64_t pl = blockIdx.y; pl < a.nplanes; pl += gridDim.y) {
     if (pl != (int64_t)blockIdx.y) __syncthreads();   // the last plane's reads of s are done
     gp.base = reinterpret_cast<char*>(gt + pl * a.pstride);
-    col_stages<L, 1>(s, tw, sgn, gp, c, g);
+    col_stages<L, 1, Rs...>(s, tw, sgn, gp, c, g);
   }
 }
+
+bool fft_cols_supported(int64_t L) {
+  switch (L) {
+    case 32: case 64: case 96: case 128: case 160: case 192:
+    case 256: case 288: case 320: case 384: case 480: case 512: return true;
+    default: return false;
+  }
+}
+
+#define ESN_COLS(LEN, ...)                                                                     \
+  case LEN:                                                                                    \
+    hipLaunchKernelGGL((fft_cols_kernel<LEN, __VA_ARGS__>), grid, block, 0, s, data, a, tw); \
+    break;
 
 hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
                            int nchunks, int ntr, hipStream_t s) {
   const dim3 grid((unsigned)nchunks, (unsigned)std::min<int64_t>(a.nplanes, 65535),
                   (unsigned)ntr);
   const dim3 block(kColThreads);
+  // radix 4 while it divides, one radix 2 for an odd power of two, then 3s and 5s
   switch (L) {
-    case 32: hipLaunchKernelGGL(fft_cols_kernel<32>, grid, block, 0, s, data, a, tw); break;
-    case 64: hipLaunchKernelGGL(fft_cols_kernel<64>, grid, block, 0, s, data, a, tw); break;
-    case 128: hipLaunchKernelGGL(fft_cols_kernel<128>, grid, block, 0, s, data, a, tw); break;
-    case 256: hipLaunchKernelGGL(fft_cols_kernel<256>, grid, block, 0, s, data, a, tw); break;
-    case 512: hipLaunchKernelGGL(fft_cols_kernel<512>, grid, block, 0, s, data, a, tw); break;
+    ESN_COLS(32, 4, 4, 2)
+    ESN_COLS(64, 4, 4, 4)
+    ESN_COLS(96, 4, 4, 2, 3)
+    ESN_COLS(128, 4, 4, 4, 2)
+    ESN_COLS(160, 4, 4, 2, 5)
+    ESN_COLS(192, 4, 4, 4, 3)
+    ESN_COLS(256, 4, 4, 4, 4)
+    ESN_COLS(288, 4, 4, 2, 3, 3)
+    ESN_COLS(320, 4, 4, 4, 5)
+    ESN_COLS(384, 4, 4, 4, 2, 3)
+    ESN_COLS(480, 4, 4, 2, 3, 5)
+    ESN_COLS(512, 4, 4, 4, 4, 2)
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
+
+#undef ESN_COLS
 
 }  // namespace esn

@@ -302,11 +302,14 @@ def test_low_upsampling_meets_bar(case, type_):
 
 
 COLUMN_FFT_CASES = [
-    # N, sigma, ntransf, fine grid: powers of two with y and z lengths in 32 .. 512
+    # N, sigma, ntransf, fine grid: y and z lengths 2^a 3^b 5^c (a >= 5) up to
+    # 512, x a multiple of 32
     ((31, 127, 16), 2.0, 1, (64, 256, 32)),   # odd N1: kept x runs of 16 and 15 columns
     ((16, 16, 256), 2.0, 1, (32, 32, 512)),   # radix-2 last stage in y (32) and z (512)
     ((101, 25, 25), 1.25, 1, (128, 32, 32)),  # kept runs reach every block of 32 columns
     ((31, 127, 16), 2.0, 3, (64, 256, 32)),   # three transforms per launch
+    ((47, 143, 79), 2.0, 1, (96, 288, 160)),  # radix 3 and 5 stages, odd N
+    ((192, 240, 48), 2.0, 1, (384, 480, 96)),  # radix 3 then 5 in one transform
 ]
 
 
