@@ -255,10 +255,12 @@ void t3_destroy(esn_plan p);
 // One pass of column FFTs (kernels_fft.hip): DFTs of length L along a stride
 // of estride elements, for blocks of 32 neighbouring x columns of each of
 // nplanes planes (pstride apart) and each transform (tstride apart).  Column
-// blocks 0 .. chunks_a - 1 come first, then the blocks from chunk_b0 on.
+// blocks 0 .. chunks_a - 1 come first, then the blocks from chunk_b0 on;
+// likewise planes 0 .. planes_a - 1, then the planes from plane_b0 on.
 constexpr int kColWidth = 32;
 struct ColFFTArgs {
   int64_t estride = 0, pstride = 0, tstride = 0, nplanes = 0;
+  int64_t planes_a = 0, plane_b0 = 0;
   int chunks_a = 0, chunk_b0 = 0;
   int sign = 1;
 };

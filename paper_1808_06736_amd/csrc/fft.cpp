@@ -92,14 +92,27 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     a.chunk_b0 = cb0;
     a.sign = sign;
     a.tstride = p->grid;
+    // the y pass runs on every z plane; the z pass only on the y rows that
+    // hold modes (k2 mod n2 in I_N2): type 1 runs it last, and only those rows
+    // are read afterwards; type 2 runs it first, on the amplified grid whose
+    // other rows are zero, so their z transforms are zero as well
     p->cy = a;
     p->cy.estride = nf[0];
     p->cy.pstride = nf[0] * nf[1];
     p->cy.nplanes = nf[2];
+    p->cy.planes_a = nf[2];
+    p->cy.plane_b0 = nf[2];
     p->cz = a;
     p->cz.estride = nf[0] * nf[1];
     p->cz.pstride = nf[0];
-    p->cz.nplanes = nf[1];
+    const int64_t ylo = (nmodes[1] + 1) / 2, yhi = nmodes[1] / 2;
+    if (ylo + yhi < nf[1]) {
+      p->cz.planes_a = ylo;
+      p->cz.plane_b0 = nf[1] - yhi;
+      p->cz.nplanes = ylo + yhi;
+    } else {
+      p->cz.planes_a = p->cz.plane_b0 = p->cz.nplanes = nf[1];
+    }
     std::vector<double2> tw((size_t)(p->ly + p->lz));
     for (int i = 0; i < p->ly + p->lz; i++) {
       const int len = i < p->ly ? p->ly : p->lz;
@@ -163,13 +176,19 @@ int fft_exec(FFTPlan* p, void* data) {
   };
   if (p->cols) {
     float2* g = static_cast<float2*>(data);
-    if (p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
-    if (launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, p->batch, p->stream) !=
-            hipSuccess ||
-        launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, p->batch, p->stream) !=
-            hipSuccess)
-      return ESN_ERR_HIP;
-    if (!p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+    auto ypass = [&] {
+      return launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, p->batch, p->stream);
+    };
+    auto zpass = [&] {
+      return launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, p->batch, p->stream);
+    };
+    if (p->x_first) {   // type 1: x, y, z (kept y rows)
+      if (!run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+      if (ypass() != hipSuccess || zpass() != hipSuccess) return ESN_ERR_HIP;
+    } else {            // type 2: z (kept y rows), y, x
+      if (zpass() != hipSuccess || ypass() != hipSuccess) return ESN_ERR_HIP;
+      if (!run(p->plan, data)) return ESN_ERR_FFT_PLAN;
+    }
     return ESN_OK;
   }
   if (!p->nyz) return run(p->plan, data) ? ESN_OK : ESN_ERR_FFT_PLAN;

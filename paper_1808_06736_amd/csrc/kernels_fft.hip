@@ -166,8 +166,9 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   ColPtr gp;
   gp.es8 = a.estride * (int64_t)sizeof(float2);
   gp.loff = (uint32_t)((c + (int64_t)g * a.estride) * (int64_t)sizeof(float2));
-  for (int64_t pl = blockIdx.y; pl < a.nplanes; pl += gridDim.y) {
-    if (pl != (int64_t)blockIdx.y) __syncthreads();   // the last plane's reads of s are done
+  for (int64_t i = blockIdx.y; i < a.nplanes; i += gridDim.y) {
+    if (i != (int64_t)blockIdx.y) __syncthreads();   // the last plane's reads of s are done
+    const int64_t pl = i < a.planes_a ? i : a.plane_b0 + (i - a.planes_a);
     gp.base = reinterpret_cast<char*>(gt + pl * a.pstride);
     col_stages<L, 1, Rs...>(s, tw, sgn, gp, c, g);
   }
