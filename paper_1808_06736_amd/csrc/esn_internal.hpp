@@ -261,11 +261,29 @@ constexpr int kColWidth = 32;
 struct ColFFTArgs {
   int64_t estride = 0, pstride = 0, tstride = 0, nplanes = 0;
   int64_t planes_a = 0, plane_b0 = 0;
+  // kept points of a DFT (masked or mode-array ends): j < keep_lo or
+  // j >= L - keep_hi
+  int64_t keep_lo = 0, keep_hi = 0;
   int chunks_a = 0, chunk_b0 = 0;
   int sign = 1;
 };
+// Mode arrays and correction factors of a z pass that reads p_k f_k (type 2)
+// or writes f_k = p_k b^_k (type 1) itself.
+struct ColModes {
+  float2* f = nullptr;                  // transform t at f + t fstride
+  int64_t fstride = 0;
+  int64_t N[3] = {1, 1, 1};             // modes per dim
+  int64_t n0 = 0, n1 = 0;               // fine-grid x and y lengths
+  const double* pf[3] = {nullptr, nullptr, nullptr};   // p_k per dim
+  int modeord = 0;
+};
+// in_mode / out_mode: 0 the grid, 1 the grid at the kept points only, 2 the
+// mode arrays (z pass).
 hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
-                           int nchunks, int ntr, hipStream_t s);
+                           int nchunks, int ntr, int in_mode, int out_mode, const ColModes& cm,
+                           hipStream_t s);
+hipError_t launch_zero_cols(float2* data, int64_t n0, int64_t rows, int64_t x0, int64_t x1,
+                            int ntr, int64_t tstride, hipStream_t s);
 // Lengths the column FFTs take: 2^a 3^b 5^c with a >= 5, up to 512.
 bool fft_cols_supported(int64_t L);
 
@@ -281,7 +299,10 @@ struct FFTPlan {
   // pruned single-precision transforms whose y and z lengths the column FFTs
   // take: the kept columns' y and z passes run as column FFTs
   int cols = 0;
+  int modes = 0;                       // the correction folds into the z pass
   ColFFTArgs cy, cz;
+  ColFFTArgs cy_keep, cz_keep;         // the same, keeping the points that hold modes
+  int64_t nx = 0;                      // x length
   int ly = 0, lz = 0, nchunks = 0;
   double2* d_tw = nullptr;             // twiddles of length ly, then of length lz
   hipStream_t stream = nullptr;
@@ -294,6 +315,11 @@ struct FFTPlan {
 int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int type, int batch,
              int prec, int sign, hipStream_t s);
 int fft_exec(FFTPlan* p, void* data);
+// With the correction folded into the column passes (p->cols): type 1
+// (x_first) transforms the spread grid and writes f = p_k b^_k for the modes;
+// type 2 reads the modes f with their factors p_k and leaves the transformed
+// grid (no amplification before it).  Layout of f as for deconv / amplify.
+int fft_exec_modes(FFTPlan* p, void* grid, void* f, const ColModes& cm);
 void fft_destroy(FFTPlan* p);
 // Move an FFT plan's work to another stream.
 int fft_set_stream(FFTPlan* p, hipStream_t s);

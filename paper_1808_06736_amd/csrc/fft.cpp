@@ -85,6 +85,7 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     }
     p->nchunks = ca + (all - cb0);
     p->cols = 1;
+    p->modes = 1;
     p->ly = (int)nf[1];
     p->lz = (int)nf[2];
     ColFFTArgs a;
@@ -113,6 +114,16 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     } else {
       p->cz.planes_a = p->cz.plane_b0 = p->cz.nplanes = nf[1];
     }
+    // with the correction in the passes: the y pass keeps the y points that
+    // hold modes, the z pass the z points
+    p->nx = nf[0];
+    p->cy_keep = p->cy;
+    p->cy_keep.keep_lo = ylo;
+    p->cy_keep.keep_hi = ylo + yhi < nf[1] ? yhi : nf[1] - ylo;
+    p->cz_keep = p->cz;
+    const int64_t zlo = (nmodes[2] + 1) / 2, zhi = nmodes[2] / 2;
+    p->cz_keep.keep_lo = zlo;
+    p->cz_keep.keep_hi = zlo + zhi < nf[2] ? zhi : nf[2] - zlo;
     std::vector<double2> tw((size_t)(p->ly + p->lz));
     for (int i = 0; i < p->ly + p->lz; i++) {
       const int len = i < p->ly ? p->ly : p->lz;
@@ -176,11 +187,14 @@ int fft_exec(FFTPlan* p, void* data) {
   };
   if (p->cols) {
     float2* g = static_cast<float2*>(data);
+    const ColModes none;
     auto ypass = [&] {
-      return launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, p->batch, p->stream);
+      return launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, p->batch, 0, 0, none,
+                             p->stream);
     };
     auto zpass = [&] {
-      return launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, p->batch, p->stream);
+      return launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, p->batch, 0, 0, none,
+                             p->stream);
     };
     if (p->x_first) {   // type 1: x, y, z (kept y rows)
       if (!run(p->plan, data)) return ESN_ERR_FFT_PLAN;
@@ -200,6 +214,41 @@ int fft_exec(FFTPlan* p, void* data) {
     }
   if (!p->x_first && !run(p->plan, data)) return ESN_ERR_FFT_PLAN;
   return ESN_OK;
+}
+
+int fft_exec_modes(FFTPlan* p, void* grid, void* f, const ColModes& cm) {
+  if (!p->modes) return ESN_ERR_BAD_ARG;
+  float2* g = static_cast<float2*>(grid);
+  ColModes m = cm;
+  m.f = static_cast<float2*>(f);
+  const ColModes none;
+  auto xpass = [&] {
+    void* in[1] = {grid};
+    return rocfft_execute(p->plan, in, nullptr, p->info) == rocfft_status_success;
+  };
+  if (p->x_first) {
+    // type 1: x; y, storing the y rows that hold modes only (the z pass reads
+    // no other); z on those rows, writing the modes with their factors
+    if (!xpass()) return ESN_ERR_FFT_PLAN;
+    if (launch_fft_cols(g, p->ly, p->cy_keep, p->d_tw, p->nchunks, p->batch, 0, 1, none,
+                        p->stream) != hipSuccess ||
+        launch_fft_cols(g, p->lz, p->cz_keep, p->d_tw + p->ly, p->nchunks, p->batch, 0, 2, m,
+                        p->stream) != hipSuccess)
+      return ESN_ERR_HIP;
+    return ESN_OK;
+  }
+  // type 2: clear the x columns outside the column blocks (read by the x
+  // pass); z on the y rows that hold modes, reading p_k f_k; y, reading those
+  // rows only (the others are zero); x
+  const int64_t x0 = (int64_t)p->cy.chunks_a * kColWidth, x1 = (int64_t)p->cy.chunk_b0 * kColWidth;
+  if (launch_zero_cols(g, p->nx, p->grid / p->nx, x0, x1, p->batch, p->grid, p->stream) !=
+          hipSuccess ||
+      launch_fft_cols(g, p->lz, p->cz_keep, p->d_tw + p->ly, p->nchunks, p->batch, 2, 0, m,
+                      p->stream) != hipSuccess ||
+      launch_fft_cols(g, p->ly, p->cy_keep, p->d_tw, p->nchunks, p->batch, 1, 0, none,
+                      p->stream) != hipSuccess)
+    return ESN_ERR_HIP;
+  return xpass() ? ESN_OK : ESN_ERR_FFT_PLAN;
 }
 
 void fft_destroy(FFTPlan* p) {

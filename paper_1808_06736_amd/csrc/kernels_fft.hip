@@ -97,15 +97,69 @@ struct ColPtr {
   }
 };
 
+// What the first stage reads and the last stage writes (in / out modes):
+//   kColPlain  the grid;
+//   kColMasked the grid, but only the kept points j < keep_lo or
+//              j >= L - keep_hi (the others read as zero, or are not stored);
+//   kColModes  (z pass) the mode array with the correction factors: type 2
+//              reads p_k f_k at the kept points (zero elsewhere, eq. (pb1)
+//              read backwards), type 1 writes f_k = p_k b^_k (eq. (pb1)).
+constexpr int kColPlain = 0, kColMasked = 1, kColModes = 2;
+
+// Thread's view of the mode array for one column (x = chunk 32 + c, y = the
+// plane) of the z pass.  The z points' offsets in the mode array and their
+// factors p_kz come from a per-block LDS table (zoff < 0: no mode).
+struct ColIO {
+  ColPtr gp;
+  int64_t keep_lo, keep_hi;
+  // modes
+  float2* f;                // this transform's mode array
+  int fxy;                  // position of (kx, ky) in it
+  float pxy;                // p_kx p_ky (0 where (x, y) holds no mode)
+  const int* zoff;          // [L] N1 N2 .. position of kz, or -1
+  const float* zfac;        // [L] p_kz
+  bool col_ok;              // (x, y) holds modes
+  __device__ __forceinline__ bool kept(int j, int L) const {
+    return j < keep_lo || j >= L - keep_hi;
+  }
+  template <int IN, int L>
+  __device__ __forceinline__ float2 load(int g, int u) const {
+    if constexpr (IN == kColPlain) return gp.at(u);
+    const int j = g + u;
+    if constexpr (IN == kColMasked) return kept(j, L) ? gp.at(u) : make_float2(0.f, 0.f);
+    const int zo = zoff[j];
+    if (!col_ok || zo < 0) return make_float2(0.f, 0.f);
+    const float p = pxy * zfac[j];
+    const float2 v = f[fxy + zo];
+    return make_float2(v.x * p, v.y * p);
+  }
+  template <int OUT, int L>
+  __device__ __forceinline__ void store(int g, int u, float2 v) const {
+    if constexpr (OUT == kColPlain) {
+      gp.at(u) = v;
+      return;
+    }
+    const int j = g + u;
+    if constexpr (OUT == kColMasked) {
+      if (kept(j, L)) gp.at(u) = v;
+      return;
+    }
+    const int zo = zoff[j];
+    if (!col_ok || zo < 0) return;
+    const float p = pxy * zfac[j];
+    f[fxy + zo] = make_float2(v.x * p, v.y * p);
+  }
+};
+
 // Stages from sub-transform length LS on, radices R, Rest... .  A radix-R
 // stage combines, for j = q LS + k (k < LS), the points q LS + k + m L/R
 // (m < R), twiddled by w^(k m L / (R LS)), into q R LS + k + r LS (r < R);
 // w = exp(sgn 2 pi i / L).  Thread (c, g) takes j = g + 8 b; where LS is a
 // multiple of 8, k = g + (8 b mod LS) and q = 8 b / LS, so the grid points of
 // the first and the last stage are g plus a uniform part.
-template <int L, int LS, int R, int... Rest>
+template <int L, int IN, int OUT, int LS, int R, int... Rest>
 __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2* __restrict__ tw,
-                                           float sgn, const ColPtr& gp, int c, int g) {
+                                           float sgn, const ColIO& io, int c, int g) {
   constexpr bool first = LS == 1;
   constexpr bool last = sizeof...(Rest) == 0;
   static_assert((L / R) % kColGroups == 0, "butterflies split evenly over the groups");
@@ -118,7 +172,7 @@ __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2*
 #pragma unroll
     for (int m = 0; m < R; m++) {
       if constexpr (first)
-        v[b][m] = gp.at(kColGroups * b + m * (L / R));
+        v[b][m] = io.load<IN, L>(g, kColGroups * b + m * (L / R));
       else
         v[b][m] = s[(q * LS + k + m * (L / R)) * kColW + c];
     }
@@ -138,21 +192,23 @@ __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2*
 #pragma unroll
     for (int r = 0; r < R; r++) {
       if constexpr (last)
-        gp.at((kColGroups * b / LS) * R * LS + (kColGroups * b) % LS + r * LS) = v[b][r];
+        io.store<OUT, L>(g, (kColGroups * b / LS) * R * LS + (kColGroups * b) % LS + r * LS,
+                         v[b][r]);
       else
         s[(q * R * LS + k + r * LS) * kColW + c] = v[b][r];
     }
   }
   if constexpr (!last) {
     __syncthreads();
-    col_stages<L, LS * R, Rest...>(s, tw, sgn, gp, c, g);
+    col_stages<L, IN, OUT, LS * R, Rest...>(s, tw, sgn, io, c, g);
   }
 }
 
-template <int L, int... Rs>
+template <int L, int IN, int OUT, int... Rs>
 __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restrict__ data,
                                                                const ColFFTArgs a,
-                                                               const double2* __restrict__ twd) {
+                                                               const double2* __restrict__ twd,
+                                                               const ColModes cm) {
   static_assert(L >= 32 && L <= 512, "lengths 32 .. 512");
   __shared__ float2 s[L * kColW];
   __shared__ float2 tw[L];
@@ -163,15 +219,84 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   const int chunk = (int)blockIdx.x < a.chunks_a ? (int)blockIdx.x
                                                   : a.chunk_b0 + ((int)blockIdx.x - a.chunks_a);
   float2* gt = data + (int64_t)blockIdx.z * a.tstride + (int64_t)chunk * kColW;
-  ColPtr gp;
-  gp.es8 = a.estride * (int64_t)sizeof(float2);
-  gp.loff = (uint32_t)((c + (int64_t)g * a.estride) * (int64_t)sizeof(float2));
+  ColIO io;
+  io.gp.es8 = a.estride * (int64_t)sizeof(float2);
+  io.gp.loff = (uint32_t)((c + (int64_t)g * a.estride) * (int64_t)sizeof(float2));
+  io.keep_lo = a.keep_lo;
+  io.keep_hi = a.keep_hi;
+  io.f = nullptr;
+  io.fxy = 0;
+  io.pxy = 0.f;
+  io.zoff = nullptr;
+  io.zfac = nullptr;
+  io.col_ok = false;
+  int64_t kx = 0;
+  bool x_ok = false;
+  constexpr bool modes = IN == kColModes || OUT == kColModes;
+  __shared__ int zoff[modes ? L : 1];
+  __shared__ float zfac[modes ? L : 1];
+  if constexpr (modes) {
+    const int64_t x = (int64_t)chunk * kColW + c;
+    const int64_t N0 = cm.N[0], N2 = cm.N[2];
+    x_ok = x < N0 - N0 / 2 || x >= cm.n0 - N0 / 2;
+    kx = x < N0 - N0 / 2 ? x : x - cm.n0;
+    io.f = cm.f + (int64_t)blockIdx.z * cm.fstride;
+    // z point j holds mode kz = j (j < ceil(N3/2)) or j - L (j >= L - floor(N3/2))
+    for (int j = threadIdx.x; j < L; j += kColThreads) {
+      const bool ok = j < N2 - N2 / 2 || j >= L - N2 / 2;
+      const int64_t k = j < N2 - N2 / 2 ? j : (int64_t)j - L;
+      const int64_t pos = cm.modeord == 0 ? k + N2 / 2 : (k >= 0 ? k : k + N2);
+      zoff[j] = ok ? (int)(pos * cm.N[0] * cm.N[1]) : -1;
+      zfac[j] = ok ? (float)cm.pf[2][k < 0 ? -k : k] : 0.f;
+    }
+    io.zoff = zoff;
+    io.zfac = zfac;
+    __syncthreads();
+  }
   for (int64_t i = blockIdx.y; i < a.nplanes; i += gridDim.y) {
     if (i != (int64_t)blockIdx.y) __syncthreads();   // the last plane's reads of s are done
     const int64_t pl = i < a.planes_a ? i : a.plane_b0 + (i - a.planes_a);
-    gp.base = reinterpret_cast<char*>(gt + pl * a.pstride);
-    col_stages<L, 1, Rs...>(s, tw, sgn, gp, c, g);
+    io.gp.base = reinterpret_cast<char*>(gt + pl * a.pstride);
+    if constexpr (modes) {
+      // the plane is a y row that holds modes (the z pass runs on those only)
+      const int64_t N0 = cm.N[0], N1 = cm.N[1];
+      const int64_t ky = pl < N1 - N1 / 2 ? pl : pl - cm.n1;
+      const bool y_ok = pl < N1 - N1 / 2 || pl >= cm.n1 - N1 / 2;
+      io.col_ok = x_ok && y_ok;
+      const int64_t px = cm.modeord == 0 ? kx + N0 / 2 : (kx >= 0 ? kx : kx + N0);
+      const int64_t py = cm.modeord == 0 ? ky + N1 / 2 : (ky >= 0 ? ky : ky + N1);
+      io.fxy = (int)(px + N0 * py);
+      io.pxy = io.col_ok
+                   ? (float)(cm.pf[0][kx < 0 ? -kx : kx] * cm.pf[1][ky < 0 ? -ky : ky])
+                   : 0.f;
+    }
+    col_stages<L, IN, OUT, 1, Rs...>(s, tw, sgn, io, c, g);
   }
+}
+
+// Zero the x columns x0 .. x1 - 1 (even, x1 > x0) of every row: the columns
+// that no column pass writes but the x pass reads.
+__global__ void zero_cols_kernel(float2* __restrict__ data, int64_t n0, int64_t rows, int64_t x0,
+                                 int64_t x1, int64_t tstride) {
+  float4* base = reinterpret_cast<float4*>(data + (int64_t)blockIdx.z * tstride);
+  const int64_t npair = (x1 - x0) / 2;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npair;
+         i += (int64_t)gridDim.x * blockDim.x)
+      base[(r * n0 + x0) / 2 + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+hipError_t launch_zero_cols(float2* data, int64_t n0, int64_t rows, int64_t x0, int64_t x1,
+                            int ntr, int64_t tstride, hipStream_t s) {
+  if (x1 <= x0) return hipSuccess;
+  const int64_t npair = (x1 - x0) / 2;
+  const int bs = npair >= 256 ? 256 : 64 * (int)((npair + 63) / 64);
+  const int64_t gx = std::min<int64_t>((npair + bs - 1) / bs, 65535);
+  const int64_t gy = std::min<int64_t>(rows, std::max<int64_t>(1, 16384 / gx));
+  hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)gx, (unsigned)std::min<int64_t>(gy, 65535),
+                                           (unsigned)ntr),
+                     dim3(bs), 0, s, data, n0, rows, x0, x1, tstride);
+  return hipGetLastError();
 }
 
 bool fft_cols_supported(int64_t L) {
@@ -182,16 +307,15 @@ bool fft_cols_supported(int64_t L) {
   }
 }
 
-#define ESN_COLS(LEN, ...)                                                                     \
-  case LEN:                                                                                    \
-    hipLaunchKernelGGL((fft_cols_kernel<LEN, __VA_ARGS__>), grid, block, 0, s, data, a, tw); \
-    break;
-
-hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
-                           int nchunks, int ntr, hipStream_t s) {
-  const dim3 grid((unsigned)nchunks, (unsigned)std::min<int64_t>(a.nplanes, 65535),
-                  (unsigned)ntr);
+template <int IN, int OUT>
+static hipError_t launch_cols_io(float2* data, int L, const ColFFTArgs& a, const double2* tw,
+                                 const ColModes& cm, dim3 grid, hipStream_t s) {
   const dim3 block(kColThreads);
+#define ESN_COLS(LEN, ...)                                                              \
+  case LEN:                                                                             \
+    hipLaunchKernelGGL((fft_cols_kernel<LEN, IN, OUT, __VA_ARGS__>), grid, block, 0, s, \
+                       data, a, tw, cm);                                                \
+    break;
   // radix 4 while it divides, one radix 2 for an odd power of two, then 3s and 5s
   switch (L) {
     ESN_COLS(32, 4, 4, 2)
@@ -209,6 +333,24 @@ hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const doubl
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
+                           int nchunks, int ntr, int in_mode, int out_mode, const ColModes& cm,
+                           hipStream_t s) {
+  const dim3 grid((unsigned)nchunks, (unsigned)std::min<int64_t>(a.nplanes, 65535),
+                  (unsigned)ntr);
+  if (in_mode == kColPlain && out_mode == kColPlain)
+    return launch_cols_io<kColPlain, kColPlain>(data, L, a, tw, cm, grid, s);
+  if (in_mode == kColModes && out_mode == kColPlain)
+    return launch_cols_io<kColModes, kColPlain>(data, L, a, tw, cm, grid, s);
+  if (in_mode == kColMasked && out_mode == kColPlain)
+    return launch_cols_io<kColMasked, kColPlain>(data, L, a, tw, cm, grid, s);
+  if (in_mode == kColPlain && out_mode == kColMasked)
+    return launch_cols_io<kColPlain, kColMasked>(data, L, a, tw, cm, grid, s);
+  if (in_mode == kColPlain && out_mode == kColModes)
+    return launch_cols_io<kColPlain, kColModes>(data, L, a, tw, cm, grid, s);
+  return hipErrorInvalidValue;
 }
 
 #undef ESN_COLS

@@ -708,21 +708,44 @@ static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
     FFTPlan* fp = ntr == chunk ? fft_full : fft_last;
     char* cc = static_cast<char*>(c) + (size_t)c0 * p->M * cs;
     char* ff = static_cast<char*>(f) + (size_t)c0 * Nt * cs;
+    // column FFT plans fold the correction (deconv / amplify) into their z
+    // pass; its time then counts as FFT time
+    ColModes cm;
+    if (fp->modes) {
+      cm.fstride = Nt;
+      for (int m = 0; m < 3; m++) {
+        cm.N[m] = p->N[m];
+        cm.pf[m] = pf[m];
+      }
+      cm.n0 = p->nf[0];
+      cm.n1 = p->nf[1];
+      cm.modeord = p->opts.modeord;
+    }
     if (dir == 1) {
       ESN_HIP(hipMemsetAsync(p->d_grid, 0, (size_t)ntr * G * cs, s));
       if (e) ESN_HIP(hipEventRecord(e[0], s));
       ESN_TRY(run_spread(p, ntr, cc, p->d_grid));
       if (e) ESN_HIP(hipEventRecord(e[1], s));
-      ESN_TRY(fft_exec(fp, p->d_grid));
-      if (e) ESN_HIP(hipEventRecord(e[2], s));
-      ESN_HIP(launch_deconv(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
-                            Nt, pf, s));
+      if (fp->modes) {
+        ESN_TRY(fft_exec_modes(fp, p->d_grid, ff, cm));
+        if (e) ESN_HIP(hipEventRecord(e[2], s));
+      } else {
+        ESN_TRY(fft_exec(fp, p->d_grid));
+        if (e) ESN_HIP(hipEventRecord(e[2], s));
+        ESN_HIP(launch_deconv(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G,
+                              ff, Nt, pf, s));
+      }
     } else {
       if (e) ESN_HIP(hipEventRecord(e[0], s));
-      ESN_HIP(launch_amplify(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G, ff,
-                             Nt, pf, s));
-      if (e) ESN_HIP(hipEventRecord(e[1], s));
-      ESN_TRY(fft_exec(fp, p->d_grid));
+      if (fp->modes) {
+        if (e) ESN_HIP(hipEventRecord(e[1], s));
+        ESN_TRY(fft_exec_modes(fp, p->d_grid, ff, cm));
+      } else {
+        ESN_HIP(launch_amplify(p->prec, p->dim, p->N, p->nf, p->opts.modeord, ntr, p->d_grid, G,
+                               ff, Nt, pf, s));
+        if (e) ESN_HIP(hipEventRecord(e[1], s));
+        ESN_TRY(fft_exec(fp, p->d_grid));
+      }
       if (e) ESN_HIP(hipEventRecord(e[2], s));
       ESN_TRY(run_interp(p, ntr, p->d_grid, cc));
     }

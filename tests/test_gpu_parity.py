@@ -337,3 +337,22 @@ def test_column_fft_grids(case):
         e2 = O.rel_l2(o2[t], O.type2(coords, fs[t], -1))
         print(f"column FFTs {N} sigma {sigma} transform {t}: type 1 {e1:.2e}, type 2 {e2:.2e}")
         assert e1 <= 10 * eps and e2 <= 10 * eps
+
+
+def test_column_fft_modes_in_fft_order():
+    """The column passes that read or write the mode arrays themselves keep
+    the caller's mode order: modeord 1 (FFT order) gives the modeord 0 result
+    permuted, for type 1 and type 2 (odd and even N on a 64 x 256 x 32 grid)."""
+    N = (31, 127, 16)
+    coords = coord_np(I.uniform_points(4000, 3, 911, np.float32), "f32")
+    c = I.complex_normal(4000, 912, np.complex64)
+    f0, info = run_type1(coords, c, N, 1e-5, "f32")
+    assert tuple(int(info.nf[m]) for m in range(3)) == (64, 256, 32)
+    f1, _ = run_type1(coords, c, N, 1e-5, "f32", modeord=1)
+    perm = [np.concatenate([np.arange(n // 2, n), np.arange(0, n // 2)]) for n in reversed(N)]
+    assert np.max(np.abs(f1 - f0[np.ix_(*perm)])) <= 1e-5 * np.max(np.abs(f0))
+    ff = I.complex_normal(tuple(reversed(N)), 913, np.complex64)
+    c0, _ = run_type2(coords, ff, N, 1e-5, "f32")
+    c1, _ = run_type2(coords, ff[np.ix_(*perm)], N, 1e-5, "f32", modeord=1)
+    assert np.max(np.abs(c1 - c0)) <= 1e-5 * np.max(np.abs(c0))
+    assert O.rel_l2(c0, O.type2(coords, ff, -1)) <= 1e-4
