@@ -11,7 +11,9 @@
 // 2^a 3^b 5^c (a >= 5) up to 512 and x a multiple of 32, those two passes are
 // the column FFT kernels (kernels_fft.hip), one launch per pass over both kept
 // runs; otherwise, on power-of-two grids, rocFFT's strided 2D plans, and on
-// other grids the full 3D rocFFT plan.
+// other grids the full 3D rocFFT plan.  With column FFTs the correction
+// (deconvolution for type 1, amplification for type 2) folds into the z pass
+// (fft_exec_modes).
 #include <algorithm>
 #include <cmath>
 #include <mutex>

@@ -17,6 +17,9 @@
 //   the barrier that precedes the writes).
 // * Twiddle factors exp(2 pi i e / L) come from a table computed in FP64 on the
 //   host, staged in LDS.
+// * The z pass may take the correction of Sec. 3.1 step 3 / Sec. 3.2 step 1
+//   itself: type 1 writes f_k = p_k b^_k (eq. (pb1)) into the mode array, type
+//   2 reads p_k f_k from it (zero at the fine-grid points that hold no mode).
 #include "device_common.hpp"
 
 namespace esn {
