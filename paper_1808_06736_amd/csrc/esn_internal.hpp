@@ -300,6 +300,7 @@ struct FFTPlan {
   // take: the kept columns' y and z passes run as column FFTs
   int cols = 0;
   int modes = 0;                       // the correction folds into the z pass
+  int padded = 0;                      // zero-padded transform (fft_make_padded)
   ColFFTArgs cy, cz;
   ColFFTArgs cy_keep, cz_keep;         // the same, keeping the points that hold modes
   int64_t nx = 0;                      // x length
@@ -321,6 +322,13 @@ int fft_exec(FFTPlan* p, void* data);
 // grid (no amplification before it).  Layout of f as for deconv / amplify.
 int fft_exec_modes(FFTPlan* p, void* grid, void* f, const ColModes& cm);
 void fft_destroy(FFTPlan* p);
+// Transform of a 3D grid of lengths L whose input (input_padded = 1) or
+// needed output (0) lies in [0, N) per dimension, the rest of the input being
+// zero: single precision with column-FFT lengths skips the y and z passes of
+// the columns outside; otherwise the full transform.  One transform per call.
+int fft_make_padded(FFTPlan* p, int dim, const int64_t* L, const int64_t* N, int prec, int sign,
+                    hipStream_t s);
+int fft_exec_padded(FFTPlan* p, void* data, int input_padded);
 // Move an FFT plan's work to another stream.
 int fft_set_stream(FFTPlan* p, hipStream_t s);
 

@@ -50,6 +50,52 @@ static rocfft_plan make_one(int dim, const size_t* len, size_t batch, const size
   return st == rocfft_status_success ? p : nullptr;
 }
 
+// Twiddle table of the column FFTs: exp(2 pi i e / ly), e < ly, then
+// exp(2 pi i e / lz), e < lz, in FP64.
+static int col_twiddles(FFTPlan* p) {
+  std::vector<double2> tw((size_t)(p->ly + p->lz));
+  for (int i = 0; i < p->ly + p->lz; i++) {
+    const int len = i < p->ly ? p->ly : p->lz;
+    const int e = i < p->ly ? i : i - p->ly;
+    const double ang = 2.0 * M_PI * (double)e / (double)len;
+    tw[(size_t)i] = make_double2(std::cos(ang), std::sin(ang));
+  }
+  if (hipMalloc(&p->d_tw, tw.size() * sizeof(double2)) != hipSuccess) {
+    p->d_tw = nullptr;
+    return ESN_ERR_ALLOC;
+  }
+  if (hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return ESN_ERR_HIP;
+  return ESN_OK;
+}
+
+// rocFFT work buffer (one for every plan of p: they run one after another on
+// the stream) and execution info on stream s.
+static int finish_plan(FFTPlan* p, hipStream_t s) {
+  if (!p->plan) return ESN_ERR_FFT_PLAN;
+  size_t work = 0;
+  for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]}) {
+    if (!q) continue;
+    size_t wb = 0;
+    if (rocfft_plan_get_work_buffer_size(q, &wb) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
+    work = std::max(work, wb);
+  }
+  p->work_bytes = work;
+  if (rocfft_execution_info_create(&p->info) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
+  if (work > 0) {
+    if (hipMalloc(&p->work, work) != hipSuccess) {
+      p->work = nullptr;
+      return ESN_ERR_ALLOC;
+    }
+    if (rocfft_execution_info_set_work_buffer(p->info, p->work, work) != rocfft_status_success)
+      return ESN_ERR_FFT_PLAN;
+  }
+  if (rocfft_execution_info_set_stream(p->info, (void*)s) != rocfft_status_success)
+    return ESN_ERR_FFT_PLAN;
+  return ESN_OK;
+}
+
 int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int type, int batch,
              int prec, int sign, hipStream_t s) {
   std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
@@ -70,7 +116,6 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
                     fft_cols_supported(nf[2]) && p->grid < ((int64_t)1 << 28);
   const bool prune =
       cols || (dim == 3 && lo + hi < nf[0] && pow2(nf[0]) && pow2(nf[1]) && pow2(nf[2]));
-  size_t work = 0;
   p->stream = s;
   if (cols) {
     const size_t lx[1] = {(size_t)nf[0]};
@@ -126,20 +171,8 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     const int64_t zlo = (nmodes[2] + 1) / 2, zhi = nmodes[2] / 2;
     p->cz_keep.keep_lo = zlo;
     p->cz_keep.keep_hi = zlo + zhi < nf[2] ? zhi : nf[2] - zlo;
-    std::vector<double2> tw((size_t)(p->ly + p->lz));
-    for (int i = 0; i < p->ly + p->lz; i++) {
-      const int len = i < p->ly ? p->ly : p->lz;
-      const int e = i < p->ly ? i : i - p->ly;
-      const double ang = 2.0 * M_PI * (double)e / (double)len;
-      tw[(size_t)i] = make_double2(std::cos(ang), std::sin(ang));
-    }
-    if (hipMalloc(&p->d_tw, tw.size() * sizeof(double2)) != hipSuccess) {
-      p->d_tw = nullptr;
-      return ESN_ERR_ALLOC;
-    }
-    if (hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) !=
-        hipSuccess)
-      return ESN_ERR_HIP;
+    const int rc = col_twiddles(p);
+    if (rc != ESN_OK) return rc;
   } else if (prune) {
     const size_t lx[1] = {(size_t)nf[0]};
     p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
@@ -159,26 +192,71 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     for (int m = 0; m < dim; m++) lengths[m] = (size_t)nf[m];   // fastest first
     p->plan = make_one(dim, lengths, (size_t)batch, nullptr, 0, prec, sign);
   }
-  if (!p->plan) return ESN_ERR_FFT_PLAN;
-  // one work buffer serves every plan (they run one after another on the stream)
-  for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]}) {
-    if (!q) continue;
-    size_t wb = 0;
-    if (rocfft_plan_get_work_buffer_size(q, &wb) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
-    work = std::max(work, wb);
+  return finish_plan(p, s);
+}
+
+int fft_make_padded(FFTPlan* p, int dim, const int64_t* L, const int64_t* N, int prec, int sign,
+                    hipStream_t s) {
+  int64_t grid = 1;
+  for (int m = 0; m < dim; m++) grid *= L[m];
+  const bool cols = dim == 3 && prec == ESN_SINGLE && L[0] % kColWidth == 0 && N[0] < L[0] &&
+                    N[1] < L[1] && fft_cols_supported(L[1]) && fft_cols_supported(L[2]) &&
+                    grid < ((int64_t)1 << 28);
+  if (!cols) return fft_make(p, dim, L, L, 1, 1, prec, sign, s);   // full transform
+  std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+  if (g_rocfft_setup != rocfft_status_success) return ESN_ERR_FFT_PLAN;
+  p->batch = 1;
+  p->elem = 8;
+  p->grid = grid;
+  p->stream = s;
+  p->padded = 1;
+  p->ly = (int)L[1];
+  p->lz = (int)L[2];
+  p->nx = L[0];
+  // column blocks covering x = 0 .. N0 - 1
+  p->nchunks = (int)((N[0] + kColWidth - 1) / kColWidth);
+  ColFFTArgs a;
+  a.chunks_a = p->nchunks;
+  a.chunk_b0 = (int)(L[0] / kColWidth);
+  a.sign = sign;
+  a.tstride = grid;
+  p->cy = a;   // every z plane
+  p->cy.estride = L[0];
+  p->cy.pstride = L[0] * L[1];
+  p->cy.nplanes = p->cy.planes_a = p->cy.plane_b0 = L[2];
+  p->cz = a;   // the y rows 0 .. N1 - 1
+  p->cz.estride = L[0] * L[1];
+  p->cz.pstride = L[0];
+  p->cz.nplanes = p->cz.planes_a = N[1];
+  p->cz.plane_b0 = L[1];
+  const size_t lx[1] = {(size_t)L[0]};
+  p->plan = make_one(1, lx, (size_t)(L[1] * L[2]), nullptr, 0, prec, sign);
+  const int rc = col_twiddles(p);
+  if (rc != ESN_OK) return rc;
+  return finish_plan(p, s);
+}
+
+int fft_exec_padded(FFTPlan* p, void* data, int input_padded) {
+  if (!p->padded) return fft_exec(p, data);
+  float2* g = static_cast<float2*>(data);
+  const ColModes none;
+  void* in[1] = {data};
+  auto xpass = [&] { return rocfft_execute(p->plan, in, nullptr, p->info) == rocfft_status_success; };
+  auto ypass = [&] {
+    return launch_fft_cols(g, p->ly, p->cy, p->d_tw, p->nchunks, 1, 0, 0, none, p->stream);
+  };
+  auto zpass = [&] {
+    return launch_fft_cols(g, p->lz, p->cz, p->d_tw + p->ly, p->nchunks, 1, 0, 0, none,
+                           p->stream);
+  };
+  if (input_padded) {
+    // nonzero input in [0, N): z on its columns, y on its x columns, then x
+    if (zpass() != hipSuccess || ypass() != hipSuccess) return ESN_ERR_HIP;
+    return xpass() ? ESN_OK : ESN_ERR_FFT_PLAN;
   }
-  p->work_bytes = work;
-  if (rocfft_execution_info_create(&p->info) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
-  if (work > 0) {
-    if (hipMalloc(&p->work, work) != hipSuccess) {
-      p->work = nullptr;
-      return ESN_ERR_ALLOC;
-    }
-    if (rocfft_execution_info_set_work_buffer(p->info, p->work, work) != rocfft_status_success)
-      return ESN_ERR_FFT_PLAN;
-  }
-  if (rocfft_execution_info_set_stream(p->info, (void*)s) != rocfft_status_success)
-    return ESN_ERR_FFT_PLAN;
+  // output needed in [0, N) only: x, y on those x columns, z on their y rows
+  if (!xpass()) return ESN_ERR_FFT_PLAN;
+  if (ypass() != hipSuccess || zpass() != hipSuccess) return ESN_ERR_HIP;
   return ESN_OK;
 }
 

@@ -13,7 +13,8 @@
 // FFT of t, inverse FFT, keep N.  Set-up costs one type 1 transform; each
 // application two FFTs of prod(2 N_i) points, against a type 2 and a type 1
 // transform (with their spreading and interpolation) for A^H W A applied
-// directly.
+// directly.  The forward FFT's input is zero outside [0, N) and only [0, N) of
+// the inverse FFT is kept, so both may skip the other columns.
 #include <cstring>
 
 #include "esn_internal.hpp"
@@ -25,7 +26,8 @@ struct esn_toeplitz_s {
   hipStream_t stream = nullptr;
   ToepArgs a;
   int64_t ltot = 1, ntot = 1;
-  FFTPlan fwd, bwd;
+  FFTPlan fwd;          // full transform (the generating values)
+  FFTPlan pfwd, pbwd;   // of the zero-padded input, and for the output in [0, N)
   void* d_that = nullptr;   // FFT of the circulant's first column / prod(L)
   void* d_grid = nullptr;   // doubled work grid
 };
@@ -43,7 +45,8 @@ void toep_free(esn_toeplitz t) {
   if (!t) return;
   (void)hipStreamSynchronize(t->stream);
   fft_destroy(&t->fwd);
-  fft_destroy(&t->bwd);
+  fft_destroy(&t->pfwd);
+  fft_destroy(&t->pbwd);
   if (t->d_that) (void)hipFree(t->d_that);
   if (t->d_grid) (void)hipFree(t->d_grid);
   delete t;
@@ -113,7 +116,10 @@ extern "C" int esn_toeplitz_makeplan(int dim, const int64_t* nmodes, int isign, 
 
   // its FFT, with the inverse transform's 1 / prod(L) folded in
   rc = fft_make(&t->fwd, dim, t->a.L, t->a.L, 1, 1, prec, -1, t->stream);
-  if (rc == ESN_OK) rc = fft_make(&t->bwd, dim, t->a.L, t->a.L, 2, 1, prec, +1, t->stream);
+  // an application's input is zero outside [0, N) and only [0, N) of its
+  // output is kept, so its transforms may skip the other columns
+  if (rc == ESN_OK) rc = fft_make_padded(&t->pfwd, dim, t->a.L, t->a.N, prec, -1, t->stream);
+  if (rc == ESN_OK) rc = fft_make_padded(&t->pbwd, dim, t->a.L, t->a.N, prec, +1, t->stream);
   if (rc != ESN_OK) return fail(rc);
   if (fft_exec(&t->fwd, t->d_that) != ESN_OK) return fail(ESN_ERR_FFT_PLAN);
   if (launch_scale(prec, t->d_that, t->ltot, 1.0 / (double)t->ltot, t->stream) != hipSuccess ||
@@ -128,9 +134,9 @@ extern "C" int esn_toeplitz_apply(esn_toeplitz t, const void* f, void* g) {
   ESN_HIP(hipSetDevice(t->device));
   hipStream_t s = t->stream;
   ESN_HIP(launch_toep_pad(t->a, t->prec, f, t->d_grid, s));
-  if (fft_exec(&t->fwd, t->d_grid) != ESN_OK) return ESN_ERR_FFT_PLAN;
+  if (fft_exec_padded(&t->pfwd, t->d_grid, 1) != ESN_OK) return ESN_ERR_FFT_PLAN;
   ESN_HIP(launch_cmul(t->prec, t->d_grid, t->d_that, t->d_grid, t->ltot, 1, s));
-  if (fft_exec(&t->bwd, t->d_grid) != ESN_OK) return ESN_ERR_FFT_PLAN;
+  if (fft_exec_padded(&t->pbwd, t->d_grid, 0) != ESN_OK) return ESN_ERR_FFT_PLAN;
   ESN_HIP(launch_toep_extract(t->a, t->prec, t->d_grid, g, s));
   return ESN_OK;
 }

@@ -22,6 +22,10 @@ CASES = [
     (2, (48, 48), 12000, "wrapped_gaussian", "f32", 1e-5, False, 1),
     (3, (16, 12, 20), 20000, "uniform", "f32", 1e-6, True, 0),
     (3, (14, 15, 13), 10000, "wrapped_gaussian", "f64", 1e-8, False, 1),
+    # doubled grids 96 x 32 x 160 and 32 x 96 x 32: column FFTs that skip the
+    # columns outside the zero-padded input / the kept output
+    (3, (48, 16, 80), 20000, "uniform", "f32", 1e-6, True, 1),
+    (3, (16, 48, 16), 15000, "wrapped_gaussian", "f32", 1e-5, False, 0),
 ]
 
 
