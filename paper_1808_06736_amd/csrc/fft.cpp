@@ -11,7 +11,8 @@
 // 2^a 3^b 5^c (a >= 5) up to 512 and x a multiple of 32, those two passes are
 // the column FFT kernels (kernels_fft.hip), one launch per pass over both kept
 // runs; otherwise, on power-of-two grids, rocFFT's strided 2D plans, and on
-// other grids the full 3D rocFFT plan.  With column FFTs the correction
+// other grids the full 3D rocFFT plan.  2D transforms on such lengths run the
+// x pass and the y pass on the kept columns the same way.  With column FFTs the correction
 // (deconvolution for type 1, amplification for type 2) folds into the z pass
 // (fft_exec_modes).
 #include <algorithm>
@@ -111,15 +112,16 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
   // (on a 256^3 grid x pass + kept runs take 153 us against 191 us for the full
   // 3D plan; on 288^3 789 us against 487 us), so other sizes take the full plan
   auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
-  const bool cols = dim == 3 && lo + hi < nf[0] && prec == ESN_SINGLE &&
+  const bool cols = dim >= 2 && lo + hi < nf[0] && prec == ESN_SINGLE &&
                     nf[0] % kColWidth == 0 && fft_cols_supported(nf[1]) &&
-                    fft_cols_supported(nf[2]) && p->grid < ((int64_t)1 << 28);
+                    (dim == 2 || fft_cols_supported(nf[2])) && p->grid < ((int64_t)1 << 28);
   const bool prune =
       cols || (dim == 3 && lo + hi < nf[0] && pow2(nf[0]) && pow2(nf[1]) && pow2(nf[2]));
   p->stream = s;
   if (cols) {
+    const int64_t n2 = dim == 3 ? nf[2] : 1;
     const size_t lx[1] = {(size_t)nf[0]};
-    p->plan = make_one(1, lx, (size_t)batch * nf[1] * nf[2], nullptr, 0, prec, sign);
+    p->plan = make_one(1, lx, (size_t)batch * nf[1] * n2, nullptr, 0, prec, sign);
     // column blocks of 32 covering x = 0 .. lo - 1 and x = nf0 - hi .. nf0 - 1;
     // blocks that would cover a column twice merge into one range
     const int all = (int)(nf[0] / kColWidth);
@@ -132,9 +134,11 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     }
     p->nchunks = ca + (all - cb0);
     p->cols = 1;
-    p->modes = 1;
+    // 2D: the y pass on the kept columns, no z pass; the correction stays in
+    // its own kernels
+    p->modes = dim == 3;
     p->ly = (int)nf[1];
-    p->lz = (int)nf[2];
+    p->lz = dim == 3 ? (int)nf[2] : 0;
     ColFFTArgs a;
     a.chunks_a = ca;
     a.chunk_b0 = cb0;
@@ -147,9 +151,9 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     p->cy = a;
     p->cy.estride = nf[0];
     p->cy.pstride = nf[0] * nf[1];
-    p->cy.nplanes = nf[2];
-    p->cy.planes_a = nf[2];
-    p->cy.plane_b0 = nf[2];
+    p->cy.nplanes = n2;
+    p->cy.planes_a = n2;
+    p->cy.plane_b0 = n2;
     p->cz = a;
     p->cz.estride = nf[0] * nf[1];
     p->cz.pstride = nf[0];
@@ -168,9 +172,11 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
     p->cy_keep.keep_lo = ylo;
     p->cy_keep.keep_hi = ylo + yhi < nf[1] ? yhi : nf[1] - ylo;
     p->cz_keep = p->cz;
-    const int64_t zlo = (nmodes[2] + 1) / 2, zhi = nmodes[2] / 2;
-    p->cz_keep.keep_lo = zlo;
-    p->cz_keep.keep_hi = zlo + zhi < nf[2] ? zhi : nf[2] - zlo;
+    if (dim == 3) {
+      const int64_t zlo = (nmodes[2] + 1) / 2, zhi = nmodes[2] / 2;
+      p->cz_keep.keep_lo = zlo;
+      p->cz_keep.keep_hi = zlo + zhi < nf[2] ? zhi : nf[2] - zlo;
+    }
     const int rc = col_twiddles(p);
     if (rc != ESN_OK) return rc;
   } else if (prune) {
@@ -278,9 +284,9 @@ int fft_exec(FFTPlan* p, void* data) {
     };
     if (p->x_first) {   // type 1: x, y, z (kept y rows)
       if (!run(p->plan, data)) return ESN_ERR_FFT_PLAN;
-      if (ypass() != hipSuccess || zpass() != hipSuccess) return ESN_ERR_HIP;
+      if (ypass() != hipSuccess || (p->lz && zpass() != hipSuccess)) return ESN_ERR_HIP;
     } else {            // type 2: z (kept y rows), y, x
-      if (zpass() != hipSuccess || ypass() != hipSuccess) return ESN_ERR_HIP;
+      if ((p->lz && zpass() != hipSuccess) || ypass() != hipSuccess) return ESN_ERR_HIP;
       if (!run(p->plan, data)) return ESN_ERR_FFT_PLAN;
     }
     return ESN_OK;

@@ -356,3 +356,26 @@ def test_column_fft_modes_in_fft_order():
     c1, _ = run_type2(coords, ff[np.ix_(*perm)], N, 1e-5, "f32", modeord=1)
     assert np.max(np.abs(c1 - c0)) <= 1e-5 * np.max(np.abs(c0))
     assert O.rel_l2(c0, O.type2(coords, ff, -1)) <= 1e-4
+
+
+@pytest.mark.parametrize("N,ntr,nf", [((64, 80), 1, (128, 160)), ((47, 143), 3, (96, 288))],
+                         ids=["64x80", "47x143-t3"])
+def test_column_fft_grids_2d(N, ntr, nf):
+    """2D single-precision plans on column-FFT lengths run the y pass on the
+    kept x columns only: type 1 and type 2 meet the bar for every transform."""
+    eps, M = 1e-5, 20000
+    coords = coord_np(I.wrapped_gaussian_points(M, 2, 921, 0.5, np.float32), "f32")
+    c = I.complex_normal((ntr, M) if ntr > 1 else M, 922, np.complex64)
+    f = I.complex_normal(((ntr,) if ntr > 1 else ()) + tuple(reversed(N)), 923, np.complex64)
+    out1, info = run_type1(coords, c, N, eps, "f32", ntransf=ntr)
+    assert tuple(int(info.nf[m]) for m in range(2)) == nf
+    out2, _ = run_type2(coords, f, N, eps, "f32", ntransf=ntr)
+    cs = c.reshape(ntr, M)
+    fs = f.reshape((ntr,) + tuple(reversed(N)))
+    o1 = out1.reshape((ntr,) + tuple(reversed(N)))
+    o2 = out2.reshape(ntr, M)
+    for t in range(ntr):
+        e1 = O.rel_l2(o1[t], O.type1(coords, cs[t], +1, N=N))
+        e2 = O.rel_l2(o2[t], O.type2(coords, fs[t], -1))
+        print(f"2D column FFTs {N} transform {t}: type 1 {e1:.2e}, type 2 {e2:.2e}")
+        assert e1 <= 10 * eps and e2 <= 10 * eps
