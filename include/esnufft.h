@@ -231,6 +231,9 @@ typedef struct esn_stats {
    * Types 1 and 2 record HIP events around the stages and read them only
    * here, so timing adds no host synchronisation to the calls; reading waits
    * for the calls timed.
+   * 3D single-precision plans whose FFT runs as column FFTs carry the
+   * correction (deconvolution / amplification) inside the FFT: t_fft then
+   * includes it and t_deconv_or_amplify is only the gap between the stages.
    * Type 3 plans: t_spread_or_interp = spreading (step 1), t_fft = the inner
    * type 2 transform (step 2), t_deconv_or_amplify = that transform's
    * interpolation alone. */
