@@ -3,17 +3,19 @@
 // modes.  A 3D DFT is three passes of 1D DFTs, one per dimension; the y and z
 // passes act on each x column by itself, so they may skip the others.
 //
-// A block takes 32 neighbouring x columns of one plane (a z plane for the y
-// pass, a y row for the z pass) and runs their 32 length-L DFTs, unnormalised,
-// with exponent sign sgn: out[r] = sum_j in[j] exp(sgn 2 pi i j r / L).
-// * Reads and writes move 32 consecutive complex values (256 bytes) per grid
-//   row, so every access is coalesced whatever the stride between the DFT's
-//   points.
+// A block takes W = 16 or 32 neighbouring x columns of one plane (a z plane
+// for the y pass, a y row for the z pass) and runs their W length-L DFTs,
+// unnormalised, with exponent sign sgn: out[r] = sum_j in[j] exp(sgn 2 pi i j
+// r / L).
+// * Reads and writes move W consecutive complex values (128 or 256 bytes) per
+//   grid row, so every access is coalesced whatever the stride between the
+//   DFT's points.  W = 16 (half the LDS, twice the blocks per CU) where every
+//   stage splits over 16 threads per column.
 // * Self-sorting (Stockham) mixed-radix stages: radix 4 while it divides, one
 //   radix 2 for an odd power of two, then radix 3 and radix 5 (lengths
 //   L = 2^a 3^b 5^c with a >= 5, up to 512).  The first stage reads the grid,
 //   the last writes it; the stages in between exchange through one LDS array
-//   of L x 32 values (each thread holds all inputs of its butterflies before
+//   of L x W values (each thread holds all inputs of its butterflies before
 //   the barrier that precedes the writes).
 // * Twiddle factors exp(2 pi i e / L) come from a table computed in FP64 on the
 //   host, staged in LDS.
@@ -24,9 +26,7 @@
 
 namespace esn {
 
-constexpr int kColW = kColWidth;                 // columns per block
 constexpr int kColThreads = 256;
-constexpr int kColGroups = kColThreads / kColW;  // butterfly groups per column
 
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -157,27 +157,29 @@ struct ColIO {
 // Stages from sub-transform length LS on, radices R, Rest... .  A radix-R
 // stage combines, for j = q LS + k (k < LS), the points q LS + k + m L/R
 // (m < R), twiddled by w^(k m L / (R LS)), into q R LS + k + r LS (r < R);
-// w = exp(sgn 2 pi i / L).  Thread (c, g) takes j = g + 8 b; where LS is a
-// multiple of 8, k = g + (8 b mod LS) and q = 8 b / LS, so the grid points of
-// the first and the last stage are g plus a uniform part.
-template <int L, int IN, int OUT, int LS, int R, int... Rest>
+// w = exp(sgn 2 pi i / L).  A block of W columns has G = 256 / W threads per
+// column; thread (c, g) takes j = g + G b.  Where LS is a multiple of G,
+// k = g + (G b mod LS) and q = G b / LS, so the grid points of the first and
+// the last stage are g plus a uniform part.
+template <int L, int W, int IN, int OUT, int LS, int R, int... Rest>
 __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2* __restrict__ tw,
                                            float sgn, const ColIO& io, int c, int g) {
+  constexpr int G = kColThreads / W;
   constexpr bool first = LS == 1;
   constexpr bool last = sizeof...(Rest) == 0;
-  static_assert((L / R) % kColGroups == 0, "butterflies split evenly over the groups");
-  static_assert(!last || (LS % kColGroups == 0 && LS * R == L), "last stage");
-  constexpr int B = L / R / kColGroups;   // butterflies per thread
+  static_assert((L / R) % G == 0, "butterflies split evenly over the groups");
+  static_assert(!last || (LS % G == 0 && LS * R == L), "last stage");
+  constexpr int B = L / R / G;   // butterflies per thread
   float2 v[B][R];
 #pragma unroll
   for (int b = 0; b < B; b++) {
-    const int j = g + kColGroups * b, k = j % LS, q = j / LS;
+    const int j = g + G * b, k = j % LS, q = j / LS;
 #pragma unroll
     for (int m = 0; m < R; m++) {
       if constexpr (first)
-        v[b][m] = io.load<IN, L>(g, kColGroups * b + m * (L / R));
+        v[b][m] = io.load<IN, L>(g, G * b + m * (L / R));
       else
-        v[b][m] = s[(q * LS + k + m * (L / R)) * kColW + c];
+        v[b][m] = s[(q * LS + k + m * (L / R)) * W + c];
     }
     if constexpr (!first) {
 #pragma unroll
@@ -191,37 +193,37 @@ __device__ __forceinline__ void col_stages(float2* __restrict__ s, const float2*
   if constexpr (!first) __syncthreads();   // every read of s is done
 #pragma unroll
   for (int b = 0; b < B; b++) {
-    const int j = g + kColGroups * b, k = j % LS, q = j / LS;
+    const int j = g + G * b, k = j % LS, q = j / LS;
 #pragma unroll
     for (int r = 0; r < R; r++) {
       if constexpr (last)
-        io.store<OUT, L>(g, (kColGroups * b / LS) * R * LS + (kColGroups * b) % LS + r * LS,
+        io.store<OUT, L>(g, (G * b / LS) * R * LS + (G * b) % LS + r * LS,
                          v[b][r]);
       else
-        s[(q * R * LS + k + r * LS) * kColW + c] = v[b][r];
+        s[(q * R * LS + k + r * LS) * W + c] = v[b][r];
     }
   }
   if constexpr (!last) {
     __syncthreads();
-    col_stages<L, IN, OUT, LS * R, Rest...>(s, tw, sgn, io, c, g);
+    col_stages<L, W, IN, OUT, LS * R, Rest...>(s, tw, sgn, io, c, g);
   }
 }
 
-template <int L, int IN, int OUT, int... Rs>
+template <int L, int W, int IN, int OUT, int... Rs>
 __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restrict__ data,
                                                                const ColFFTArgs a,
                                                                const double2* __restrict__ twd,
                                                                const ColModes cm) {
   static_assert(L >= 32 && L <= 512, "lengths 32 .. 512");
-  __shared__ float2 s[L * kColW];
+  __shared__ float2 s[L * W];
   __shared__ float2 tw[L];
-  const int c = threadIdx.x % kColW, g = threadIdx.x / kColW;
+  const int c = threadIdx.x % W, g = threadIdx.x / W;
   const float sgn = (float)a.sign;
   for (int i = threadIdx.x; i < L; i += kColThreads)
     tw[i] = make_float2((float)twd[i].x, (float)(a.sign * twd[i].y));
   const int chunk = (int)blockIdx.x < a.chunks_a ? (int)blockIdx.x
                                                   : a.chunk_b0 + ((int)blockIdx.x - a.chunks_a);
-  float2* gt = data + (int64_t)blockIdx.z * a.tstride + (int64_t)chunk * kColW;
+  float2* gt = data + (int64_t)blockIdx.z * a.tstride + (int64_t)chunk * W;
   ColIO io;
   io.gp.es8 = a.estride * (int64_t)sizeof(float2);
   io.gp.loff = (uint32_t)((c + (int64_t)g * a.estride) * (int64_t)sizeof(float2));
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   __shared__ int zoff[modes ? L : 1];
   __shared__ float zfac[modes ? L : 1];
   if constexpr (modes) {
-    const int64_t x = (int64_t)chunk * kColW + c;
+    const int64_t x = (int64_t)chunk * W + c;
     const int64_t N0 = cm.N[0], N2 = cm.N[2];
     x_ok = x < N0 - N0 / 2 || x >= cm.n0 - N0 / 2;
     kx = x < N0 - N0 / 2 ? x : x - cm.n0;
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
                    ? (float)(cm.pf[0][kx < 0 ? -kx : kx] * cm.pf[1][ky < 0 ? -ky : ky])
                    : 0.f;
     }
-    col_stages<L, IN, OUT, 1, Rs...>(s, tw, sgn, io, c, g);
+    col_stages<L, W, IN, OUT, 1, Rs...>(s, tw, sgn, io, c, g);
   }
 }
 
@@ -310,29 +312,38 @@ bool fft_cols_supported(int64_t L) {
   }
 }
 
+// Blocks of 16 columns (128-byte rows; half the LDS of 32, so twice the
+// blocks per CU) where every stage splits over 16 threads per column, i.e.
+// L a multiple of 64; 32 columns otherwise.  a, nchunks: in blocks of 32.
 template <int IN, int OUT>
 static hipError_t launch_cols_io(float2* data, int L, const ColFFTArgs& a, const double2* tw,
-                                 const ColModes& cm, dim3 grid, hipStream_t s) {
+                                 const ColModes& cm, int nchunks, int ntr, hipStream_t s) {
   const dim3 block(kColThreads);
-#define ESN_COLS(LEN, ...)                                                              \
-  case LEN:                                                                             \
-    hipLaunchKernelGGL((fft_cols_kernel<LEN, IN, OUT, __VA_ARGS__>), grid, block, 0, s, \
-                       data, a, tw, cm);                                                \
+  const int narrow = L % 64 == 0 ? 2 : 1;   // blocks per 32 columns
+  ColFFTArgs b = a;
+  b.chunks_a *= narrow;
+  b.chunk_b0 *= narrow;
+  const dim3 grid((unsigned)(nchunks * narrow), (unsigned)std::min<int64_t>(a.nplanes, 65535),
+                  (unsigned)ntr);
+#define ESN_COLS(LEN, WID, ...)                                                              \
+  case LEN:                                                                                  \
+    hipLaunchKernelGGL((fft_cols_kernel<LEN, WID, IN, OUT, __VA_ARGS__>), grid, block, 0, s, \
+                       data, b, tw, cm);                                                     \
     break;
   // radix 4 while it divides, one radix 2 for an odd power of two, then 3s and 5s
   switch (L) {
-    ESN_COLS(32, 4, 4, 2)
-    ESN_COLS(64, 4, 4, 4)
-    ESN_COLS(96, 4, 4, 2, 3)
-    ESN_COLS(128, 4, 4, 4, 2)
-    ESN_COLS(160, 4, 4, 2, 5)
-    ESN_COLS(192, 4, 4, 4, 3)
-    ESN_COLS(256, 4, 4, 4, 4)
-    ESN_COLS(288, 4, 4, 2, 3, 3)
-    ESN_COLS(320, 4, 4, 4, 5)
-    ESN_COLS(384, 4, 4, 4, 2, 3)
-    ESN_COLS(480, 4, 4, 2, 3, 5)
-    ESN_COLS(512, 4, 4, 4, 4, 2)
+    ESN_COLS(32, 32, 4, 4, 2)
+    ESN_COLS(64, 16, 4, 4, 4)
+    ESN_COLS(96, 32, 4, 4, 2, 3)
+    ESN_COLS(128, 16, 4, 4, 4, 2)
+    ESN_COLS(160, 32, 4, 4, 2, 5)
+    ESN_COLS(192, 16, 4, 4, 4, 3)
+    ESN_COLS(256, 16, 4, 4, 4, 4)
+    ESN_COLS(288, 32, 4, 4, 2, 3, 3)
+    ESN_COLS(320, 16, 4, 4, 4, 5)
+    ESN_COLS(384, 16, 4, 4, 4, 2, 3)
+    ESN_COLS(480, 32, 4, 4, 2, 3, 5)
+    ESN_COLS(512, 16, 4, 4, 4, 4, 2)
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -341,18 +352,16 @@ static hipError_t launch_cols_io(float2* data, int L, const ColFFTArgs& a, const
 hipError_t launch_fft_cols(float2* data, int L, const ColFFTArgs& a, const double2* tw,
                            int nchunks, int ntr, int in_mode, int out_mode, const ColModes& cm,
                            hipStream_t s) {
-  const dim3 grid((unsigned)nchunks, (unsigned)std::min<int64_t>(a.nplanes, 65535),
-                  (unsigned)ntr);
   if (in_mode == kColPlain && out_mode == kColPlain)
-    return launch_cols_io<kColPlain, kColPlain>(data, L, a, tw, cm, grid, s);
+    return launch_cols_io<kColPlain, kColPlain>(data, L, a, tw, cm, nchunks, ntr, s);
   if (in_mode == kColModes && out_mode == kColPlain)
-    return launch_cols_io<kColModes, kColPlain>(data, L, a, tw, cm, grid, s);
+    return launch_cols_io<kColModes, kColPlain>(data, L, a, tw, cm, nchunks, ntr, s);
   if (in_mode == kColMasked && out_mode == kColPlain)
-    return launch_cols_io<kColMasked, kColPlain>(data, L, a, tw, cm, grid, s);
+    return launch_cols_io<kColMasked, kColPlain>(data, L, a, tw, cm, nchunks, ntr, s);
   if (in_mode == kColPlain && out_mode == kColMasked)
-    return launch_cols_io<kColPlain, kColMasked>(data, L, a, tw, cm, grid, s);
+    return launch_cols_io<kColPlain, kColMasked>(data, L, a, tw, cm, nchunks, ntr, s);
   if (in_mode == kColPlain && out_mode == kColModes)
-    return launch_cols_io<kColPlain, kColModes>(data, L, a, tw, cm, grid, s);
+    return launch_cols_io<kColPlain, kColModes>(data, L, a, tw, cm, nchunks, ntr, s);
   return hipErrorInvalidValue;
 }
 
