@@ -24,6 +24,10 @@ One JSON line is printed.  Besides the contract fields it carries
 * ``parity``: the GPU output's relative l2 error on that oracle sample;
 * ``sort_ablation`` (both types on one point set): execute with the points
   left unsorted against the bin-sorted execute, alone and with the sort.
+``stages`` holds the library's per-stage times; where the FFT runs as column
+FFTs (3D single precision on column-FFT lengths, as the headline) it carries
+the deconvolution / amplification, so ``fft_ms`` includes them and
+``deconv_ms`` / ``amplify_ms`` are only the gaps between the stages.
 """
 from __future__ import annotations
 
