@@ -108,9 +108,10 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
   p->x_first = type == 1;
   // kept x runs: k1 = 0 .. ceil(N1/2) - 1 and n1 - floor(N1/2) .. n1 - 1
   const int64_t lo = (nmodes[0] + 1) / 2, hi = nmodes[0] / 2;
-  // rocFFT's strided (y, z) transforms are fast only for power-of-two sizes
-  // (on a 256^3 grid x pass + kept runs take 153 us against 191 us for the full
-  // 3D plan; on 288^3 789 us against 487 us), so other sizes take the full plan
+  // column FFTs where they apply; else rocFFT's strided (y, z) transforms,
+  // which are fast only for power-of-two sizes (on a 256^3 grid x pass + kept
+  // runs take 153 us against 191 us for the full 3D plan; on 288^3 789 us
+  // against 487 us), and the full plan for other sizes
   auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
   const bool cols = dim >= 2 && lo + hi < nf[0] && prec == ESN_SINGLE &&
                     nf[0] % kColWidth == 0 && fft_cols_supported(nf[1]) &&
