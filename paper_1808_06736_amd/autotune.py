@@ -1,6 +1,6 @@
 """Autotuner for the plan options that only change speed.
 
-Bin size, subproblem size (Sec. 4.1, 4.2), the spreading / interpolation method
+Bin size, subproblem size (Sec. 5.1, 5.2), the spreading / interpolation method
 and the number of vectors fused per launch do not change the result beyond
 rounding, only the time.  ``tune`` times a small candidate set on the caller's
 actual points (execute only, best of a few runs, after a warm-up) and returns

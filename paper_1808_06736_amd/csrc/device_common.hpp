@@ -114,7 +114,7 @@ __device__ __forceinline__ void es_weights_t(int sh, T f, T beta, T* ker) {
 }
 
 // The same from the piecewise polynomial table c[W][W + kPolyExtra + 1]
-// (Sec. 4.3): window cell k lies in interval k at the local coordinate
+// (Sec. 5.3): window cell k lies in interval k at the local coordinate
 // t = 2 u - 1, u = l0 - t_point + W/2 in [0, 1) (the same for all k), and its
 // weight is interval k's polynomial at t (Horner's scheme).  c is the same for
 // every thread, so its values come through scalar loads.

@@ -1,6 +1,6 @@
 // Spreading and interpolation on the matrix cores (3D, single precision,
 // w <= 7), one wave per subproblem (a run of at most maxsub bin-sorted points
-// of one bin, Sec. 4.2).
+// of one bin, Sec. 5.2).
 //
 // Points are binned by window cell (the cell floor(w/2) after the first cell
 // of the point's window), so a point in window cell l has its w window cells

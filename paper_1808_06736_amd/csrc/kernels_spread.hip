@@ -1,6 +1,6 @@
 // Spreading, eq. (bl):  b_l = sum_j c_j psi~(l h - x_j)  on the fine grid.
 //
-// spread_lds: one wave per subproblem (Sec. 4.2).  A subproblem is a run of at
+// spread_lds: one wave per subproblem (Sec. 5.2).  A subproblem is a run of at
 // most maxsub bin-sorted points of one bin.  The wave spreads them into a tile
 // in LDS covering the bin plus a halo (bin + w cells per dim, so no index
 // wrapping is needed while spreading), then adds the tile to the fine grid

@@ -168,7 +168,7 @@ extern "C" int esn_correction_factors(int w, double beta, int nquad, int64_t nf,
   return ESN_OK;
 }
 
-// Piecewise polynomial form of the ES kernel (Sec. 4.3): the support [-1, 1]
+// Piecewise polynomial form of the ES kernel (Sec. 5.3): the support [-1, 1]
 // of phi(z) = exp(beta (sqrt(1 - z^2) - 1)) is split into w equal intervals,
 // one per window cell, and each is replaced by a polynomial of degree w + 3
 // in the local variable t in [-1, 1], z = (k + (t + 1) / 2 - w / 2) (2 / w) on

@@ -4,7 +4,7 @@ This module only draws random numbers and lays out index samples.  It holds
 none of the transform's arithmetic, so both the GPU path's tests/benchmarks and
 the CPU oracle's tests can use it without sharing any of the method.
 
-Workloads (point distributions follow the paper's performance tests, Sec. 5
+Workloads (point distributions follow the paper's performance tests, Sec. 6
 "Tasks": iid uniform points in 1D/2D/3D, radial "disc quad"-like sets whose
 density diverges at the origin, and complex Gaussian strengths):
 

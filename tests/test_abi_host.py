@@ -64,7 +64,7 @@ def test_width_rule(digits):
 
 
 def test_paper_width_examples():
-    """Widths printed in the paper's parallel scaling discussion (Sec. 5):
+    """Widths printed in the paper's parallel scaling discussion (Sec. 6):
     eps = 1e-12 touches 13^3 fine grid points, eps = 1e-3 touches 4^3."""
     rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_widths.txt"))
             if l.strip() and not l.startswith("#")]
@@ -196,7 +196,7 @@ def _phi(beta, z):
 
 @pytest.mark.parametrize("w", range(2, 17))
 def test_kernel_poly_table_matches_kernel(w):
-    """Sec. 4.3: w intervals, degree w + 3.  The table reproduces phi on every
+    """Sec. 5.3: w intervals, degree w + 3.  The table reproduces phi on every
     interval to well below the tolerance the width is chosen for
     (eps = 10^-(w-1); FP64 rounding bounds it at w = 15, 16), and a point's w
     window weights (window cells l0 .. l0 + w - 1, l0 = ceil(t - w/2)) come out

@@ -234,7 +234,7 @@ KEREVAL_CASES = [
 @pytest.mark.parametrize("type_", [1, 2])
 def test_kernel_table_and_direct_evaluation(case, type_):
     """Both kernel evaluations (exp and sqrt at every weight, and the piecewise
-    polynomial table of Sec. 4.3) meet the bar with every spreading or
+    polynomial table of Sec. 5.3) meet the bar with every spreading or
     interpolation method, and agree with each other to eps (double precision)
     or to the single precision rounding floor."""
     dim, N, M, points, prec, eps = case

@@ -35,7 +35,7 @@ def test_single_point_spread_is_kernel_tensor(prec, kerevalmeth):
     """One unit strength at x spreads, eq. (bl), to the w^3 tensor product of
     phi((l h - x) / alpha) on the window l0..l0+w-1, l0 = ceil(x/h - w/2):
     to rounding with exp and sqrt at each weight, and to the piecewise
-    polynomial table's fit error (below eps / 10, Sec. 4.3) with the table."""
+    polynomial table's fit error (below eps / 10, Sec. 5.3) with the table."""
     N = (16, 20, 12)
     eps = 1e-6 if prec == "f32" else 1e-9
     x = np.array([0.3]), np.array([-2.0]), np.array([3.1])
@@ -184,7 +184,7 @@ def test_modeord_fft_order():
 
 @pytest.mark.parametrize("dim,prec", [(2, "f32"), (3, "f32"), (3, "f64")])
 def test_unsorted_matches_sorted(dim, prec):
-    """The sort/no-sort ablation (Sec. 4.1): same result either way."""
+    """The sort/no-sort ablation (Sec. 5.1): same result either way."""
     N = (30, 26, 22)[:dim]
     coords = I.wrapped_gaussian_points(30000, dim, 111, 0.4, np.float32 if prec == "f32" else np.float64)
     cdt = np.complex64 if prec == "f32" else np.complex128
