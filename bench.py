@@ -10,7 +10,7 @@ points once and runs type 2 as its adjoint (opposite sign) on the same sorted
 points; the same step with one plan per type, each sorting for itself, is timed
 too and reported under ``separate_plans``.  Plans (kernel parameters, the FP64
 quadrature of the kernel's Fourier transform, rocFFT plans) are made once
-before timing, as the paper times only calls after planning (Sec. 5).  All
+before timing, as the paper times only calls after planning (Sec. 6).  All
 inputs are resident in HBM before the timed region.  ``value`` = NU points
 processed per second (M * ntransf per transform type, summed) over the timed
 steps.
@@ -70,7 +70,7 @@ def parse():
                     help="offered loads as fractions of the plain serial throughput")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-sort-ablation", action="store_true",
-                    help="skip the unsorted-points comparison (Sec. 4.1)")
+                    help="skip the unsorted-points comparison (Sec. 5.1)")
     ap.add_argument("--traffic", default="",
                     help="JSON with measured HBM bytes per launch of the dominant "
                          "kernel ({\"kernel\": ..., \"bytes\": ...}) for roofline.traffic")
@@ -336,9 +336,23 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
                                                           outs, args.cpu_sample)
+    if wl.name == "3d_clustered":
+        out["paper_cpu_context"] = PAPER_CPU_CONTEXT
     for p in {id(p): p for p in plans.values()}.values():
         p.close()
     print(json.dumps(out))
+
+
+# The paper's own 3D type 1 figure (Sec. 6.1, Table 2), quoted as context
+# with its hardware: another machine, another problem size, FP64.
+PAPER_CPU_CONTEXT = {
+    "what": "3D type 1, N = 256^3 modes, M = 3e8 points clustered at the origin, tol 1e-6",
+    "time_s": 14.6,
+    "nu_pts_per_s": 3e8 / 14.6,
+    "rel_l2": 1.4e-6,
+    "hardware": "2 x Intel Xeon E5-2643 (3.4 GHz), 12 cores / 24 threads, FP64",
+    "source": "Sec. 6.1, Table 2",
+}
 
 
 def bench_type3(args, wl):
@@ -422,13 +436,14 @@ def bench_type3(args, wl):
                                "sample": f"{nt} targets x {M} sources ({dt:.1f} s); scaled to "
                                          f"all {N} targets of one step",
                                "cpu": _cpu_model()}
-        res["parity"] = {"rel_l2": O.rel_l2(out.cpu().numpy()[idx], ref), "bar": 10 * wl.eps}
+        e, lo, hi = O.rel_l2_interval(out.cpu().numpy()[idx], ref, seed=3)
+        res["parity"] = {"rel_l2": e, "ci95": [lo, hi], "bar": 10 * wl.eps}
     p.close()
     print(json.dumps(res))
 
 
 def sort_ablation(wl, N, coords, c_in, f_in, outs, cdt, stages, reps=3):
-    """The bin sort's effect (Sec. 4.1): execute with the points in the caller's
+    """The bin sort's effect (Sec. 5.1): execute with the points in the caller's
     order (sort 0: one thread per point, global atomics for type 1, direct
     gathers for type 2) against the bin-sorted execute of the timed loop, alone
     and with the sort (setpts) added."""
@@ -647,7 +662,9 @@ def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
         fg = outs[1].cpu().numpy()
         fg = fg[0] if ntr > 1 else fg
         idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
-        parity["type1_rel_l2"] = O.rel_l2(fg[idx], ref)
+        e, lo, hi = O.rel_l2_interval(fg[idx], ref, seed=1)
+        parity["type1_rel_l2"] = e
+        parity["type1_ci95"] = [lo, hi]
     if 2 in wl.types:
         # about 2e10 oracle terms (all points when M is small)
         sel = I.sample_points(coords, max(16384, int(2e10 // Ntot)), seed=37)
@@ -659,7 +676,9 @@ def cpu_baseline(wl, coords, c_np, f_np, plans, outs, cpu_sample):
         parts.append(f"type 2: {len(sel)} points x {Ntot} modes ({dt:.1f} s)")
         cg = outs[2].cpu().numpy()
         cg = cg[0] if ntr > 1 else cg
-        parity["type2_rel_l2"] = O.rel_l2(cg[sel], ref)
+        e, lo, hi = O.rel_l2_interval(cg[sel], ref, seed=2)
+        parity["type2_rel_l2"] = e
+        parity["type2_ci95"] = [lo, hi]
     parity["bar"] = 10 * wl.eps
     value = M * ntr * len(wl.types) / t_full
     return ({"value": value, "unit": "NU pts/s", "cores": threads, "kind": "oracle",

@@ -79,7 +79,7 @@ typedef struct esn_opts {
   double upsampfac;   /* fine grid / modes ratio sigma: 2.0 (eq. (params)) or
                          1.25 (low upsampling: w = ceil(1.7136 log10(1/eps)
                          + 0.6), beta = 1.8397 w; types 1 and 2 only) */
-  int sort;           /* bin-sort the points (Sec. 4.1): 1 (default) choose by
+  int sort;           /* bin-sort the points (Sec. 5.1): 1 (default) choose by
                          size; 2 stable radix sort of the point records by cell;
                          3 counting sort by cell (atomic per point, no order
                          inside a cell); 0: keep the caller's order */
@@ -88,7 +88,7 @@ typedef struct esn_opts {
   int interp_method;  /* 0 auto; 1 LDS tile per subproblem; 2 direct gather;
                          3 matrix cores (3D, single precision, w <= 7) */
   int bin[3];         /* bin size in fine-grid cells per dim; 0 = default */
-  int maxsubprob;     /* max points per subproblem (Sec. 4.2); 0 = default
+  int maxsubprob;     /* max points per subproblem (Sec. 5.2); 0 = default
                          (on the matrix cores 1024 for type 1 and 512 for
                          type 2, 1024 otherwise) */
   int ntransf_chunk;  /* transforms per fused launch; 0 = as many as fit */
@@ -96,7 +96,7 @@ typedef struct esn_opts {
   int kerevalmeth;    /* kernel evaluation: 0 auto (the table in double
                          precision, exp and sqrt in single); 1 exp and sqrt
                          at every weight (eq. (ES)); 2 piecewise polynomial
-                         table (Sec. 4.3, esn_kernel_poly) */
+                         table (Sec. 5.3, esn_kernel_poly) */
 } esn_opts;
 
 /* Fill *o with the defaults (debug 0, chkbnds 1, modeord 0, upsampfac 2.0,
@@ -134,7 +134,7 @@ int esn_gauss_legendre(int p, double* nodes, double* weights);
 int esn_correction_factors(int w, double beta, int nquad, int64_t nf, int64_t N, double* out);
 
 /* Piecewise polynomial form of the kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1))
- * (Sec. 4.3): w equal intervals of [-1, 1], one per window cell, each a
+ * (Sec. 5.3): w equal intervals of [-1, 1], one per window cell, each a
  * polynomial of degree w + 3 in a local t in [-1, 1], with
  * z = (k + (t + 1) / 2 - w / 2) (2 / w) on interval k.  coeffs: host array of
  * w (w + 4) doubles, coefficient of t^j on interval k at coeffs[k (w + 4) + j]
@@ -160,8 +160,8 @@ int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntrans
 /* Give the plan M >= 0 points (coordinate arrays x[, y[, z]] of M values,
  * float if coord_prec == ESN_SINGLE else double; unused dims may be NULL).
  * Folds each coordinate into [0, 2pi) and rescales it to fine-grid units in
- * FP64, bin-sorts the points (Sec. 4.1) and builds the subproblem list
- * (Sec. 4.2).  Synchronises the stream (it reads back the subproblem count
+ * FP64, bin-sorts the points (Sec. 5.1) and builds the subproblem list
+ * (Sec. 5.2).  Synchronises the stream (it reads back the subproblem count
  * and the bounds/NaN flags).  On ESN_ERR_NAN_PTS or (with chkbnds)
  * ESN_ERR_PTS_OUT_OF_RANGE the plan is left without points, so a following
  * esn_execute returns ESN_ERR_NO_POINTS until a successful esn_setpts. */
@@ -247,6 +247,22 @@ typedef struct esn_stats {
  * time a loop of calls without a synchronisation in it. */
 int esn_get_stats_history(esn_plan p, esn_stats* out, int max, int* count);
 
+/* Debug view of the bin sort (Sec. 5.1) and the subproblems (Sec. 5.2) of
+ * the plan's current points (types 1 and 2), for tests of the sort's
+ * invariants.  geom (host, 5 values) gets {M, number of bins, cells per bin,
+ * number of subproblems, sort method (0 none, 2 radix, 3 counting)}; with
+ * every array NULL only geom is filled.  Otherwise each non-NULL host array
+ * is filled:
+ *   perm[M]           original index of the i-th sorted point;
+ *   key[M]            its cell key, bin * cells_per_bin + index of the cell in
+ *                     the bin (window cells, see esn_setpts);
+ *   bin_start[nbins+1] first sorted position of every bin, bin_start[nbins] = M;
+ *   sub[3 * nsub]     subproblems {bin, first sorted position, length}.
+ * bin_start and sub need a sorted plan (BAD_ARG otherwise).  Allocates
+ * temporary device memory and synchronises the plan's stream. */
+int esn_debug_sort(esn_plan p, int64_t* geom, int32_t* perm, uint32_t* key, int32_t* bin_start,
+                   int32_t* sub);
+
 /* Copy the plan's GPU-computed correction factors of dimension m (0-based,
  * floor(N_m/2) + 1 doubles) into the host array out of length len.
  * Synchronises the plan's stream. */
@@ -314,7 +330,8 @@ int esn_toeplitz_destroy(esn_toeplitz t);
  * prec); a cached plan remembers the points_id it last sorted, and a request
  * naming the same nonzero points_id (the caller promises the same points)
  * skips setpts.  Data pointers are device pointers that must stay valid until
- * esn_server_wait returns for the ticket.  Kernels of concurrent requests
+ * esn_server_wait returns for the ticket; once it has returned, the outputs
+ * are complete on the device.  Kernels of concurrent requests
  * overlap on the device; results do not depend on what else is running. */
 typedef struct esn_request {
   int type;                /* 1 or 2 */
@@ -331,6 +348,11 @@ typedef struct esn_request {
   void* c;                 /* [M] strengths (type 1 input, type 2 output) */
   void* f;                 /* [N3][N2][N1] modes (type 1 output, type 2 input) */
   long long points_id;     /* 0, or an id shared by requests with identical points */
+  void* stream;            /* hipStream_t that wrote the inputs (x, y, z, and c for
+                              type 1 or f for type 2), or NULL for the null stream:
+                              submit records an event on it and the request's work
+                              waits for that event, so inputs still being written
+                              by work queued there are complete before they are read */
 } esn_request;
 
 typedef struct esn_serve_stats {

@@ -151,3 +151,19 @@ def rel_l2(approx, exact) -> float:
     a = np.asarray(approx, dtype=np.complex128).reshape(-1)
     e = np.asarray(exact, dtype=np.complex128).reshape(-1)
     return float(np.linalg.norm(a - e) / np.linalg.norm(e))
+
+
+def rel_l2_interval(approx, exact, nboot: int = 1000, seed: int = 0, level: float = 0.95):
+    """Relative l2 error on a sample of outputs with a bootstrap interval: the
+    sampled outputs are resampled with replacement nboot times and the error
+    recomputed; returns (error, low, high) with [low, high] the central
+    `level` range of the resampled errors."""
+    a = np.asarray(approx, dtype=np.complex128).reshape(-1)
+    e = np.asarray(exact, dtype=np.complex128).reshape(-1)
+    d2 = np.abs(a - e) ** 2
+    e2 = np.abs(e) ** 2
+    g = np.random.default_rng(seed)
+    idx = g.integers(0, a.size, size=(nboot, a.size))
+    errs = np.sqrt(d2[idx].sum(axis=1) / e2[idx].sum(axis=1))
+    lo, hi = np.quantile(errs, [(1 - level) / 2, (1 + level) / 2])
+    return float(np.sqrt(d2.sum() / e2.sum())), float(lo), float(hi)

@@ -64,7 +64,7 @@ class EsnStats(ctypes.Structure):
 class EsnRequest(ctypes.Structure):
     _fields_ = [("type", ci), ("dim", ci), ("nmodes", i64 * 3), ("isign", ci), ("eps", cd),
                 ("prec", ci), ("M", i64), ("coord_prec", ci), ("x", vp), ("y", vp), ("z", vp),
-                ("c", vp), ("f", vp), ("points_id", ctypes.c_longlong)]
+                ("c", vp), ("f", vp), ("points_id", ctypes.c_longlong), ("stream", vp)]
 
 
 class EsnServeStats(ctypes.Structure):
@@ -116,6 +116,7 @@ _SIGS = {
     "esn_get_stats_history": ([vp, ctypes.POINTER(EsnStats), ci, ctypes.POINTER(ci)], ci),
     "esn_toeplitz_destroy": ([vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
+    "esn_debug_sort": ([vp, vp, vp, vp, vp, vp], ci),
     "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
     "esn_server_submit": ([vp, ctypes.POINTER(EsnRequest), ctypes.POINTER(ctypes.c_longlong)], ci),
     "esn_server_wait": ([vp, ctypes.c_longlong, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
@@ -247,7 +248,7 @@ def esn_correction_factors(w, beta, nquad, nf, N):
 
 
 def esn_kernel_poly(w, beta):
-    """Piecewise polynomial kernel table (Sec. 4.3): array [w, w + 4], row k the
+    """Piecewise polynomial kernel table (Sec. 5.3): array [w, w + 4], row k the
     monomial coefficients (t^0 first) of interval k's polynomial in t in [-1, 1]."""
     import numpy as np
     out = np.zeros((int(w), int(w) + 4))
@@ -260,6 +261,31 @@ def esn_plan_correction(plan, m, N_m):
     out = np.zeros(int(N_m) // 2 + 1)
     check(lib().esn_plan_correction(plan, int(m), out.ctypes.data, out.shape[0]),
           "esn_plan_correction")
+    return out
+
+
+def esn_debug_sort(plan):
+    """The plan's bin sort as host numpy arrays: dict with M, nbins,
+    cells_per_bin, nsub, method, perm[M], key[M], bin_start[nbins + 1] and
+    sub[nsub, 3] ({bin, first position, length}); bin_start and sub only for
+    sorted plans."""
+    import numpy as np
+    geom = np.zeros(5, dtype=np.int64)
+    check(lib().esn_debug_sort(plan, vp(geom.ctypes.data), None, None, None, None),
+          "esn_debug_sort")
+    M, nbins, cpb, nsub, method = (int(v) for v in geom)
+    out = dict(M=M, nbins=nbins, cells_per_bin=cpb, nsub=nsub, method=method)
+    perm = np.zeros(max(M, 0), dtype=np.int32)
+    key = np.zeros(max(M, 0), dtype=np.uint32)
+    ptr = lambda a: vp(a.ctypes.data) if a.size else None
+    bstart = sub = None
+    if method:
+        bstart = np.zeros(nbins + 1, dtype=np.int32)
+        sub = np.zeros((nsub, 3), dtype=np.int32)
+    check(lib().esn_debug_sort(plan, vp(geom.ctypes.data), ptr(perm), ptr(key),
+                               ptr(bstart) if bstart is not None else None,
+                               ptr(sub) if sub is not None else None), "esn_debug_sort")
+    out.update(perm=perm, key=key, bin_start=bstart, sub=sub)
     return out
 
 
@@ -358,6 +384,10 @@ class Plan:
     def stats_history(self, max_entries=256):
         """Stage times of the latest setpts / execute calls, oldest first (debug plans)."""
         return esn_get_stats_history(self.handle, max_entries)
+
+    def debug_sort(self):
+        """The bin sort of the current points (see esn_debug_sort)."""
+        return esn_debug_sort(self.handle)
 
     def setpts(self, *coords):
         torch = self.torch
@@ -711,6 +741,8 @@ class Server:
         r.c = c.data_ptr() if r.M else None
         r.f = f.data_ptr()
         r.points_id = int(points_id)
+        # the request waits for the work queued so far on torch's current stream
+        r.stream = _stream_handle(torch)
         st, t = esn_server_submit(self.handle, r)
         check(st, "esn_server_submit")
         self._keep[t] = (coords, c, f)

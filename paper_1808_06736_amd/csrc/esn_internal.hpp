@@ -47,7 +47,7 @@ struct TimingRec {
 };
 constexpr int kTimingRing = 256;
 
-// Piecewise polynomial kernel (Sec. 4.3): degree w + kPolyExtra per interval.
+// Piecewise polynomial kernel (Sec. 5.3): degree w + kPolyExtra per interval.
 constexpr int kPolyExtra = 3;
 
 struct GeomArgs {
@@ -99,31 +99,53 @@ struct SortArgs {
   int coord_prec;           // ESN_SINGLE / ESN_DOUBLE
   const void* x[3];         // caller's coordinates
   int64_t n[3];
+  double inv_n[3];          // 1 / n
+  double scale[3];          // n / 2pi
+  double span[3], pow2f[3]; // n 2^fbits and 2^fbits (fixed-point coordinates)
   int b[3], nb[3], fbits[3];
+  int bpow2;                // every b[m] is 2^bshift[m]
+  int bshift[3];
   int pts_code;
   int chkbnds;
   int w;                    // kernel width (decides each point's window cell)
   int blocked;              // 3D cell order by 2 x 2 column blocks (even b[0], b[1])
-  uint32_t* key;            // [M] cell key of each point
+  uint32_t* key;            // [M] cell key of each point (counting sort)
   int32_t* slot;            // [M] rank of the point within its cell (counting sort)
   int32_t* count;           // [ncells + 1] points per cell (counting sort)
   const int32_t* sstart;    // [ncells + 1] first sorted position of a cell (counting sort)
-  unsigned char* pts;       // [M] point records (radix sort: input order; counting
-                            // sort: sorted; no sort: input order)
+  unsigned char* pts;       // [M] point records (counting sort: sorted; no sort:
+                            // input order)
   int32_t* flags;           // [1]: bit0 NaN/inf, bit1 out of range
-  int vec4;                 // coordinate arrays aligned for 4-point vector loads
 };
-// Cell key and point record of every point, in input order.
-hipError_t launch_sort_keys(const SortArgs& a, hipStream_t s);
 // Point records written unsorted (no binning).
 hipError_t launch_encode_unsorted(const SortArgs& a, hipStream_t s);
-// Stable sort of the M point records (rec_bytes 16 or 32) by the low key_bits
-// bits of their keys.  Keys and records are in key[0], rec[0] on entry and in
-// key[sel], rec[sel] on return (sel in {0, 1}); tmp holds
-// sort_tmp_bytes(M, key_bits, rec_bytes) bytes.
-size_t sort_tmp_bytes(int64_t M, int key_bits, int rec_bytes);
-hipError_t sort_records(uint32_t* key[2], unsigned char* rec[2], int* sel, int64_t M,
-                        int key_bits, int rec_bytes, void* tmp, size_t tmp_bytes, hipStream_t s);
+// Radix sort (large point sets): least-significant digit first, digits of
+// dbits <= kRsMaxDigitBits bits, passes <= kRsMaxPasses.
+constexpr int kRsMaxDigitBits = 8;
+constexpr int kRsMaxPasses = 4;
+struct RsortArgs {
+  int passes = 0, dbits = 0, ntiles = 0;
+  int64_t tp = 0;               // points per tile
+  int vec4 = 0;                 // coordinate arrays aligned for 4-point vector loads
+  int32_t* count = nullptr;     // [2^dbits][ntiles] digit counts per tile
+  int32_t* offset = nullptr;    // [2^dbits][ntiles] their exclusive scan
+};
+// Passes of a key of key_bits bits (*dbits: bits per digit).
+int radix_digits(int key_bits, int* dbits);
+// Points per tile of a pass.
+int64_t radix_tile_points(int rec_bytes);
+// Scratch bytes of radix_sort_points for M points.
+size_t radix_scratch_bytes(int64_t M, int key_bits, int rec_bytes);
+// Stable sort of the points of a (a.M, a.x; coordinate checks into
+// a.flags[0]) by key (keys below 2^key_bits): records in key order into
+// out_rec (M records), the sorted keys into scratch (*sorted_keys).
+hipError_t radix_sort_points(const SortArgs& a, int key_bits, unsigned char* out_rec,
+                             void* scratch, size_t scratch_bytes, uint32_t** sorted_keys,
+                             hipStream_t s);
+// key[i] and perm[i] of every stored record pts[i], i < a.M (a.dim, a.n, a.b,
+// a.nb, a.fbits, a.pts_code, a.w, a.blocked set).
+hipError_t launch_record_keys(const SortArgs& a, const unsigned char* pts, uint32_t* key,
+                              int32_t* perm, hipStream_t s);
 // Counting sort: count each point into its cell (the count before the
 // increment is its slot), then, after an exclusive scan of the counts, store
 // its record at start[cell] + slot.
@@ -240,6 +262,11 @@ int make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntransf, 
               int prec, esn_plan* out, const esn_opts* opts, void* stream, bool spread_only);
 // Stage times of a debug plan's latest setpts and execute (waits for them).
 int plan_stats(esn_plan p, esn_stats* o);
+// setpts behind esn_setpts (ext_scratch null) and esn_setpts_noalloc
+// (ext_scratch: the sort's scratch of ext_bytes bytes; radix sort, no
+// allocation, the plan must already hold room for M points).
+int setpts_impl(esn_plan p, int64_t M, int coord_prec, const void* const* xs, void* ext_scratch,
+                size_t ext_bytes);
 // Type 3 plans (type3.cpp).
 int t3_makeplan(int dim, int isign, int ntransf, double eps, int prec, esn_plan* out,
                 const esn_opts* opts, void* stream);
@@ -384,13 +411,11 @@ struct esn_plan_s {
   int64_t M = -1;                // -1: no points yet
   int64_t cap_M = 0;
   unsigned char* d_pts = nullptr;   // [M] sorted point records
-  uint32_t* d_key[2] = {nullptr, nullptr};   // [M] cell keys (sort double buffer)
-  unsigned char* d_rec0 = nullptr;           // [M] point records (sort double buffer with d_pts)
-  void* d_sort_tmp = nullptr;
-  size_t sort_tmp = 0;
+  uint32_t* d_ckey = nullptr;    // [M] cell keys (counting sort)
+  void* d_rscratch = nullptr;    // radix sort scratch (radix_scratch_bytes(cap_M))
+  size_t rscratch_bytes = 0;
   int key_bits = 0;              // bits of the largest cell key
   int64_t ncells = 0;            // bins * cells per bin
-  int64_t cap_radix = 0;         // points the radix sort buffers hold
   int64_t cap_count = 0;         // points the counting sort buffers hold
   int32_t* d_slot = nullptr;     // [M] counting sort: slot within the cell
   int32_t* d_count = nullptr;    // [ncells + 1] counting sort: points per cell

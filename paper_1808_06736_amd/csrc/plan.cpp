@@ -112,12 +112,11 @@ GeomArgs make_geom(const esn_plan_s* p, int ntr) {
 
 void free_points(esn_plan_s* p) {
   dfree(p, (void**)&p->d_pts);
-  dfree(p, (void**)&p->d_rec0);
-  for (int k = 0; k < 2; k++) dfree(p, (void**)&p->d_key[k]);
-  dfree(p, &p->d_sort_tmp);
+  dfree(p, (void**)&p->d_ckey);
+  dfree(p, &p->d_rscratch);
   dfree(p, (void**)&p->d_slot);
-  p->sort_tmp = 0;
-  p->cap_M = p->cap_radix = p->cap_count = 0;
+  p->rscratch_bytes = 0;
+  p->cap_M = p->cap_count = 0;
 }
 
 void free_subs(esn_plan_s* p) {
@@ -399,7 +398,7 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   };
 
   // ---- kernel evaluation: exp and sqrt at every weight, or the piecewise
-  // polynomial table of Sec. 4.3.  Automatic: the table in double precision,
+  // polynomial table of Sec. 5.3.  Automatic: the table in double precision,
   // where exp and sqrt are long FP64 instruction sequences, and exp and sqrt
   // in single precision, where each is one hardware instruction.
   p->kerevalmeth = o.kerevalmeth ? o.kerevalmeth : (prec == ESN_DOUBLE ? 2 : 1);
@@ -483,43 +482,96 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   return p->warn;
 }
 
+// Geometry of the plan's bin sort for M points with coordinates xs.
+static SortArgs sort_args(const esn_plan_s* p, int64_t M, int coord_prec, const void* const* xs) {
+  SortArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.dim = p->dim;
+  a.M = M;
+  a.coord_prec = coord_prec;
+  for (int m = 0; m < 3; m++) {
+    a.x[m] = (xs && m < p->dim) ? xs[m] : nullptr;
+    a.n[m] = p->nf[m];
+    a.inv_n[m] = 1.0 / (double)p->nf[m];
+    a.scale[m] = (double)p->nf[m] * 0.15915494309189533577;   // n / 2pi
+    a.span[m] = std::ldexp((double)p->nf[m], p->fbits[m]);
+    a.pow2f[m] = std::ldexp(1.0, p->fbits[m]);
+    a.b[m] = p->bin[m];
+    a.nb[m] = p->nb[m];
+    a.fbits[m] = p->fbits[m];
+  }
+  a.pts_code = p->pts_code;
+  a.chkbnds = p->opts.chkbnds;
+  a.w = p->par.w;
+  a.blocked = p->dim == 3 && p->bin[0] % 2 == 0 && p->bin[1] % 2 == 0;
+  a.bpow2 = 1;
+  for (int m = 0; m < 3; m++) {
+    int sh = 0;
+    while ((1 << sh) < p->bin[m]) sh++;
+    a.bshift[m] = sh;
+    if ((1 << sh) != p->bin[m]) a.bpow2 = 0;
+  }
+  return a;
+}
+
 extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
                           const void* z) {
+  const void* xs[3] = {x, y, z};
+  return esn::setpts_impl(p, M, coord_prec, xs, nullptr, 0);
+}
+
+// setpts; with ext_scratch set, the sort's scratch is ext_scratch
+// (ext_bytes bytes), the sort is the radix sort, and nothing is allocated:
+// the plan must already hold room for M points and their subproblems.
+int esn::setpts_impl(esn_plan p, int64_t M, int coord_prec, const void* const* xs,
+                     void* ext_scratch, size_t ext_bytes) {
   if (!p || p->type == 3 || M < 0 || M > kMaxPoints) return ESN_ERR_BAD_ARG;
   if (coord_prec != ESN_SINGLE && coord_prec != ESN_DOUBLE) return ESN_ERR_BAD_ARG;
-  const void* xs[3] = {x, y, z};
   if (M > 0)
     for (int m = 0; m < p->dim; m++)
       if (!xs[m]) return ESN_ERR_BAD_ARG;
+  const bool noalloc = ext_scratch != nullptr;
+  // bin sort method: the radix sort's fixed cost dominates for small point
+  // sets, the counting sort's scattered atomics for large ones
+  int method = 0;
+  if (noalloc)
+    method = p->opts.sort ? 2 : 0;
+  else if (p->opts.sort == 1)
+    method = (M < ((int64_t)1 << 21) && p->ncells < ((int64_t)1 << 23)) ? 3 : 2;
+  else if (p->opts.sort >= 2)
+    method = p->opts.sort;
+  const size_t rbytes = (size_t)pts_record_bytes(p->pts_code);
+  void* scratch = p->d_rscratch;
+  size_t scratch_bytes = p->rscratch_bytes;
+  if (noalloc) {
+    if (M > p->cap_M) return ESN_ERR_BAD_ARG;
+    if (method && std::min<int64_t>(p->nbins, M) + M / p->maxsub + 1 > p->cap_sub)
+      return ESN_ERR_BAD_ARG;
+    if (method == 2 && radix_scratch_bytes(M, p->key_bits, (int)rbytes) > ext_bytes)
+      return ESN_ERR_BAD_ARG;
+    scratch = ext_scratch;
+    scratch_bytes = ext_bytes;
+  }
   ESN_HIP(hipSetDevice(p->device));
   hipStream_t s = p->stream;
   p->M = -1;
   TimingRec* tr = timing_next(p, 1);
   if (tr) ESN_HIP(hipEventRecord(tr->e[0], s));
-  // bin sort method: the radix sort's fixed cost dominates for small point
-  // sets, the counting sort's scattered atomics for large ones
-  int method = 0;
-  if (p->opts.sort == 1)
-    method = (M < ((int64_t)1 << 21) && p->ncells < ((int64_t)1 << 23)) ? 3 : 2;
-  else if (p->opts.sort >= 2)
-    method = p->opts.sort;
-  const size_t rbytes = (size_t)pts_record_bytes(p->pts_code);
   if (M > p->cap_M) {
     free_points(p);
-    if (dalloc(p, (void**)&p->d_pts, rbytes * M) || dalloc(p, (void**)&p->d_key[0], 4 * M))
-      return ESN_ERR_ALLOC;
+    if (dalloc(p, (void**)&p->d_pts, rbytes * M)) return ESN_ERR_ALLOC;
     p->cap_M = M;
   }
-  if (method == 2 && M > p->cap_radix) {
-    dfree(p, (void**)&p->d_rec0);
-    dfree(p, (void**)&p->d_key[1]);
-    dfree(p, &p->d_sort_tmp);
-    p->sort_tmp = sort_tmp_bytes(p->cap_M, p->key_bits, (int)rbytes);
-    if (dalloc(p, (void**)&p->d_rec0, rbytes * p->cap_M) ||
-        dalloc(p, (void**)&p->d_key[1], 4 * p->cap_M) ||
-        dalloc(p, &p->d_sort_tmp, std::max<size_t>(p->sort_tmp, 256)))
-      return ESN_ERR_ALLOC;
-    p->cap_radix = p->cap_M;
+  if (method == 2 && !noalloc) {
+    const size_t need = radix_scratch_bytes(p->cap_M, p->key_bits, (int)rbytes);
+    if (need > p->rscratch_bytes) {
+      dfree(p, &p->d_rscratch);
+      p->rscratch_bytes = 0;
+      if (dalloc(p, &p->d_rscratch, need)) return ESN_ERR_ALLOC;
+      p->rscratch_bytes = need;
+    }
+    scratch = p->d_rscratch;
+    scratch_bytes = p->rscratch_bytes;
   }
   if (method == 3) {
     if (!p->d_count) {
@@ -530,39 +582,19 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
     }
     if (M > p->cap_count) {
       dfree(p, (void**)&p->d_slot);
-      if (dalloc(p, (void**)&p->d_slot, 4 * p->cap_M)) return ESN_ERR_ALLOC;
+      dfree(p, (void**)&p->d_ckey);
+      if (dalloc(p, (void**)&p->d_slot, 4 * p->cap_M) || dalloc(p, (void**)&p->d_ckey, 4 * p->cap_M))
+        return ESN_ERR_ALLOC;
       p->cap_count = p->cap_M;
     }
   }
-  SortArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.dim = p->dim;
-  a.M = M;
-  a.coord_prec = coord_prec;
-  for (int m = 0; m < 3; m++) {
-    a.x[m] = m < p->dim ? xs[m] : nullptr;
-    a.n[m] = p->nf[m];
-    a.b[m] = p->bin[m];
-    a.nb[m] = p->nb[m];
-    a.fbits[m] = p->fbits[m];
-  }
-  a.pts_code = p->pts_code;
-  a.chkbnds = p->opts.chkbnds;
-  a.w = p->par.w;
-  a.blocked = p->dim == 3 && p->bin[0] % 2 == 0 && p->bin[1] % 2 == 0;
-  a.key = p->d_key[0];
+  SortArgs a = sort_args(p, M, coord_prec, xs);
+  a.key = p->d_ckey;
   a.slot = p->d_slot;
   a.count = p->d_count;
   a.sstart = p->d_sstart;
-  a.pts = method == 2 ? p->d_rec0 : p->d_pts;
+  a.pts = p->d_pts;
   a.flags = p->d_flags;
-  {
-    // 4-point vector loads need every coordinate array aligned to 4 values
-    const uintptr_t al = coord_prec == ESN_SINGLE ? 16 : 32;
-    a.vec4 = 1;
-    for (int m = 0; m < p->dim; m++)
-      if (reinterpret_cast<uintptr_t>(xs[m]) % al) a.vec4 = 0;
-  }
   ESN_HIP(hipMemsetAsync(p->d_flags, 0, 16, s));
   int nsub = 0;
   const int64_t cpb = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
@@ -581,15 +613,9 @@ extern "C" int esn_setpts(esn_plan p, int64_t M, int coord_prec, const void* x, 
   }
   if (method == 2) {
     ESN_HIP(hipMemsetAsync(p->d_bend, 0, 4 * p->nbins, s));
-    ESN_HIP(launch_sort_keys(a, s));
-    int sel = 0;
-    unsigned char* recs[2] = {p->d_rec0, p->d_pts};
-    ESN_HIP(sort_records(p->d_key, recs, &sel, M, p->key_bits, (int)rbytes, p->d_sort_tmp,
-                         p->sort_tmp, s));
-    // the sorted records are the plan's points; the other buffer is scratch
-    p->d_pts = recs[sel];
-    p->d_rec0 = recs[1 - sel];
-    ESN_HIP(launch_bin_ends(p->d_key[sel], M, (int)cpb, p->d_bend, s));
+    uint32_t* skey = nullptr;
+    ESN_HIP(radix_sort_points(a, p->key_bits, p->d_pts, scratch, scratch_bytes, &skey, s));
+    ESN_HIP(launch_bin_ends(skey, M, (int)cpb, p->d_bend, s));
     ESN_HIP(launch_bin_subproblems(p->d_bend, p->d_bstart, p->nbins, M, p->maxsub, p->d_nsub,
                                    p->d_tiles, p->d_sub_bin, p->d_sub_start, p->d_sub_len,
                                    p->d_flags + 1, s));
@@ -853,6 +879,57 @@ extern "C" int esn_get_info(esn_plan p, esn_info* o) {
   return ESN_OK;
 }
 
+extern "C" int esn_debug_sort(esn_plan p, int64_t* geom, int32_t* perm, uint32_t* key,
+                              int32_t* bin_start, int32_t* sub) {
+  if (!p || !geom || p->type == 3) return ESN_ERR_BAD_ARG;
+  geom[0] = p->M;
+  geom[1] = p->nbins;
+  geom[2] = (int64_t)p->bin[0] * p->bin[1] * p->bin[2];
+  geom[3] = p->nsub;
+  geom[4] = p->last_sort;
+  if (!perm && !key && !bin_start && !sub) return ESN_OK;
+  if (p->M < 0) return ESN_ERR_NO_POINTS;
+  if (p->last_sort == 0 && (bin_start || sub)) return ESN_ERR_BAD_ARG;
+  ESN_HIP(hipSetDevice(p->device));
+  hipStream_t s = p->stream;
+  const int64_t M = p->M;
+  if ((perm || key) && M > 0) {
+    uint32_t* d_key = nullptr;
+    int32_t* d_perm = nullptr;
+    if (hipMalloc((void**)&d_key, 4 * M) != hipSuccess) return ESN_ERR_ALLOC;
+    if (hipMalloc((void**)&d_perm, 4 * M) != hipSuccess) {
+      (void)hipFree(d_key);
+      return ESN_ERR_ALLOC;
+    }
+    const SortArgs a = sort_args(p, M, ESN_SINGLE, nullptr);
+    int rc = ESN_OK;
+    if (launch_record_keys(a, p->d_pts, d_key, d_perm, s) != hipSuccess ||
+        (key && hipMemcpyAsync(key, d_key, 4 * M, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        (perm && hipMemcpyAsync(perm, d_perm, 4 * M, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = ESN_ERR_HIP;
+    (void)hipFree(d_key);
+    (void)hipFree(d_perm);
+    if (rc != ESN_OK) return rc;
+  }
+  if (bin_start)
+    ESN_HIP(hipMemcpyAsync(bin_start, p->d_bstart, 4 * (p->nbins + 1), hipMemcpyDeviceToHost, s));
+  if (sub && p->nsub > 0) {
+    std::vector<int32_t> b(p->nsub), st(p->nsub), ln(p->nsub);
+    ESN_HIP(hipMemcpyAsync(b.data(), p->d_sub_bin, 4 * p->nsub, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipMemcpyAsync(st.data(), p->d_sub_start, 4 * p->nsub, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipMemcpyAsync(ln.data(), p->d_sub_len, 4 * p->nsub, hipMemcpyDeviceToHost, s));
+    ESN_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < p->nsub; i++) {
+      sub[3 * i] = b[i];
+      sub[3 * i + 1] = st[i];
+      sub[3 * i + 2] = ln[i];
+    }
+  }
+  ESN_HIP(hipStreamSynchronize(s));
+  return ESN_OK;
+}
+
 extern "C" int esn_plan_correction(esn_plan p, int m, double* out, int64_t len) {
   if (!p || !out || m < 0 || m >= p->dim || len != p->N[m] / 2 + 1) return ESN_ERR_BAD_ARG;
   ESN_HIP(hipSetDevice(p->device));
@@ -937,7 +1014,7 @@ int64_t plan_estimate_bytes(int type, int dim, const int64_t* nmodes, double eps
   (void)type;
   return 2 * grid                 // fine grid + rocFFT work buffer
          + 8 * (cells + 1)        // bin counts and starts (at most one bin per cell)
-         + M * (2 * rec + 8)      // record and key double buffers of the sort
+         + M * (2 * rec + 8)      // sorted records, the sort's second record buffer and keys
          + (int64_t)(M / 256 + 1024) * 12   // subproblem lists
          + (1 << 20);             // factors, flags, small buffers
 }

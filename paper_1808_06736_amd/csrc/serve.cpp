@@ -4,7 +4,10 @@
 // queue.  A request is admitted when a worker is free and its device memory
 // fits the HBM budget (idle cached plans are evicted, least recently used
 // first, to make room), so requests arriving while others run start as soon as
-// a worker and memory free up, and their kernels overlap on the device.  Plans
+// a worker and memory free up, and their kernels overlap on the device.  While
+// the head of the queue waits for memory, a later request that fits may start
+// first (a bounded number of times).  A request's work waits for an event
+// recorded at submit on the stream that wrote its inputs.  Plans
 // are cached by problem shape (type, dim, modes, sign, tolerance, precision);
 // a cached plan remembers the point set it last sorted, so a request that
 // names the same points id skips setpts.  Latency is measured from submit to
@@ -27,8 +30,15 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// A request waiting for memory at the head of the queue lets requests among
+// the next kBypassWindow start if they fit, at most kMaxBypass times.
+constexpr size_t kBypassWindow = 8;
+constexpr int kMaxBypass = 16;
+
 struct Req {
   esn_request r;
+  int bypassed = 0;            // times a later request started first
+  hipEvent_t ready = nullptr;  // recorded at submit on the stream that wrote the inputs
   long long ticket = 0;
   Clock::time_point t_submit, t_done;
   int status = ESN_OK;
@@ -111,6 +121,10 @@ CachedPlan* find_plan(esn_server_s* sv, const std::string& key, long long points
 }
 
 void finish(esn_server_s* sv, const std::shared_ptr<Req>& q, int status) {
+  if (q->ready) {
+    (void)hipEventDestroy(q->ready);
+    q->ready = nullptr;
+  }
   q->status = status;
   q->t_done = Clock::now();
   q->done = true;
@@ -130,7 +144,9 @@ void worker_loop(esn_server_s* sv, int slot) {
   hipStream_t stream = sv->streams[slot];
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
-    // wait for an admissible head of the queue
+    // wait for an admissible request: the head of the queue, or, while the
+    // head waits for memory, one of the next kBypassWindow requests (the head
+    // may be passed kMaxBypass times before everything waits for it)
     std::shared_ptr<Req> q;
     CachedPlan* cp = nullptr;
     int64_t reserved = 0;
@@ -147,36 +163,34 @@ void worker_loop(esn_server_s* sv, int slot) {
         sv->cv_done.notify_all();
         continue;
       }
-      CachedPlan* c = find_plan(sv, head->key, head->r.points_id);
-      if (c) {
+      const size_t window =
+          head->bypassed < kMaxBypass ? std::min(sv->queue.size(), kBypassWindow) : 1;
+      for (size_t i = 0; i < window && !q; i++) {
+        std::shared_ptr<Req> cand = sv->queue[i];
+        if (cand->est > sv->budget) continue;       // failed when it reaches the head
+        CachedPlan* c = find_plan(sv, cand->key, cand->r.points_id);
         // a cached plan's memory is already counted; it may grow with M
-        const int64_t grow = std::max<int64_t>(0, head->est - c->bytes);
-        evict_for(sv, grow, head->key);
-        if (sv->in_use + grow <= sv->budget || sv->running == 0) {
-          sv->queue.pop_front();
-          c->busy = true;
-          c->last_use = ++sv->use_clock;
-          cp = c;
-          reserved = grow;
-          sv->in_use += grow;
-          q = head;
-          break;
+        const int64_t need = c ? std::max<int64_t>(0, cand->est - c->bytes) : cand->est;
+        evict_for(sv, need, cand->key);
+        if (sv->in_use + need <= sv->budget || (c && sv->running == 0)) {
+          sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)i);
+          if (i > 0) head->bypassed++;
+          if (c) {
+            c->busy = true;
+            c->last_use = ++sv->use_clock;
+            cp = c;
+          }
+          reserved = need;
+          sv->in_use += need;
+          q = cand;
         }
-      } else {
-        evict_for(sv, head->est, head->key);
-        if (sv->in_use + head->est <= sv->budget) {
-          sv->queue.pop_front();
-          reserved = head->est;
-          sv->in_use += head->est;
-          q = head;
-          break;
-        }
-        if (sv->running == 0) {                     // nothing will free memory
-          sv->queue.pop_front();
-          finish(sv, head, ESN_ERR_BUDGET);
-          sv->cv_done.notify_all();
-          continue;
-        }
+      }
+      if (q) break;
+      if (sv->running == 0) {                       // nothing will free memory
+        sv->queue.pop_front();
+        finish(sv, head, ESN_ERR_BUDGET);
+        sv->cv_done.notify_all();
+        continue;
       }
       sv->cv_work.wait(lk);                         // wait for memory to free up
     }
@@ -199,10 +213,13 @@ void worker_loop(esn_server_s* sv, int slot) {
       st = esn::plan_set_stream(plan, stream);
     }
     int warn = st == ESN_WARN_EPS_TOO_SMALL ? st : ESN_OK;
+    // inputs written on the caller's stream are complete before they are read
+    if (st < 2 && q->ready && hipStreamWaitEvent(stream, q->ready, 0) != hipSuccess)
+      st = ESN_ERR_HIP;
     if (st < 2 && !same_points)
       st = esn_setpts(plan, q->r.M, q->r.coord_prec, q->r.x, q->r.y, q->r.z);
     if (st < 2) st = esn_execute(plan, q->r.c, q->r.f);
-    if (st < 2 && hipStreamSynchronize(stream) != hipSuccess) st = ESN_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess && st < 2) st = ESN_ERR_HIP;
     if (st < 2 && warn) st = warn;
     esn_info info{};
     if (plan) esn_get_info(plan, &info);
@@ -287,9 +304,18 @@ extern "C" int esn_server_submit(esn_server sv, const esn_request* r, long long*
   q->key = plan_key(q->r);
   q->est = esn::plan_estimate_bytes(r->type, r->dim, q->r.nmodes, r->eps, r->prec, r->M);
   if (q->est < 0) return ESN_ERR_BAD_ARG;
+  (void)hipSetDevice(sv->device);
+  if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess) return ESN_ERR_HIP;
+  if (hipEventRecord(q->ready, static_cast<hipStream_t>(r->stream)) != hipSuccess) {
+    (void)hipEventDestroy(q->ready);
+    return ESN_ERR_HIP;
+  }
   q->t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (sv->stop) return ESN_ERR_QUEUE;
+  if (sv->stop) {
+    (void)hipEventDestroy(q->ready);
+    return ESN_ERR_QUEUE;
+  }
   q->ticket = sv->next_ticket++;
   if (!sv->have_first) {
     sv->t_first = q->t_submit;

@@ -94,3 +94,35 @@ def test_batched_radial_type2():
         c1 = host(single.type2(dev(f[t])))
         assert O.rel_l2(cb[t], c1) < 1e-6
     single.close()
+
+
+def test_headline_step_one_plan_type1_and_adjoint():
+    """The timed step of the headline workload exactly as it runs in the
+    benchmark: one type 1 plan (default options, debug timing on), one setpts,
+    execute (type 1, isign +1) and execute_adjoint (type 2, isign -1) on the
+    same sorted points.  Both outputs meet the bar on the oracle samples; the
+    sampled errors are printed with bootstrap 95% intervals."""
+    wl = I.WORKLOADS["3d_clustered"]
+    coords = wl.coords()
+    c = wl.strengths()
+    f = wl.coefficients()
+    p = _plan(1, wl, debug=1)
+    p.setpts(*[dev(a) for a in coords])
+    f_out = torch().empty(f.shape, dtype=cdtype(wl.prec), device="cuda")
+    c_out = torch().empty(c.shape, dtype=cdtype(wl.prec), device="cuda")
+    p.execute(dev(c), f_out)
+    p.execute_adjoint(c_out, dev(f))
+    torch().cuda.synchronize()
+    info = p.info()
+    f_gpu, c_gpu = host(f_out), host(c_out)
+    p.close()
+    N = wl.N[:wl.dim]
+    modes = [I.sample_modes(n, 12, seed=61 + m) for m, n in enumerate(N)]
+    idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
+    e1 = O.rel_l2_interval(f_gpu[idx], O.type1(coords, c, +1, modes=modes), seed=1)
+    sel = I.sample_points(coords, 1024, seed=63)
+    e2 = O.rel_l2_interval(c_gpu[sel], O.type2([a[sel] for a in coords], f, -1), seed=2)
+    print(f"headline step: type 1 rel l2 {e1[0]:.3e} [{e1[1]:.3e}, {e1[2]:.3e}], adjoint "
+          f"(type 2) rel l2 {e2[0]:.3e} [{e2[1]:.3e}, {e2[2]:.3e}] (methods "
+          f"{info.spread_method}/{info.interp_method}, subproblems {info.nsubprob})")
+    assert e1[0] <= 10 * wl.eps and e2[0] <= 10 * wl.eps

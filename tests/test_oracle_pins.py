@@ -201,3 +201,18 @@ def test_type3_dilation_invariance():
     f = O.type3(x, c, s, 1)
     g = O.type3([x[m] / gam[m] for m in range(3)], c, [s[m] * gam[m] for m in range(3)], 1)
     assert np.max(np.abs(f - g)) < 1e-11 * np.max(np.abs(f))
+
+
+def test_bootstrap_interval_of_the_sampled_error():
+    """rel_l2_interval: exact agreement gives 0 with a zero-width interval; a
+    uniform relative perturbation delta gives delta for every resample; for a
+    random error the interval holds the point estimate."""
+    g = np.random.default_rng(3)
+    e = g.standard_normal(512) + 1j * g.standard_normal(512)
+    assert O.rel_l2_interval(e, e) == (0.0, 0.0, 0.0)
+    err, lo, hi = O.rel_l2_interval(e * (1 + 1e-6), e)
+    assert abs(err - 1e-6) < 1e-12 and abs(lo - 1e-6) < 1e-12 and abs(hi - 1e-6) < 1e-12
+    a = e + 1e-5 * (g.standard_normal(512) + 1j * g.standard_normal(512))
+    err, lo, hi = O.rel_l2_interval(a, e, seed=1)
+    assert lo < err < hi and hi / lo < 1.5
+    assert abs(err - O.rel_l2(a, e)) < 1e-15
