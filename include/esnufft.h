@@ -247,6 +247,22 @@ typedef struct esn_stats {
  * time a loop of calls without a synchronisation in it. */
 int esn_get_stats_history(esn_plan p, esn_stats* out, int max, int* count);
 
+/* esn_setpts for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and result as esn_setpts, with the radix bin sort always
+ * (esn_opts.sort 0 keeps the caller's order as usual).  Allocates nothing:
+ *   - the sort's scratch is one static device array of 128 MiB per GPU, shared
+ *     by every call on that GPU; the call clears what must start at zero, and
+ *     calls that overlap on one GPU (other threads, other streams) race on it;
+ *   - the plan must already hold room for M points: an earlier esn_setpts of
+ *     at least M points on this plan (whose device memory the plan keeps).
+ * Returns ESN_ERR_BAD_ARG when M exceeds that room or the sort's scratch for
+ * M points exceeds the static array (about 5.5e6 points in single precision,
+ * 3.3e6 in double precision), ESN_ERR_HIP if the array's address cannot be
+ * found; otherwise as esn_setpts. */
+int esn_setpts_noalloc(esn_plan p, int64_t M, int coord_prec, const void* x, const void* y,
+                       const void* z);
+
 /* Debug view of the bin sort (Sec. 5.1) and the subproblems (Sec. 5.2) of
  * the plan's current points (types 1 and 2), for tests of the sort's
  * invariants.  geom (host, 5 values) gets {M, number of bins, cells per bin,

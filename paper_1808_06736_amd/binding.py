@@ -117,6 +117,7 @@ _SIGS = {
     "esn_toeplitz_destroy": ([vp], ci),
     "esn_plan_correction": ([vp, ci, vp, i64], ci),
     "esn_debug_sort": ([vp, vp, vp, vp, vp, vp], ci),
+    "esn_setpts_noalloc": ([vp, i64, ci, vp, vp, vp], ci),
     "esn_server_create": ([ctypes.POINTER(EsnOpts), ci, ctypes.c_longlong, ctypes.POINTER(vp)], ci),
     "esn_server_submit": ([vp, ctypes.POINTER(EsnRequest), ctypes.POINTER(ctypes.c_longlong)], ci),
     "esn_server_wait": ([vp, ctypes.c_longlong, ctypes.POINTER(ci), ctypes.POINTER(cd)], ci),
@@ -388,6 +389,29 @@ class Plan:
     def debug_sort(self):
         """The bin sort of the current points (see esn_debug_sort)."""
         return esn_debug_sort(self.handle)
+
+    def setpts_noalloc(self, *coords):
+        """setpts without device allocation (esn_setpts_noalloc): the plan
+        must already hold room for these points (an earlier setpts of at
+        least as many)."""
+        torch = self.torch
+        if len(coords) != self.dim:
+            raise ValueError(f"need {self.dim} coordinate arrays")
+        M = coords[0].numel()
+        cdt = coords[0].dtype
+        if cdt not in (torch.float32, torch.float64):
+            raise ValueError("coordinates must be float32 or float64")
+        ptrs = []
+        for a in coords:
+            if a.dtype != cdt or a.numel() != M or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("coordinates: same dtype, same length, contiguous, on the GPU")
+            ptrs.append(vp(a.data_ptr()) if M > 0 else None)
+        ptrs += [None] * (3 - len(ptrs))
+        st = lib().esn_setpts_noalloc(self.handle, M,
+                                      ESN_SINGLE if cdt == torch.float32 else ESN_DOUBLE, *ptrs)
+        check(st, "esn_setpts_noalloc")
+        self.M = M
+        return self
 
     def setpts(self, *coords):
         torch = self.torch

@@ -31,7 +31,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "type3.cpp", "serve.cpp",
            "kernels_sort.hip", "kernels_deconv.hip", "kernels_spread.hip",
            "kernels_interp.hip", "kernels_mfma.hip", "kernels_type3.hip",
-           "toeplitz.cpp", "kernels_toeplitz.hip", "kernels_fft.hip"]
+           "toeplitz.cpp", "kernels_toeplitz.hip", "kernels_fft.hip", "noalloc.cpp"]
 
 
 # Per-source extra flags (none).  The matrix-core kernels keep their MFMA
