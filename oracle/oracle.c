@@ -24,7 +24,10 @@
  * Threads only split independent work: type 1 splits the points (each thread
  * sums its own points for every requested mode; partial sums are then added in
  * thread order, so results do not depend on scheduling); types 2 and 3 split
- * the outputs.  Type 3 forms each phase s_k.x_j in FP64 and takes its cosine
+ * the outputs.  Every sum is accumulated in blocks of at most ORACLE_BLOCK
+ * terms: a block's terms are summed on their own and the block sums added
+ * to the running total, which keeps the rounding of long sums (up to 1e7
+ * terms) near that of a 4096-term sum plus the number of blocks.  Type 3 forms each phase s_k.x_j in FP64 and takes its cosine
  * and sine directly (the targets are not a grid, so there is no product form).
  */
 #include <math.h>
@@ -32,6 +35,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Terms per block of every accumulation. */
+#define ORACLE_BLOCK 4096
 
 typedef struct {
   int dim;
@@ -57,35 +63,42 @@ static void phases(double x, int isign, int64_t n, const int64_t *k, double *e) 
 static void *type1_worker(void *arg) {
   job_t *jb = (job_t *)arg;
   int64_t n1 = jb->nk[0], n2 = jb->nk[1], n3 = jb->nk[2];
+  int64_t K = n1 * n2 * n3;
   double *e1 = malloc(sizeof(double) * 2 * n1);
   double *e2 = malloc(sizeof(double) * 2 * n2);
   double *e3 = malloc(sizeof(double) * 2 * n3);
-  double *acc = jb->out;
-  for (int64_t j = jb->j0; j < jb->j1; j++) {
-    phases(jb->x[0][j], jb->isign, n1, jb->k[0], e1);
-    if (jb->dim >= 2) phases(jb->x[1][j], jb->isign, n2, jb->k[1], e2);
-    else { e2[0] = 1.0; e2[1] = 0.0; }
-    if (jb->dim >= 3) phases(jb->x[2][j], jb->isign, n3, jb->k[2], e3);
-    else { e3[0] = 1.0; e3[1] = 0.0; }
-    double cr = jb->c[2 * j], ci = jb->c[2 * j + 1];
-    for (int64_t a3 = 0; a3 < n3; a3++) {
-      /* c_j * exp(i k3 z_j) */
-      double u3r = cr * e3[2 * a3] - ci * e3[2 * a3 + 1];
-      double u3i = cr * e3[2 * a3 + 1] + ci * e3[2 * a3];
-      for (int64_t a2 = 0; a2 < n2; a2++) {
-        /* ... * exp(i k2 y_j) */
-        double u2r = u3r * e2[2 * a2] - u3i * e2[2 * a2 + 1];
-        double u2i = u3r * e2[2 * a2 + 1] + u3i * e2[2 * a2];
-        double *row = acc + 2 * n1 * (a2 + n2 * a3);
-        for (int64_t a1 = 0; a1 < n1; a1++) {
-          /* ... * exp(i k1 x_j), accumulated into f_k */
-          row[2 * a1] += u2r * e1[2 * a1] - u2i * e1[2 * a1 + 1];
-          row[2 * a1 + 1] += u2r * e1[2 * a1 + 1] + u2i * e1[2 * a1];
+  double *blk = calloc(2 * K, sizeof(double));   /* sum over the current block of points */
+  double *acc = jb->out;                          /* sum of the finished blocks */
+  for (int64_t b0 = jb->j0; b0 < jb->j1; b0 += ORACLE_BLOCK) {
+    int64_t b1 = b0 + ORACLE_BLOCK < jb->j1 ? b0 + ORACLE_BLOCK : jb->j1;
+    memset(blk, 0, sizeof(double) * 2 * K);
+    for (int64_t j = b0; j < b1; j++) {
+      phases(jb->x[0][j], jb->isign, n1, jb->k[0], e1);
+      if (jb->dim >= 2) phases(jb->x[1][j], jb->isign, n2, jb->k[1], e2);
+      else { e2[0] = 1.0; e2[1] = 0.0; }
+      if (jb->dim >= 3) phases(jb->x[2][j], jb->isign, n3, jb->k[2], e3);
+      else { e3[0] = 1.0; e3[1] = 0.0; }
+      double cr = jb->c[2 * j], ci = jb->c[2 * j + 1];
+      for (int64_t a3 = 0; a3 < n3; a3++) {
+        /* c_j * exp(i k3 z_j) */
+        double u3r = cr * e3[2 * a3] - ci * e3[2 * a3 + 1];
+        double u3i = cr * e3[2 * a3 + 1] + ci * e3[2 * a3];
+        for (int64_t a2 = 0; a2 < n2; a2++) {
+          /* ... * exp(i k2 y_j) */
+          double u2r = u3r * e2[2 * a2] - u3i * e2[2 * a2 + 1];
+          double u2i = u3r * e2[2 * a2 + 1] + u3i * e2[2 * a2];
+          double *row = blk + 2 * n1 * (a2 + n2 * a3);
+          for (int64_t a1 = 0; a1 < n1; a1++) {
+            /* ... * exp(i k1 x_j), accumulated into f_k */
+            row[2 * a1] += u2r * e1[2 * a1] - u2i * e1[2 * a1 + 1];
+            row[2 * a1 + 1] += u2r * e1[2 * a1 + 1] + u2i * e1[2 * a1];
+          }
         }
       }
     }
+    for (int64_t q = 0; q < 2 * K; q++) acc[q] += blk[q];
   }
-  free(e1); free(e2); free(e3);
+  free(e1); free(e2); free(e3); free(blk);
   return NULL;
 }
 
@@ -101,7 +114,9 @@ static void *type2_worker(void *arg) {
     else { e2[0] = 1.0; e2[1] = 0.0; }
     if (jb->dim >= 3) phases(jb->x[2][j], jb->isign, n3, jb->k[2], e3);
     else { e3[0] = 1.0; e3[1] = 0.0; }
-    double sr = 0.0, si = 0.0;
+    double sr = 0.0, si = 0.0;     /* sum of the finished blocks of modes */
+    double br = 0.0, bi = 0.0;     /* sum over the current block */
+    int64_t nb = 0;                /* terms in the current block */
     for (int64_t a3 = 0; a3 < n3; a3++) {
       for (int64_t a2 = 0; a2 < n2; a2++) {
         /* exp(i (k2 y + k3 z)) */
@@ -112,13 +127,18 @@ static void *type2_worker(void *arg) {
           double pr = p23r * e1[2 * a1] - p23i * e1[2 * a1 + 1];
           double pi = p23r * e1[2 * a1 + 1] + p23i * e1[2 * a1];
           double fr = frow[2 * a1], fi = frow[2 * a1 + 1];
-          sr += fr * pr - fi * pi;
-          si += fr * pi + fi * pr;
+          br += fr * pr - fi * pi;
+          bi += fr * pi + fi * pr;
+          if (++nb == ORACLE_BLOCK) {
+            sr += br; si += bi;
+            br = bi = 0.0;
+            nb = 0;
+          }
         }
       }
     }
-    jb->out[2 * j] = sr;
-    jb->out[2 * j + 1] = si;
+    jb->out[2 * j] = sr + br;
+    jb->out[2 * j + 1] = si + bi;
   }
   free(e1); free(e2); free(e3);
   return NULL;
@@ -229,18 +249,23 @@ typedef struct {
 static void *type3_worker(void *arg) {
   job3_t *jb = (job3_t *)arg;
   for (int64_t k = jb->k0; k < jb->k1; k++) {
-    double fr = 0.0, fi = 0.0;
+    double fr = 0.0, fi = 0.0;     /* sum of the finished blocks of sources */
+    double br = 0.0, bi = 0.0;     /* sum over the current block */
     for (int64_t j = 0; j < jb->M; j++) {
       double ph = 0.0;
       for (int m = 0; m < jb->dim; m++) ph += jb->s[m][k] * jb->x[m][j];
       ph *= (double)jb->isign;
       double cr = jb->c[2 * j], ci = jb->c[2 * j + 1];
       double er = cos(ph), ei = sin(ph);
-      fr += cr * er - ci * ei;
-      fi += cr * ei + ci * er;
+      br += cr * er - ci * ei;
+      bi += cr * ei + ci * er;
+      if ((j + 1) % ORACLE_BLOCK == 0) {
+        fr += br; fi += bi;
+        br = bi = 0.0;
+      }
     }
-    jb->f[2 * k] = fr;
-    jb->f[2 * k + 1] = fi;
+    jb->f[2 * k] = fr + br;
+    jb->f[2 * k + 1] = fi + bi;
   }
   return NULL;
 }

@@ -20,12 +20,16 @@ MUTANTS = [
     ("dropped last term", "for (int64_t j = jb->j0; j < jb->j1; j++) {",
      "for (int64_t j = jb->j0; j < jb->j1 - (jb->j1 > jb->j0 + 1); j++) {"),
     ("ignored isign", "double th = (double)isign * (double)k[a] * x;", "double th = (double)k[a] * x;"),
-    ("conjugated product in type 2", "si += fr * pi + fi * pr;", "si += fr * pi - fi * pr;"),
+    ("conjugated product in type 2", "bi += fr * pi + fi * pr;", "bi += fr * pi - fi * pr;"),
+    ("unfinished block left out of a type 2 sum", "jb->out[2 * j] = sr + br;", "jb->out[2 * j] = sr;"),
+    ("block sums of type 1 not added", "for (int64_t q = 0; q < 2 * K; q++) acc[q] += blk[q];",
+     "for (int64_t q = 0; q < 2 * K; q++) acc[q] = blk[q];"),
 ]
 
 PINS = [
-    (P.test_type1_uniform_grid_is_dft, [((7,), 1), ((6, 5), -1), ((4, 7), 1), ((5, 4, 3), 1)]),
-    (P.test_type2_uniform_grid_is_dft, [((9,), 1), ((6, 5), -1), ((4, 3, 5), -1)]),
+    (P.test_type1_uniform_grid_is_dft, [((7,), 1), ((6, 5), -1), ((4, 7), 1), ((5, 4, 3), 1),
+                                        ((5003,), 1)]),
+    (P.test_type2_uniform_grid_is_dft, [((9,), 1), ((6, 5), -1), ((4, 3, 5), -1), ((5003,), -1)]),
     (P.test_adjointness, [(1, (13,), 40), (2, (6, 9), 50), (3, (5, 4, 7), 30)]),
     (P.test_translation_and_period, [(1,), (-1,)]),
     (P.test_type2_single_mode, [()]),

@@ -38,13 +38,17 @@ def _fft_ordered(f_modes, Ns):
     return g
 
 
-@pytest.mark.parametrize("Ns", [(8,), (7,), (6, 5), (4, 7), (5, 4, 3), (2, 3, 4)])
+# (5003,), (70, 65) and (17, 16, 16) hold more than 4096 points and modes, so
+# the oracle's sums run over more than one block of terms
+@pytest.mark.parametrize("Ns", [(8,), (7,), (6, 5), (4, 7), (5, 4, 3), (2, 3, 4), (5003,),
+                                (70, 65), (17, 16, 16)])
 @pytest.mark.parametrize("isign", [1, -1])
 def test_type1_uniform_grid_is_dft(Ns, isign):
     d = len(Ns)
     pts = _grid_points(Ns)
     c = I.complex_normal(tuple(reversed(Ns)), seed=11)
-    f = O.type1(pts, c.reshape(-1), isign, N=Ns)
+    # one thread for the long sums, so that one thread's points span blocks
+    f = O.type1(pts, c.reshape(-1), isign, N=Ns, nthreads=1 if np.prod(Ns) > 4096 else None)
     # sum_j c_j exp(isign 2 pi i k.j/N): numpy's unnormalised inverse (+) or forward (-) FFT
     F = np.fft.ifftn(c) * np.prod(Ns) if isign > 0 else np.fft.fftn(c)
     want = F[np.ix_(*[(I.mode_range(N) % N) for N in reversed(Ns)])]
@@ -52,7 +56,7 @@ def test_type1_uniform_grid_is_dft(Ns, isign):
     assert np.max(np.abs(f - want)) < 1e-11 * np.max(np.abs(want))
 
 
-@pytest.mark.parametrize("Ns", [(9,), (6, 5), (4, 3, 5)])
+@pytest.mark.parametrize("Ns", [(9,), (6, 5), (4, 3, 5), (5003,), (70, 65)])
 @pytest.mark.parametrize("isign", [1, -1])
 def test_type2_uniform_grid_is_dft(Ns, isign):
     pts = _grid_points(Ns)
