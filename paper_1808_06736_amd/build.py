@@ -31,7 +31,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = ["params.cpp", "fft.cpp", "plan.cpp", "type3.cpp", "serve.cpp",
            "kernels_sort.hip", "kernels_deconv.hip", "kernels_spread.hip",
            "kernels_interp.hip", "kernels_mfma.hip", "kernels_type3.hip",
-           "toeplitz.cpp", "kernels_toeplitz.hip", "kernels_fft.hip", "noalloc.cpp"]
+           "toeplitz.cpp", "kernels_toeplitz.hip", "kernels_fft.hip", "noalloc.cpp",
+           "kernels_mfma2d.hip"]
 
 
 # Per-source extra flags (none).  The matrix-core kernels keep their MFMA

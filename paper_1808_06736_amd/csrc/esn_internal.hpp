@@ -109,6 +109,7 @@ struct SortArgs {
   int chkbnds;
   int w;                    // kernel width (decides each point's window cell)
   int blocked;              // 3D cell order by 2 x 2 column blocks (even b[0], b[1])
+  int blocked2d;            // 2D cell order by blocked2d x blocked2d blocks (4 or 8; 0: row-major)
   uint32_t* key;            // [M] cell key of each point (counting sort)
   int32_t* slot;            // [M] rank of the point within its cell (counting sort)
   int32_t* count;           // [ncells + 1] points per cell (counting sort)
@@ -194,6 +195,16 @@ hipError_t launch_interp_mfma(int w, const GeomArgs& g, int nsub, const void* gr
                               hipStream_t s);
 size_t mfma_spread_lds_bytes(int w, const int* b);
 size_t mfma_interp_lds_bytes(const int* b);
+// Matrix-core spreading / interpolation in 2D (kernels_mfma2d.hip): single or
+// double precision, w <= 13, bins of whole 4 x 4 blocks of window cells, g.ntr
+// transforms per launch sharing the staged weights; one wave per subproblem.
+hipError_t launch_spread_mfma2d(int prec, int w, const GeomArgs& g, int nsub, const void* c,
+                                void* grid, hipStream_t s);
+hipError_t launch_interp_mfma2d(int prec, int w, const GeomArgs& g, int nsub, const void* grid,
+                                void* c, hipStream_t s);
+size_t mfma2d_lds_bytes(int prec, int w, const int* b, int ntr, bool spread);
+// Block of window cells of the 2D matrix-core kernels at width w (8 for w <= 9, else 4).
+inline int mfma2d_block(int w) { return w <= 9 ? 8 : 4; }
 
 // LDS bytes one subproblem tile needs for ntr transforms (with the spreading
 // kernel's per-point staging when staging is true).

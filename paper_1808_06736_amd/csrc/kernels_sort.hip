@@ -88,7 +88,8 @@ __device__ __forceinline__ double load_coord(const void* p, int64_t j) {
 // bin are ordered by z within each (x, y) column; with a.blocked the columns
 // come in 2 x 2 blocks and a block's four columns are merged in z order (cell
 // (lx, ly, lz) at 4 (lz + b2 (block)) + 2 (ly & 1) + (lx & 1)), so that each
-// block's points with z cells 2j, 2j + 1 are one run.
+// block's points with z cells 2j, 2j + 1 are one run.  In 2D with a.blocked2d
+// = B the cells come in B x B blocks (block-major), so each block is one run.
 __device__ __forceinline__ int key_of_cells(const SortArgs& a, const int* cell) {
   int bx, by, bz;
   if (a.bpow2) {           // bin sizes 2^bshift: shifts instead of divisions
@@ -110,6 +111,10 @@ __device__ __forceinline__ int key_of_cells(const SortArgs& a, const int* cell) 
               4 * (lz + a.b[2] * ((lx >> 1) + (a.b[0] >> 1) * (ly >> 1)));
     else
       local = lz + a.b[2] * (lx + a.b[0] * ly);
+  } else if (a.blocked2d) {
+    const int B = a.blocked2d, sB = B == 8 ? 3 : 2;
+    local = (lx & (B - 1)) + B * (ly & (B - 1)) +
+            B * B * ((lx >> sB) + (a.b[0] >> sB) * (ly >> sB));
   } else {
     local = lx + a.b[0] * ly;
   }

@@ -14,6 +14,9 @@ using namespace esn;
 namespace {
 
 constexpr size_t kLdsBudgetCap = 64 * 1024;   // bytes of LDS one tile may use
+// the 2D matrix-core kernels run 256-thread blocks: two of them per CU share its
+// 160 KiB of LDS
+constexpr size_t kLdsBudget2dCap = 80 * 1024;
 constexpr int64_t kMaxPoints = 2147483647LL;  // int32 permutation indices
 
 size_t csize(int prec) { return prec == ESN_DOUBLE ? 2 * sizeof(double) : 2 * sizeof(float); }
@@ -34,6 +37,15 @@ size_t lds_budget(int device) {
     cached_dev = device;
   }
   return std::min(cached, kLdsBudgetCap);
+}
+
+size_t lds_budget_2d(int device) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess ||
+      v <= 0)
+    v = 64 * 1024;
+  return std::min((size_t)v, kLdsBudget2dCap);
 }
 
 int ceil_log2(int64_t n) {
@@ -326,6 +338,7 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
     p->bin[m] = (int)std::min<int64_t>(p->bin[m], p->nf[m]);
   }
   const size_t budget = lds_budget(p->device);
+  const size_t budget2d = lds_budget_2d(p->device);
   bool user_bins = o.bin[0] > 0 || o.bin[1] > 0 || o.bin[2] > 0;
   while (!user_bins && tile_lds_bytes(prec, dim, w, p->bin, 1) > budget) {
     int mx = 0;
@@ -348,19 +361,32 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   const bool tile_fits = tile_lds_bytes(prec, dim, w, p->bin, 1) <= budget;
   // matrix-core spreading / interpolation: 3D single precision, w <= 7,
   // fixed-point coordinates, even bin sizes, one transform per launch (method 3)
-  const bool mfma_ok = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
-                       p->pts_code == kPtsFixed32 && p->bin[0] % 2 == 0 &&
-                       p->bin[1] % 2 == 0 && p->bin[2] % 2 == 0 &&
-                       mfma_spread_lds_bytes(w, p->bin) <= budget &&
-                       mfma_interp_lds_bytes(p->bin) <= budget;
-  p->spread_method = o.spread_method ? o.spread_method : (mfma_ok ? 3 : (tile_fits ? 1 : 2));
-  p->interp_method = o.interp_method ? o.interp_method : (mfma_ok ? 3 : (tile_fits ? 1 : 2));
+  const bool mfma3d_ok = dim == 3 && prec == ESN_SINGLE && w <= 7 && o.sort &&
+                         p->pts_code == kPtsFixed32 && p->bin[0] % 2 == 0 &&
+                         p->bin[1] % 2 == 0 && p->bin[2] % 2 == 0 &&
+                         mfma_spread_lds_bytes(w, p->bin) <= budget &&
+                         mfma_interp_lds_bytes(p->bin) <= budget;
+  // 2D on the matrix cores: w <= 13, bins of whole blocks of window cells
+  const int bs2 = mfma2d_block(w);
+  const bool mfma2d_ok = dim == 2 && w <= 13 && o.sort && p->bin[0] % bs2 == 0 &&
+                         p->bin[1] % bs2 == 0 &&
+                         mfma2d_lds_bytes(prec, w, p->bin, 1, true) <= budget2d;
+  const bool mfma_ok = mfma3d_ok || mfma2d_ok;
+  // defaults: the matrix cores where they measured faster than the LDS tiles
+  // (3D single precision both ways; 2D double precision spreading, 1e7 points
+  // on a 2000^2 grid at w = 10: 1.78 ms against 2.39 ms)
+  const bool mfma_spread = mfma3d_ok || (mfma2d_ok && prec == ESN_DOUBLE);
+  const bool mfma_interp = mfma3d_ok;
+  p->spread_method =
+      o.spread_method ? o.spread_method : (mfma_spread ? 3 : (tile_fits ? 1 : 2));
+  p->interp_method =
+      o.interp_method ? o.interp_method : (mfma_interp ? 3 : (tile_fits ? 1 : 2));
   if ((p->spread_method == 3 || p->interp_method == 3) && !mfma_ok) {
     delete p;
     return ESN_ERR_BAD_ARG;
   }
   const bool mfma = (type == 1 && p->spread_method == 3) || (type == 2 && p->interp_method == 3);
-  if (mfma && o.maxsubprob <= 0) p->maxsub = type == 1 ? 1024 : 512;
+  if (mfma && dim == 3 && o.maxsubprob <= 0) p->maxsub = type == 1 ? 1024 : 512;
   if (!o.sort) p->spread_method = p->interp_method = 2;
   if (!tile_fits) {
     if (p->spread_method == 1 || p->interp_method == 1) {
@@ -371,8 +397,18 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   const bool uses_lds = (type == 1 && (p->spread_method == 1 || p->spread_method == 3)) ||
                         (type == 2 && (p->interp_method == 1 || p->interp_method == 3));
   int chunk = o.ntransf_chunk > 0 ? o.ntransf_chunk : ntransf;
-  if (mfma) chunk = 1;
-  if (uses_lds) {
+  if (mfma && dim == 3) chunk = 1;
+  if (mfma && dim == 2) {
+    // transforms share a launch's staged weights, each with its own LDS tile
+    int lim = 1;
+    while (lim < ntransf && mfma2d_lds_bytes(prec, w, p->bin, lim + 1, type == 1) <= budget2d)
+      lim++;
+    if (o.ntransf_chunk <= 0) chunk = std::min(chunk, lim);
+    else if (mfma2d_lds_bytes(prec, w, p->bin, std::min(chunk, ntransf), type == 1) > budget2d) {
+      delete p;
+      return ESN_ERR_BAD_ARG;
+    }
+  } else if (uses_lds) {
     size_t one = tile_lds_bytes(prec, dim, w, p->bin, 1);
     int lim = (int)std::max<size_t>(1, budget / one);
     if (o.ntransf_chunk <= 0) chunk = std::min(chunk, lim);
@@ -504,6 +540,10 @@ static SortArgs sort_args(const esn_plan_s* p, int64_t M, int coord_prec, const 
   a.chkbnds = p->opts.chkbnds;
   a.w = p->par.w;
   a.blocked = p->dim == 3 && p->bin[0] % 2 == 0 && p->bin[1] % 2 == 0;
+  {
+    const int bs2 = mfma2d_block(p->par.w);
+    a.blocked2d = (p->dim == 2 && p->bin[0] % bs2 == 0 && p->bin[1] % bs2 == 0) ? bs2 : 0;
+  }
   a.bpow2 = 1;
   for (int m = 0; m < 3; m++) {
     int sh = 0;
@@ -652,7 +692,10 @@ int esn::setpts_impl(esn_plan p, int64_t M, int coord_prec, const void* const* x
 static int run_spread(esn_plan_s* p, int ntr, const void* c, void* grid) {
   GeomArgs g = make_geom(p, ntr);
   if (p->spread_method == 3) {
-    ESN_HIP(launch_spread_mfma(p->par.w, g, p->nsub, c, grid, p->stream));
+    if (p->dim == 2)
+      ESN_HIP(launch_spread_mfma2d(p->prec, p->par.w, g, p->nsub, c, grid, p->stream));
+    else
+      ESN_HIP(launch_spread_mfma(p->par.w, g, p->nsub, c, grid, p->stream));
     return ESN_OK;
   }
   size_t lds = p->spread_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr) : 0;
@@ -664,7 +707,10 @@ static int run_spread(esn_plan_s* p, int ntr, const void* c, void* grid) {
 static int run_interp(esn_plan_s* p, int ntr, const void* grid, void* c) {
   GeomArgs g = make_geom(p, ntr);
   if (p->interp_method == 3) {
-    ESN_HIP(launch_interp_mfma(p->par.w, g, p->nsub, grid, c, p->stream));
+    if (p->dim == 2)
+      ESN_HIP(launch_interp_mfma2d(p->prec, p->par.w, g, p->nsub, grid, c, p->stream));
+    else
+      ESN_HIP(launch_interp_mfma(p->par.w, g, p->nsub, grid, c, p->stream));
     return ESN_OK;
   }
   size_t lds = p->interp_method == 1 ? tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, ntr, false) : 0;
@@ -680,8 +726,13 @@ static int make_adjoint(esn_plan_s* p) {
   const int dir = 3 - p->type;
   const int method = dir == 1 ? p->spread_method : p->interp_method;
   int chunk = p->chunk;
-  if (method == 3) {
+  if (method == 3 && p->dim == 3) {
     chunk = 1;
+  } else if (method == 3) {
+    const size_t budget = lds_budget_2d(p->device);
+    chunk = std::max(1, chunk);
+    while (chunk > 1 && mfma2d_lds_bytes(p->prec, p->par.w, p->bin, chunk, dir == 1) > budget)
+      chunk--;
   } else if (method == 1) {
     const size_t budget = lds_budget(p->device);
     const size_t one = tile_lds_bytes(p->prec, p->dim, p->par.w, p->bin, 1, dir == 1);

@@ -91,7 +91,19 @@ METHOD_CASES = [
     (3, (24, 20, 28), 300007, "wrapped_gaussian", "f32", 1e-6),
     (3, (12, 12, 12), 200003, "wrapped_gaussian", "f32", 1e-3),
     (2, (40, 33), 50011, "wrapped_gaussian", "f64", 1e-9),
+    (2, (64, 50), 80021, "uniform", "f32", 1e-5),
+    (2, (37, 48), 60013, "wrapped_gaussian", "f64", 1e-12),
 ]
+
+
+def _methods(dim, prec, eps):
+    """Methods a case runs: LDS tiles, atomics / gathers, and the matrix cores
+    where they apply (3D single precision at w <= 7; 2D at w <= 13)."""
+    if dim == 3 and prec == "f32" and eps >= 1e-6:
+        return [1, 2, 3]
+    if dim == 2 and eps >= 1e-12:
+        return [1, 2, 3]
+    return [1, 2]
 
 
 @pytest.mark.parametrize("case", METHOD_CASES,
@@ -103,7 +115,7 @@ def test_spread_methods_agree(case):
     coords, c, _ = _inputs(dim, N, M, points, prec, 300 + dim)
     ref = O.type1(coords, c, +1, N=N)
     outs = {}
-    methods = [1, 2, 3] if (dim == 3 and prec == "f32" and eps >= 1e-6) else [1, 2]
+    methods = _methods(dim, prec, eps)
     for m in methods:
         f, info = run_type1(coords, c, N, eps, prec, spread_method=m)
         err = O.rel_l2(f, ref)
@@ -125,7 +137,7 @@ def test_interp_methods_agree(case):
     coords, _, f = _inputs(dim, N, M, points, prec, 400 + dim)
     ref = O.type2(coords, f, -1)
     outs = {}
-    methods = [1, 2, 3] if (dim == 3 and prec == "f32" and eps >= 1e-6) else [1, 2]
+    methods = _methods(dim, prec, eps)
     for m in methods:
         cc, info = run_type2(coords, f, N, eps, prec, interp_method=m)
         err = O.rel_l2(cc, ref)
@@ -167,6 +179,65 @@ def test_matrix_core_matches_lds_tiles_on_many_small_problems(type_):
                 outs[m], _ = run_type2(coords, f, N, eps, "f32", interp_method=m)
         err = O.rel_l2(outs[3], outs[1])
         assert err < 1e-5, (N, M, points, eps, err)
+
+
+def _many_small_cases_2d(count, seed):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(count):
+        N = tuple(int(x) for x in rng.integers(12, 120, 2))
+        M = int(10 ** rng.uniform(3.0, 5.0))
+        points = "uniform" if i % 2 == 0 else "wrapped_gaussian"
+        prec, eps = [("f32", 1e-6), ("f32", 1e-4), ("f64", 1e-9), ("f64", 1e-12)][i % 4]
+        cases.append((N, M, points, prec, eps, 2000 + i))
+    return cases
+
+
+@pytest.mark.parametrize("type_", [1, 2])
+def test_matrix_core_2d_matches_lds_tiles_on_many_small_problems(type_):
+    """The 2D matrix-core kernels (single and double precision, w up to 13)
+    agree with the LDS-tile kernels to rounding on 40 small problems of random
+    shape, size, point distribution and tolerance."""
+    for N, M, points, prec, eps, seed in _many_small_cases_2d(40, 27 + type_):
+        coords, c, f = _inputs(2, N, M, points, prec, seed)
+        outs = {}
+        for m in (1, 3):
+            if type_ == 1:
+                outs[m], info = run_type1(coords, c, N, eps, prec, spread_method=m)
+            else:
+                outs[m], info = run_type2(coords, f, N, eps, prec, interp_method=m)
+        err = O.rel_l2(outs[3], outs[1])
+        assert err < (1e-5 if prec == "f32" else 1e-12), (N, M, points, prec, eps, err)
+
+
+@pytest.mark.parametrize("prec,eps", [("f32", 1e-5), ("f64", 1e-9)])
+@pytest.mark.parametrize("type_", [1, 2])
+def test_matrix_core_2d_batched_equals_single(prec, eps, type_):
+    """Five vectors on one point set through the 2D matrix-core kernels, fused
+    in launches of two (the weights staged once for both) and run one at a
+    time: the results agree and meet the oracle bar."""
+    N = (56, 44)
+    M = 40_000
+    coords, _, _ = _inputs(2, N, M, "wrapped_gaussian", prec, 77)
+    cdt = np.complex64 if prec == "f32" else np.complex128
+    c = I.complex_normal((5, M), 78, cdt)
+    f = I.complex_normal((5,) + tuple(reversed(N)), 79, cdt)
+    if type_ == 1:
+        fused, info = run_type1(coords, c, N, eps, prec, ntransf=5, spread_method=3,
+                                ntransf_chunk=2)
+    else:
+        fused, info = run_type2(coords, f, N, eps, prec, ntransf=5, interp_method=3,
+                                ntransf_chunk=2)
+    assert info.ntransf_chunk == 2
+    for t in range(5):
+        if type_ == 1:
+            one, _ = run_type1(coords, c[t], N, eps, prec, spread_method=3)
+            ref = O.type1(coords, c[t], +1, N=N)
+        else:
+            one, _ = run_type2(coords, f[t], N, eps, prec, interp_method=3)
+            ref = O.type2(coords, f[t], -1)
+        assert O.rel_l2(fused[t], one) < (1e-5 if prec == "f32" else 1e-12)
+        assert O.rel_l2(fused[t], ref) <= 10 * eps
 
 
 SEAM_CASES = [

@@ -73,6 +73,8 @@ def _host_keys(coords, info, fixed):
             local = (lx & 1) + 2 * (ly & 1) + 4 * (lz + b[2] * ((lx >> 1) + (b[0] >> 1) * (ly >> 1)))
         else:
             local = lz + b[2] * (lx + b[0] * ly)
+    elif dim == 2 and b[0] % (B := (8 if w <= 9 else 4)) == 0 and b[1] % B == 0:
+        local = (lx % B) + B * (ly % B) + B * B * ((lx // B) + (b[0] // B) * (ly // B))
     else:
         local = lx + b[0] * ly
     return (binid * cpb + local).astype(np.int64), near
@@ -132,6 +134,7 @@ CASES = [
     ("3d_counting", 3, (40, 45, 36), 60_001, "clustered", "f32", 3, {}),
     ("2d_radix", 2, (1000, 1000), 2_100_000, "uniform", "f32", 1, {}),
     ("2d_f64_forced_radix", 2, (300, 170), 77_777, "clustered", "f64", 2, {}),
+    ("2d_unblocked_radix", 2, (300, 170), 50_000, "uniform", "f32", 2, {"bin": (10, 6)}),
     ("1d_radix_one_pass", 1, (1000,), 50_000, "uniform", "f64", 2, {}),
     ("1d_single_point", 1, (100,), 1, "uniform", "f32", 2, {}),
     # 320 x 320 x 288 cells: 25-bit keys, three passes of 9-bit digits
