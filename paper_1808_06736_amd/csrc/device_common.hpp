@@ -42,29 +42,38 @@ __host__ __device__ __forceinline__ int window_cell(int cell, int sh, int64_t n)
   return k >= n ? k - (int)n : k;
 }
 
+// Coordinate of a fixed-point value v (cell in the high bits, fbits bits of
+// fraction) or of an FP64 value t.
+template <typename T>
+__device__ __forceinline__ Coord<T> decode_fixed(uint32_t v, int fbits, int* sh_out, int w) {
+  Coord<T> r;
+  const uint32_t mask = (fbits >= 32) ? 0xffffffffu : ((1u << fbits) - 1u);
+  const uint32_t fr = v & mask;
+  r.cell = (int)(fbits >= 32 ? 0u : (v >> fbits));
+  // the fraction fr * 2^-fbits (exact in float when fbits <= 24)
+  if constexpr (sizeof(T) == 4) r.f = ldexpf((float)fr, -fbits);
+  else r.f = ldexp((double)fr, -fbits);
+  *sh_out = window_shift_fixed(fr, fbits, w);
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ Coord<T> decode_f64(double t, int* sh_out, int w) {
+  Coord<T> r;
+  const double c = floor(t);
+  const double f = t - c;                      // exact in FP64
+  r.cell = (int)c;
+  r.f = (T)f;
+  *sh_out = window_shift_f64(f, w);
+  return r;
+}
+
 // Coordinate m of sorted point i from its record.
 template <typename T>
 __device__ __forceinline__ Coord<T> decode_coord(const unsigned char* pts, int code, int fbits,
                                                  int64_t i, int m, int* sh_out, int w) {
-  Coord<T> r;
-  if (code == kPtsFixed32) {
-    const uint32_t v = reinterpret_cast<const uint32_t*>(pts + i * 16)[m];
-    const uint32_t mask = (fbits >= 32) ? 0xffffffffu : ((1u << fbits) - 1u);
-    const uint32_t fr = v & mask;
-    r.cell = (int)(fbits >= 32 ? 0u : (v >> fbits));
-    // the fraction fr * 2^-fbits (exact in float when fbits <= 24)
-    if constexpr (sizeof(T) == 4) r.f = ldexpf((float)fr, -fbits);
-    else r.f = ldexp((double)fr, -fbits);
-    *sh_out = window_shift_fixed(fr, fbits, w);
-  } else {
-    const double t = reinterpret_cast<const double*>(pts + i * 32)[m];
-    const double c = floor(t);
-    const double f = t - c;                      // exact in FP64
-    r.cell = (int)c;
-    r.f = (T)f;
-    *sh_out = window_shift_f64(f, w);
-  }
-  return r;
+  if (code == kPtsFixed32)
+    return decode_fixed<T>(reinterpret_cast<const uint32_t*>(pts + i * 16)[m], fbits, sh_out, w);
+  return decode_f64<T>(reinterpret_cast<const double*>(pts + i * 32)[m], sh_out, w);
 }
 
 // Original index of sorted point i.
@@ -119,8 +128,12 @@ __device__ __forceinline__ void es_weights_t(int sh, T f, T beta, T* ker) {
 // weight is interval k's polynomial at t (Horner's scheme).  c is the same for
 // every thread, so its values come through scalar loads.
 template <int W, typename T>
-__device__ __forceinline__ void es_weights_poly(int sh, T f, const T* __restrict__ c, T* ker) {
+__device__ __forceinline__ void es_weights_poly(int sh, T f, const T* __restrict__ cg, T* ker) {
   constexpr int P = W + kPolyExtra;
+  // read-only for the whole launch: through the constant address space, so the
+  // uniform loads become scalar loads even after the kernel's own stores
+  typedef const __attribute__((address_space(4))) T* ConstPtr;
+  const ConstPtr c = (ConstPtr)cg;
   const T u = (T)sh - f + ((W & 1) ? (T)0.5 : (T)0);
   const T t = (T)2 * u - (T)1;
 #pragma unroll

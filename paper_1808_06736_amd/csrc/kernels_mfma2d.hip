@@ -52,10 +52,9 @@ template <> struct Mfma16<double> {
   __device__ static __forceinline__ int row(int kq, int j) { return kq + 4 * j; }
 };
 
-// Staged points per batch: 64, then points that the last steps of a run may
-// read past the batch (weights of a point beyond a run only meet masked or
-// unstored operands; they stay finite).
-constexpr int kStage2d = 80;
+// Staged points per batch in spreading: 64, then one row that staging never
+// writes (zero), which masked lanes read.
+constexpr int kStage2d = 65;
 
 // Block size of a width: blocks of B window cells keep every window inside the
 // 16 slots from the block's first cell (B - 1 + w <= 16).
@@ -71,41 +70,88 @@ __host__ __device__ inline int tile2d_dim(int b, int bs) { return b + 16 - bs; }
 // 32-bit writes go 16 lanes at a time.  Every layout below keeps each access
 // of the kernels at that minimum:
 //  * tiles are planar (real and imaginary parts in separate planes) with a row
-//    pitch of 4 mod 32 elements, so the 16 x 4 lanes of a matrix operand or
-//    result (column r16 one row apart, k group kq one or four elements apart)
-//    fall on distinct banks;
+//    pitch of 4 (single) or 2 (double precision) mod 32 elements, so the
+//    16 x 4 lanes of a matrix operand or result (column r16 one row apart,
+//    k group kq one or four elements apart) fall on distinct banks;
 //  * spreading stages the weights point-major (16 slots per point) with the
-//    slot index XORed by a function of the point, so that staging (one point
-//    per lane, same slot) and the operand reads (16 slots of 4 points) are
-//    both spread over all banks;
+//    slot index XORed by bits of the point index (p / 2 mod 8 single, p / 2
+//    mod 16 double precision: 64-bit writes go 32 lanes at a time), so that
+//    staging (one point per lane, same slot) and the operand reads (16 slots
+//    of 4 points) are both spread over all banks;
 //  * interpolation stages them slot-major with pitches of 16 mod 32 (x) and
 //    16 or 4 mod 32 (y, single precision: four consecutive slots per k group).
-__host__ __device__ inline int tile2d_pitch(int tx) { return tx + ((4 - tx) & 31); }
+__host__ __device__ inline int tile2d_pitch(int tx, int prec) {
+  return tx + (((prec == ESN_DOUBLE ? 2 : 4) - tx) & 31);
+}
 template <typename T>
-__device__ __forceinline__ int stage_swz(int p) { return sizeof(T) == 4 ? (p >> 1) & 15 : p & 15; }
+__device__ __forceinline__ int stage_swz(int p) { return sizeof(T) == 4 ? (p >> 1) & 7 : (p >> 1) & 15; }
+// Offset of slot r16 of staged point p (the swizzle repeats every 32 points).
+template <typename T>
+__device__ __forceinline__ int stage_off(int p, int r16) { return p * 16 + (r16 ^ stage_swz<T>(p)); }
 constexpr int kPitchX2d = 80;
 template <typename T> __host__ __device__ constexpr int pitch_y2d() { return sizeof(T) == 4 ? 84 : 80; }
 
 size_t mfma2d_lds_bytes(int prec, int w, const int* b, int ntr, bool spread) {
   const size_t cs = prec == ESN_DOUBLE ? 16 : 8, rs = prec == ESN_DOUBLE ? 8 : 4;
   const int bs = block2d(w);
-  const size_t plane = (size_t)tile2d_pitch(tile2d_dim(b[0], bs)) * tile2d_dim(b[1], bs);
-  // spreading keeps two copies of the tiles, interpolation one
+  const size_t plane = (size_t)tile2d_pitch(tile2d_dim(b[0], bs), prec) * tile2d_dim(b[1], bs);
+  // real and imaginary planes per transform; spreading keeps two copies
   const size_t tile = (spread ? 2 : 1) * 2 * plane * rs * ntr;
-  const size_t stage = spread ? 2 * kStage2d * 16 * rs
-                              : 16 * (kPitchX2d + (prec == ESN_DOUBLE ? 80 : 84)) * rs;
-  // strengths or results [64], run keys, footprint offsets and original indices [64]
-  return tile + stage + 64 * cs + 3 * 64 * sizeof(int) + 16;
+  // spreading: x weights and the y weights times the strength's real and
+  // imaginary parts [kStage2d][16] each (with several transforms also the
+  // plain y weights), run keys and footprint offsets [64];
+  // interpolation: x and y weights slot-major, results [64], run keys,
+  // footprint offsets and original indices [64]
+  if (spread)
+    return tile + (ntr > 1 ? 4 : 3) * kStage2d * 16 * rs + 2 * 64 * sizeof(int) + 16;
+  return tile + 16 * (kPitchX2d + (prec == ESN_DOUBLE ? 80 : 84)) * rs + 64 * cs +
+         3 * 64 * sizeof(int) + 16;
 }
 
-// The 16 staged weights of one point along one dimension: w kernel values from
+// A sorted point's record (coordinates and original index), loaded ahead of
+// its batch: fixed point a = (x, y, z, index); FP64 a = (x, y), b = (z, index).
+typedef uint32_t u32x4_2d __attribute__((ext_vector_type(4)));
+struct Rec2d {
+  u32x4_2d a, b;
+};
+__device__ __forceinline__ Rec2d load_rec2d(const GeomArgs& g, int64_t i) {
+  Rec2d r;
+  if (g.pts_code == kPtsFixed32) {
+    r.a = *reinterpret_cast<const u32x4_2d*>(g.pts + i * 16);
+    r.b = r.a;
+  } else {
+    r.a = *reinterpret_cast<const u32x4_2d*>(g.pts + i * 32);
+    r.b = *reinterpret_cast<const u32x4_2d*>(g.pts + i * 32 + 16);
+  }
+  return r;
+}
+template <int W, typename T>
+__device__ __forceinline__ Coord<T> rec_coord(const GeomArgs& g, const Rec2d& r, int m, int* sh) {
+  if (g.pts_code == kPtsFixed32) return decode_fixed<T>(r.a[m], g.fbits[m], sh, W);
+  const uint64_t bits = ((uint64_t)r.a[2 * m + 1] << 32) | r.a[2 * m];
+  return decode_f64<T>(__longlong_as_double((long long)bits), sh, W);
+}
+__device__ __forceinline__ int64_t rec_perm(const GeomArgs& g, const Rec2d& r) {
+  return g.pts_code == kPtsFixed32 ? (int32_t)r.a[3] : (int32_t)r.b[2];
+}
+
+// Window cell of record r along dimension m relative to the bin origin o.
+template <int W, typename T>
+__device__ __forceinline__ int rec_cell2d(const GeomArgs& g, const Rec2d& r, int m, int o) {
+  int sh;
+  const Coord<T> cd = rec_coord<W, T>(g, r, m, &sh);
+  return window_cell(cd.cell, sh, g.n[m]) - o;
+}
+
+// The 16 staged weights of a point along dimension m: w kernel values from
 // the window cell's offset in its block, zeros elsewhere.  Returns the window
 // cell relative to the bin origin o.
 template <int W, typename T>
-__device__ __forceinline__ int weights16(const GeomArgs& g, int64_t i, int m, int o, T (&r)[16]) {
+__device__ __forceinline__ int weights16(const GeomArgs& g, const Rec2d& rec, int m, int o,
+                                         T (&r)[16]) {
   constexpr int BS = block2d(W);
   int sh;
-  const Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], i, m, &sh, W);
+  const Coord<T> cd = rec_coord<W, T>(g, rec, m, &sh);
   T k[W];
   es_weights_any<W, T>(sh, cd.f, (T)g.beta, g.ktab, k);
   const int l = window_cell(cd.cell, sh, g.n[m]) - o;
@@ -122,19 +168,21 @@ __device__ __forceinline__ int weights16(const GeomArgs& g, int64_t i, int m, in
   return l;
 }
 
+// Periodic wrap of a tile index v in [-w/2, n + bin + 16): one correction
+// each way in 32-bit arithmetic, the general remainder only on grids smaller
+// than a tile.
+__device__ __forceinline__ int wrap_tile(int v, int n) {
+  v = v < 0 ? v + n : v;
+  v = v >= n ? v - n : v;
+  if (v < 0 || v >= n) v = (int)wrap_any(v, n);
+  return v;
+}
+
 // Bin of subproblem sidx and its origin (window cells).
 __device__ __forceinline__ void bin_origin2d(const GeomArgs& g, int bin, int* o0, int* o1) {
   const int bi0 = bin % g.nb[0], bi1 = bin / g.nb[0];
   *o0 = bi0 * g.b[0];
   *o1 = bi1 * g.b[1];
-}
-
-// Window cell of sorted point i along dimension m relative to the bin origin o.
-template <int W, typename T>
-__device__ __forceinline__ int rel_cell2d(const GeomArgs& g, int64_t i, int m, int o) {
-  int sh;
-  const Coord<T> cd = decode_coord<T>(g.pts, g.pts_code, g.fbits[m], i, m, &sh, W);
-  return window_cell(cd.cell, sh, g.n[m]) - o;
 }
 
 // Adds a 16 x 16 result (this lane's four elements of column r16) into a tile
@@ -149,13 +197,41 @@ __device__ __forceinline__ void add_block(double* dst, int kq, Mfma16<double>::v
   for (int j = 0; j < 4; j++) dst[kq + 4 * j] += acc[j];
 }
 
+// Sum of v over the four 16-lane rows of the wave (lanes l, l ^ 16, l ^ 32,
+// l ^ 48), in every lane: the row swaps of the lane-permute unit, no LDS.
+__device__ __forceinline__ float rows_sum(float v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ __forceinline__ double rows_sum(double v) {
+  // the same permutation on both halves of each value
+  uint32_t lo = (uint32_t)__double_as_longlong(v), hi = (uint32_t)(__double_as_longlong(v) >> 32);
+  const auto l1 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h1 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v = __longlong_as_double(((int64_t)h1[0] << 32) | l1[0]) +
+      __longlong_as_double(((int64_t)h1[1] << 32) | l1[1]);
+  lo = (uint32_t)__double_as_longlong(v);
+  hi = (uint32_t)(__double_as_longlong(v) >> 32);
+  const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __longlong_as_double(((int64_t)h2[0] << 32) | l2[0]) +
+         __longlong_as_double(((int64_t)h2[1] << 32) | l2[1]);
+}
+
 // Four waves per subproblem share the staged weights.  Wave v takes the real
 // (v even) or imaginary (v odd) part and the even (v < 2) or odd steps of
 // every run; the two step halves add into two copies of the tile, so no two
-// waves write the same LDS value.  Per batch of 64 points wave 0 stages the x
-// weights and the run data, wave 1 the y weights, wave 2 the first
-// transform's strengths.  Transforms 0 .. g.ntr - 1 share the staged weights,
-// each with its own tiles.
+// waves write the same LDS value (LDS atomics measured far slower).  Per batch of 64 points wave 0 stages the x weights, wave 1 the y
+// weights times the strength (real and imaginary part rows), wave 2 the run
+// data; each loads the next batch's point records while the batch is
+// contracted, wave 1 also the next strengths.  Transforms 0 .. g.ntr - 1
+// share the x weights and the runs, wave 1 restaging the y rows with each
+// transform's strengths from a staged copy of the plain y weights; each
+// transform has its own tiles.
 template <int W, typename T>
 __global__ void __launch_bounds__(256)
 spread2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __restrict__ grid) {
@@ -163,18 +239,19 @@ spread2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __res
   using v4 = typename M::v4;
   constexpr int H = W / 2;
   constexpr int BS = block2d(W);
+  constexpr int RS = kStage2d * 16;   // one staged array
+  constexpr int kZero = 64 * 16;      // offset of the zero row
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int TX = tile2d_dim(g.b[0], BS), TY = tile2d_dim(g.b[1], BS);
-  const int TP = tile2d_pitch(TX);
+  const int TP = tile2d_pitch(TX, sizeof(T) == 8 ? ESN_DOUBLE : ESN_SINGLE);
   const int plane = TP * TY;
   const int ntr = g.ntr;
   T* tile = reinterpret_cast<T*>(smem_raw);                             // [2][ntr][2][TY][TP]
   T* sx = tile + (size_t)4 * plane * ntr;                               // [kStage2d][16]
-  T* sy = sx + kStage2d * 16;                                           // [kStage2d][16]
-  cplx_t<T>* sc = reinterpret_cast<cplx_t<T>*>(sy + kStage2d * 16);     // [64]
-  int* srun = reinterpret_cast<int*>(sc + 64);                          // [64] block id
+  T* syc = sx + RS;                                                     // [2][kStage2d][16]
+  T* sky = syc + 2 * RS;                                                // [kStage2d][16] if ntr > 1
+  int* srun = reinterpret_cast<int*>(sky + (ntr > 1 ? RS : 0));         // [64] block id
   int* sorg = srun + 64;                                                // [64] footprint offset
-  int* sperm = sorg + 64;                                               // [64] original index
 
   const int sidx = blockIdx.x;
   const int bin = g.sub_bin[sidx];
@@ -187,72 +264,114 @@ spread2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __res
   const int lane = tid & 63;
   const int part = wv & 1, half = wv >> 1;
   for (int i = tid; i < 4 * plane * ntr; i += 256) tile[i] = (T)0;
-  for (int i = tid; i < 2 * kStage2d * 16; i += 256) sx[i] = (T)0;
+  for (int i = tid; i < 3 * RS; i += 256) sx[i] = (T)0;
   const int r16 = lane & 15;   // A row / B column / D column
   const int kq = lane >> 4;    // k group (the step's point) / D row group
-  // this wave's plane: copy `half`, part `part`
-  T* mine = tile + (size_t)(half * 2 * ntr + part) * plane;
+  const T* syp = syc + part * RS;
+  Rec2d cur;                   // waves 0 - 2: this batch's record of this lane
+  Rec2d nxt;                   // and the next batch's
+  cplx_t<T> cnext;             // wave 1: the next batch's strength
+  if (wv < 3 && lane < min(64, p1 - p0)) {
+    nxt = load_rec2d(g, p0 + lane);
+    if (wv == 1) cnext = c[rec_perm(g, nxt)];
+  }
 
   for (int base = p0; base < p1; base += 64) {
     const int nbatch = min(64, p1 - base);
+    const int nnext = min(64, p1 - base - 64);
     __syncthreads();
-    if (lane < nbatch) {
-      const int64_t i = base + lane;
-      if (wv < 2) {
+    if (wv < 3 && lane < nbatch) {
+      cur = nxt;
+      const int sw = stage_swz<T>(lane);
+      if (wv == 0) {
         T r[16];
-        const int l = weights16<W, T>(g, i, wv, wv == 0 ? ox : oy, r);
-        T* row = (wv == 0 ? sx : sy) + lane * 16;
-        const int sw = stage_swz<T>(lane);
+        weights16<W, T>(g, cur, 0, ox, r);
+        T* row = sx + lane * 16;
 #pragma unroll
         for (int s = 0; s < 16; s++) row[s ^ sw] = r[s];
-        if (wv == 0) {
-          const int ly = rel_cell2d<W, T>(g, i, 1, oy);
-          srun[lane] = (l / BS) + (g.b[0] / BS) * (ly / BS);
-          sorg[lane] = (ly & ~(BS - 1)) * TP + (l & ~(BS - 1));
-          sperm[lane] = (int)point_perm(g.pts, g.pts_code, i);
+      } else if (wv == 1) {
+        T ry[16];
+        weights16<W, T>(g, cur, 1, oy, ry);
+        T* row = syc + lane * 16;
+#pragma unroll
+        for (int s = 0; s < 16; s++) {
+          row[s ^ sw] = ry[s] * cnext.x;
+          row[RS + (s ^ sw)] = ry[s] * cnext.y;
         }
-      } else if (wv == 2) {
-        sc[lane] = c[point_perm(g.pts, g.pts_code, i)];
+        if (ntr > 1) {
+#pragma unroll
+          for (int s = 0; s < 16; s++) row[2 * RS + (s ^ sw)] = ry[s];
+        }
+      } else {
+        const int lx = rec_cell2d<W, T>(g, cur, 0, ox);
+        const int ly = rec_cell2d<W, T>(g, cur, 1, oy);
+        srun[lane] = (lx / BS) + (g.b[0] / BS) * (ly / BS);
+        sorg[lane] = (ly & ~(BS - 1)) * TP + (lx & ~(BS - 1));
       }
     }
+    if (wv < 3 && lane < nnext) nxt = load_rec2d(g, base + 64 + lane);
     __syncthreads();
     const bool starts = lane < nbatch && (lane == 0 || srun[lane] != srun[lane - 1]);
     const uint64_t runs0 = __ballot(starts);
     for (int tr = 0; tr < ntr; tr++) {
       if (tr > 0) {
         __syncthreads();
-        if (tid < nbatch) sc[tid] = c[(int64_t)tr * g.cstride + sperm[tid]];
+        if (wv == 1 && lane < nbatch) {
+          const cplx_t<T> cv = c[(int64_t)tr * g.cstride + rec_perm(g, cur)];
+          T* row = syc + lane * 16;
+#pragma unroll
+          for (int s = 0; s < 16; s++) {
+            const T ky = row[2 * RS + s];
+            row[s] = ky * cv.x;
+            row[RS + s] = ky * cv.y;
+          }
+        }
         __syncthreads();
       }
-      T* tl = mine + (size_t)2 * tr * plane;
+      // this wave's plane: copy `half`, transform tr, part `part`
+      T* tl = tile + (size_t)((half * ntr + tr) * 2 + part) * plane;
       uint64_t runs = runs0;
       while (runs) {
         const int q0 = __ffsll((unsigned long long)runs) - 1;
         runs &= runs - 1;
         const int q1 = runs ? __ffsll((unsigned long long)runs) - 1 : nbatch;
-        // steps q0 + 4 half, q0 + 4 half + 8, ..., alternately into two
-        // accumulators so that consecutive matrix products do not wait
-        v4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-        for (int q = q0 + 4 * half; q < q1; q += 16) {
-          {
-            const int p = q + kq;               // this lane's point (< kStage2d: q <= 63)
-            const int o = p * 16 + (r16 ^ stage_swz<T>(p));
-            const cplx_t<T> cv = sc[min(p, 63)];
-            acc0 = M::mma(sx[o], p < q1 ? sy[o] * (part ? cv.y : cv.x) : (T)0, acc0);
-          }
-          if (q + 8 < q1) {
-            const int p = q + 8 + kq;
-            const int o = p * 16 + (r16 ^ stage_swz<T>(p));
-            const cplx_t<T> cv = sc[min(p, 63)];
-            acc1 = M::mma(sx[o], p < q1 ? sy[o] * (part ? cv.y : cv.x) : (T)0, acc1);
-          }
+        // this wave's steps q0 + 4 half + 8 k, k even into acc0 and odd into
+        // acc1; a step's lane reads slot r16 of point q + kq, at offsets o[k mod
+        // 4] that grow by 512 every fourth step (the swizzle repeats every 32
+        // points).  Points past the run read the zero row instead (a select of
+        // the offset, no branch).  The first two steps run unconditionally, so
+        // both accumulators start from a matrix product.
+        int q = q0 + 4 * half;
+        const int pk = q + kq;
+        int o0 = stage_off<T>(pk, r16), o1 = stage_off<T>(pk + 8, r16);
+        int o2 = stage_off<T>(pk + 16, r16), o3 = stage_off<T>(pk + 24, r16);
+        const v4 zero = {0, 0, 0, 0};
+        int xa = q + kq < q1 ? o0 : kZero, xb = q + 8 + kq < q1 ? o1 : kZero;
+        v4 acc0 = M::mma(sx[xa], syp[xa], zero);
+        v4 acc1 = M::mma(sx[xb], syp[xb], zero);
+        for (q += 16; q < q1; q += 16) {
+          xa = q + kq < q1 ? o2 : kZero;
+          xb = q + 8 + kq < q1 ? o3 : kZero;
+          acc0 = M::mma(sx[xa], syp[xa], acc0);
+          acc1 = M::mma(sx[xb], syp[xb], acc1);
+          o0 += 512;
+          o1 += 512;
+          q += 16;
+          if (q >= q1) break;
+          xa = q + kq < q1 ? o0 : kZero;
+          xb = q + 8 + kq < q1 ? o1 : kZero;
+          acc0 = M::mma(sx[xa], syp[xa], acc0);
+          acc1 = M::mma(sx[xb], syp[xb], acc1);
+          o2 += 512;
+          o3 += 512;
         }
-        acc0 += acc1;
         // add the block's 16 x 16 result into the plane: column r16 is y slot
         const int org = __builtin_amdgcn_readfirstlane(sorg[q0]);
-        add_block(tl + org + r16 * TP, kq, acc0);
+        add_block(tl + org + r16 * TP, kq, acc0 + acc1);
       }
     }
+    // the next batch's strengths (its records were loaded before the barrier)
+    if (wv == 1 && lane < nnext) cnext = c[rec_perm(g, nxt)];
   }
   __syncthreads();
 
@@ -260,9 +379,8 @@ spread2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __res
   const int gx0 = ox - H, gy0 = oy - H;
   for (int i = tid; i < TX * TY; i += 256) {
     const int ix = i % TX, iy = i / TX;
-    const int64_t gx = wrap_any(gx0 + ix, g.n[0]);
-    const int64_t gy = wrap_any(gy0 + iy, g.n[1]);
-    const int64_t gi = gx + g.n[0] * gy;
+    const int nx = (int)g.n[0], ny = (int)g.n[1];
+    const int64_t gi = wrap_tile(gx0 + ix, nx) + (int64_t)nx * wrap_tile(gy0 + iy, ny);
     const int li = iy * TP + ix;
     for (int tr = 0; tr < ntr; tr++) {
       const T* t0 = tile + (size_t)2 * tr * plane + li;
@@ -279,8 +397,10 @@ spread2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ c, T* __res
 
 // Four waves per subproblem share the grid tiles and the staged weights.
 // Wave v takes the real (v even) or imaginary (v odd) part and the even
-// (v < 2) or odd 16-point groups of every run.  Per batch wave 0 stages the x
-// weights and the run data, wave 1 the y weights.
+// (v < 2) or odd 16-point groups of every run, two groups at a time where the
+// run has them.  Per batch wave 0 stages the x weights, wave 1 the y weights,
+// wave 2 the run data; each loads the next batch's point records while the
+// batch is contracted.
 template <int W, typename T>
 __global__ void __launch_bounds__(256)
 interp2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ grid,
@@ -292,7 +412,7 @@ interp2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ grid,
   constexpr int PX = kPitchX2d, PY = pitch_y2d<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int TX = tile2d_dim(g.b[0], BS), TY = tile2d_dim(g.b[1], BS);
-  const int TP = tile2d_pitch(TX);
+  const int TP = tile2d_pitch(TX, sizeof(T) == 8 ? ESN_DOUBLE : ESN_SINGLE);
   const int plane = TP * TY;
   const int ntr = g.ntr;
   T* tile = reinterpret_cast<T*>(smem_raw);                             // [ntr][2][TY][TP]
@@ -313,13 +433,16 @@ interp2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ grid,
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int part = wv & 1, half = wv >> 1;
+  Rec2d nxt;                   // waves 0 - 2: the next batch's record of this lane
+  if (wv < 3 && lane < min(64, p1 - p0)) nxt = load_rec2d(g, p0 + lane);
   for (int i = tid; i < 16 * (PX + PY); i += 256) sx[i] = (T)0;
   {
     // the bin's tiles from the periodic fine grid
     const int gx0 = ox - H, gy0 = oy - H;
     for (int i = tid; i < TX * TY; i += 256) {
       const int ix = i % TX, iy = i / TX;
-      const int64_t gi = wrap_any(gx0 + ix, g.n[0]) + g.n[0] * wrap_any(gy0 + iy, g.n[1]);
+      const int nx = (int)g.n[0], ny = (int)g.n[1];
+      const int64_t gi = wrap_tile(gx0 + ix, nx) + (int64_t)nx * wrap_tile(gy0 + iy, ny);
       const int li = iy * TP + ix;
       for (int tr = 0; tr < ntr; tr++) {
         const cplx_t<T> v = grid[(int64_t)tr * g.gstride + gi];
@@ -334,22 +457,26 @@ interp2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ grid,
 
   for (int base = p0; base < p1; base += 64) {
     const int nbatch = min(64, p1 - base);
+    const int nnext = min(64, p1 - base - 64);
     __syncthreads();
-    if (lane < nbatch && wv < 2) {
-      const int64_t i = base + lane;
-      T r[16];
-      const int l = weights16<W, T>(g, i, wv, wv == 0 ? ox : oy, r);
-      T* col = (wv == 0 ? sx : sy) + lane;
-      const int pitch = wv == 0 ? PX : PY;
+    if (wv < 3 && lane < nbatch) {
+      const Rec2d cur = nxt;
+      if (wv < 2) {
+        T r[16];
+        weights16<W, T>(g, cur, wv, wv == 0 ? ox : oy, r);
+        T* col = (wv == 0 ? sx : sy) + lane;
+        const int pitch = wv == 0 ? PX : PY;
 #pragma unroll
-      for (int s = 0; s < 16; s++) col[s * pitch] = r[s];
-      if (wv == 0) {
-        const int ly = rel_cell2d<W, T>(g, i, 1, oy);
-        srun[lane] = (l / BS) + (g.b[0] / BS) * (ly / BS);
-        sorg[lane] = (ly & ~(BS - 1)) * TP + (l & ~(BS - 1));
-        sperm[lane] = (int)point_perm(g.pts, g.pts_code, i);
+        for (int s = 0; s < 16; s++) col[s * pitch] = r[s];
+      } else {
+        const int lx = rec_cell2d<W, T>(g, cur, 0, ox);
+        const int ly = rec_cell2d<W, T>(g, cur, 1, oy);
+        srun[lane] = (lx / BS) + (g.b[0] / BS) * (ly / BS);
+        sorg[lane] = (ly & ~(BS - 1)) * TP + (lx & ~(BS - 1));
+        sperm[lane] = (int)rec_perm(g, cur);
       }
     }
+    if (wv < 3 && lane < nnext) nxt = load_rec2d(g, base + 64 + lane);
     __syncthreads();
     const bool starts = lane < nbatch && (lane == 0 || srun[lane] != srun[lane - 1]);
     const uint64_t runs0 = __ballot(starts);
@@ -366,19 +493,41 @@ interp2d_mfma_kernel(const GeomArgs g, const cplx_t<T>* __restrict__ grid,
         T gp[4];
 #pragma unroll
         for (int s = 0; s < 4; s++) gp[s] = tl[org + r16 * TP + 4 * s + kq];
-        for (int q = q0 + 16 * half; q < q1; q += 32) {
-          const int p = q + r16;                // this lane's point (< kStage2d)
-          v4 u = {0, 0, 0, 0};
+        int q = q0 + 16 * half;
+        // two groups (q and q + 32) at a time
+        for (; q + 32 < q1; q += 64) {
+          const int pa = q + r16, pb = pa + 32;   // < PX
+          v4 ua = {0, 0, 0, 0}, ub = {0, 0, 0, 0};
 #pragma unroll
-          for (int s = 0; s < 4; s++) u = M::mma(gp[s], sx[(4 * s + kq) * PX + p], u);
+          for (int s = 0; s < 4; s++) {
+            ua = M::mma(gp[s], sx[(4 * s + kq) * PX + pa], ua);
+            ub = M::mma(gp[s], sx[(4 * s + kq) * PX + pb], ub);
+          }
           // c_p = sum_y ky_p(y) U[y, p]: this lane's four y slots, then the
-          // four lane groups
-          T v = (T)0;
+          // four lane rows
+          T va = (T)0, vb = (T)0;
 #pragma unroll
-          for (int j = 0; j < 4; j++) v += sy[M::row(kq, j) * PY + p] * u[j];
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
-          if (kq == 0 && p < q1) sout_part[2 * p] = v;
+          for (int j = 0; j < 4; j++) {
+            va += sy[M::row(kq, j) * PY + pa] * ua[j];
+            vb += sy[M::row(kq, j) * PY + pb] * ub[j];
+          }
+          va = rows_sum(va);
+          vb = rows_sum(vb);
+          if (kq == 0) {
+            if (pa < q1) sout_part[2 * pa] = va;
+            if (pb < q1) sout_part[2 * pb] = vb;
+          }
+        }
+        if (q < q1) {
+          const int pa = q + r16;
+          v4 ua = {0, 0, 0, 0};
+#pragma unroll
+          for (int s = 0; s < 4; s++) ua = M::mma(gp[s], sx[(4 * s + kq) * PX + pa], ua);
+          T va = (T)0;
+#pragma unroll
+          for (int j = 0; j < 4; j++) va += sy[M::row(kq, j) * PY + pa] * ua[j];
+          va = rows_sum(va);
+          if (kq == 0 && pa < q1) sout_part[2 * pa] = va;
         }
       }
       __syncthreads();

@@ -374,7 +374,9 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
   const bool mfma_ok = mfma3d_ok || mfma2d_ok;
   // defaults: the matrix cores where they measured faster than the LDS tiles
   // (3D single precision both ways; 2D double precision spreading, 1e7 points
-  // on a 2000^2 grid at w = 10: 1.78 ms against 2.39 ms)
+  // on a 2000^2 grid at w = 10: 1.13 ms against 2.40 ms).  In 2D single
+  // precision spreading the two tie (0.46 ms at w = 6) and interpolation is
+  // faster on the LDS tiles (0.29 / 0.48 ms against 0.42 / 0.89 ms).
   const bool mfma_spread = mfma3d_ok || (mfma2d_ok && prec == ESN_DOUBLE);
   const bool mfma_interp = mfma3d_ok;
   p->spread_method =
