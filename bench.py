@@ -277,6 +277,8 @@ def main():
     kname = {(1, 3): "spread_mfma_kernel", (2, 3): "interp_mfma_kernel",
              (1, 1): "spread_lds_kernel", (2, 1): "interp_lds_kernel",
              (1, 2): "spread_gm_kernel", (2, 2): "interp_gm_kernel"}[(tdom, method)]
+    if method == 3 and dim == 2:
+        kname = kname.replace("_mfma", "2d_mfma")
     if intensity >= ridge:
         # arithmetic-bound: on the matrix cores (method 3) against the dense
         # MFMA peak of the precision, otherwise against the vector ALU peak
@@ -287,8 +289,10 @@ def main():
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = (f"{kname}<{inf.w}>" if method == 3 else
-                      f"{kname}<{dim},{inf.w},{'float' if prec == 'f32' else 'double'}>")
+    tname = "float" if prec == "f32" else "double"
+    roof["kernel"] = (f"{kname}<{inf.w}>" if method == 3 and dim == 3 else
+                      f"{kname}<{inf.w},{tname}>" if method == 3 else
+                      f"{kname}<{dim},{inf.w},{tname}>")
     roof["traffic"] = measured_traffic(args.traffic, roof["kernel"], wl.name)
     roof["algorithmic_bytes"] = bytes_
     roof["algorithmic_flops"] = flops
