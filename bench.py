@@ -64,9 +64,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), the "
                          "reference for scaling HBM byte counters")
-    ap.add_argument("--serve-requests", type=int, default=120,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the serving measurement (0: skip it)")
-    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.8, 2.0],
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.5, 0.8, 0.95],
                     help="offered loads as fractions of the plain serial throughput")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-sort-ablation", action="store_true",
@@ -488,13 +488,25 @@ def serve_bench(nreq, loads, nslots, seed=5):
 
     The mix: type U{1,2}, d U{2,3}, N_i U[64,512] (2D) / U[64,160] (3D), M
     log-uniform in [1e5, 5e6], uniform or clustered points, eps U{1e-3, 1e-6
-    (single), 1e-9 (double)} (inputs.serve_mix).  Plain = the same requests
-    one at a time in arrival order, each planned, sorted, executed and freed
-    (the paper's one-call interface, Sec. 2).  Served = the request loop with
-    `nslots` worker streams.  Arrivals are Poisson at each of `loads` x the plain
-    serial request rate (above 1 the plain path cannot keep up and throughput
-    shows capacity).  Every shape is run once untimed first on both paths (rocFFT
-    compiles kernels for new sizes), then the timed pass starts.
+    (single), 1e-9 (double)} (inputs.serve_mix), every request with its own
+    data.  Paths:
+    * plain: one request at a time in arrival order, each planned, sorted,
+      executed and freed (the paper's one-call interface, Sec. 2);
+    * plain_reuse: one at a time, but plans kept per (type, N, eps, precision)
+      and reused (setpts + execute only), which separates what the served path
+      gains from plan caching from what it gains from overlap;
+    * served_warm: the request loop with `nslots` worker streams and its plan
+      cache filled by an untimed pass over the same requests;
+    * served_cold: a fresh request loop (empty plan cache).
+    Loads are taken against the plain path's serial throughput and, in
+    ``loads_vs_plain_reuse``, against the plan-reusing path's.
+    Both plain paths are serial, so their latency at an arrival sequence
+    follows from each request's measured service time (single-server FIFO
+    queue: start = max(arrival, previous finish)); the served paths are run
+    with submissions at the arrival times.  Arrivals are Poisson at `loads` x
+    the plain serial request rate.  Every shape is run once untimed first on
+    both paths (rocFFT compiles kernels for new sizes).  Every served result is
+    compared with the plain result of the same request on 256 sampled outputs.
     """
     import torch
     from paper_1808_06736_amd import binding as B
@@ -513,6 +525,15 @@ def serve_bench(nreq, loads, nslots, seed=5):
             f = I.device_complex(tuple(reversed(N)), 30_000 + k, cdt)
         data.append((wl, xs, c, f))
     torch.cuda.synchronize()
+    gsel = torch.Generator(device="cpu").manual_seed(seed)
+    sample = []   # 256 output positions per request
+    for wl, xs, c, f in data:
+        out = f if wl.types[0] == 1 else c
+        sample.append(torch.randint(0, out.numel(), (256,), generator=gsel).cuda())
+
+    def output(d):
+        wl, xs, c, f = d
+        return (f if wl.types[0] == 1 else c).reshape(-1)
 
     def plain_one(wl, xs, c, f):
         p = B.Plan(wl.types[0], wl.N[:wl.dim], wl.eps, dtype=c.dtype)
@@ -521,19 +542,49 @@ def serve_bench(nreq, loads, nslots, seed=5):
         torch.cuda.synchronize()
         p.close()
 
+    plans = {}
+
+    def reuse_one(wl, xs, c, f):
+        key = (wl.types[0], wl.N[:wl.dim], wl.eps, c.dtype)
+        if key not in plans:
+            plans[key] = B.Plan(wl.types[0], wl.N[:wl.dim], wl.eps, dtype=c.dtype)
+        p = plans[key]
+        p.setpts(*xs)
+        p.execute(c, f)
+        torch.cuda.synchronize()
+
+    def service_times(fn):
+        t = []
+        for d in data:
+            t0 = time.perf_counter()
+            fn(*d)
+            t.append(time.perf_counter() - t0)
+        return np.array(t)
+
     # warm-up: every shape once on both paths
     for d in data:
         plain_one(*d)
-    srv = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
-    for tk in [srv.submit(wl.types[0], xs, c, f, wl.eps) for wl, xs, c, f in data]:
-        srv.wait(tk)
+    warm = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
+    for tk in [warm.submit(wl.types[0], xs, c, f, wl.eps) for wl, xs, c, f in data]:
+        warm.wait(tk)
 
-    # plain serial service time -> arrival rates
-    t0 = time.perf_counter()
-    for d in data:
-        plain_one(*d)
-    serial = time.perf_counter() - t0
-    pts = float(sum(wl.M for wl, *_ in data))
+    # plain service times (and the reference outputs), plain with plan reuse
+    s_plain = service_times(plain_one)
+    ref = [output(d)[sample[k]].clone() for k, d in enumerate(data)]
+    service_times(reuse_one)      # fills the plan dict
+    s_reuse = service_times(reuse_one)
+    for p in plans.values():
+        p.close()
+    serial = float(s_plain.sum())
+    pts = np.array([float(wl.M) for wl, *_ in data])
+
+    def fifo(arrive, svc):
+        lat, fin = np.empty(len(svc)), 0.0
+        for k in range(len(svc)):
+            st = max(arrive[k], fin)
+            fin = st + svc[k]
+            lat[k] = fin - arrive[k]
+        return lat, fin          # latencies, finish of the last request
 
     def wait_until(t_abs):
         while True:
@@ -542,42 +593,86 @@ def serve_bench(nreq, loads, nslots, seed=5):
                 return
             time.sleep(dt - 2e-4 if dt > 1e-3 else 0)
 
-    runs = []
-    for load in loads:
-        rate = load * nreq / serial
-        gaps = np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / rate, size=nreq)
-        arrive = np.cumsum(gaps)
-        # plain: one at a time, in arrival order
-        lat = []
-        start = time.perf_counter()
-        for k, d in enumerate(data):
-            wait_until(start + arrive[k])
-            plain_one(*d)
-            lat.append(time.perf_counter() - (start + arrive[k]))
-        plain_wall = time.perf_counter() - start
-        plain = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                 "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                 "pts_per_s": pts / plain_wall}
-        # served: submit at the arrival times
+    classes = sorted({(wl.types[0], wl.dim, wl.eps) for wl, *_ in data})
+    cls_idx = {cl: [k for k, (wl, *_) in enumerate(data) if (wl.types[0], wl.dim, wl.eps) == cl]
+               for cl in classes}
+
+    def summary(lat, wall):
+        out = {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+               "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+               "pts_per_s": float(pts.sum() / wall)}
+        out["per_class"] = {
+            f"type{t} {d}d eps {e:g}": {
+                "requests": len(ix), "p50_ms": 1e3 * float(np.percentile(lat[ix], 50)),
+                "pts_per_s_per_request": float(np.mean(pts[ix] / lat[ix]))}
+            for (t, d, e), ix in cls_idx.items()}
+        return out
+
+    def served_run(srv, arrive):
         srv.reset_stats()
         tickets = []
         start = time.perf_counter()
         for k, (wl, xs, c, f) in enumerate(data):
             wait_until(start + arrive[k])
             tickets.append(srv.submit(wl.types[0], xs, c, f, wl.eps))
-        statuses = [srv.wait(t)[0] for t in tickets]
-        served_wall = time.perf_counter() - start
-        s = srv.stats()
-        served = {"p50_ms": s.p50_ms, "p99_ms": s.p99_ms, "pts_per_s": pts / served_wall,
-                  "failed": int(sum(1 for x in statuses if x >= 2)),
-                  "plan_cache_hits": int(s.plan_cache_hits), "hbm_peak_bytes": int(s.hbm_peak)}
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - start
+        torch.cuda.synchronize()
+        lat = np.array([r[1] for r in res]) * 1e-3
+        err = max(float(torch.linalg.vector_norm(output(d)[sample[k]] - ref[k]) /
+                        torch.linalg.vector_norm(ref[k]).clamp_min(1e-300))
+                  for k, d in enumerate(data))
+        st = srv.stats()
+        out = summary(lat, wall)
+        out.update({"failed": int(sum(1 for r in res if r[0] >= 2)),
+                    "plan_cache_hits": int(st.plan_cache_hits),
+                    "plan_cache_misses": int(st.plan_cache_misses),
+                    "hbm_peak_bytes": int(st.hbm_peak),
+                    "max_rel_l2_vs_plain_on_samples": err})
+        return out
+
+    runs = []
+    for load in loads:
+        rate = load * nreq / serial
+        gaps = np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / rate, size=nreq)
+        arrive = np.cumsum(gaps) - gaps[0]
+        lp, wall_p = fifo(arrive, s_plain)
+        lr, wall_r = fifo(arrive, s_reuse)
+        plain = summary(lp, wall_p)
+        reuse = summary(lr, wall_r)
+        served_w = served_run(warm, arrive)
+        cold = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
+        served_c = served_run(cold, arrive)
+        cold.close()
         runs.append({"offered_load": load, "arrival_rate_per_s": rate, "plain": plain,
-                     "served": served,
-                     "p50_speedup": plain["p50_ms"] / max(served["p50_ms"], 1e-9),
-                     "p99_speedup": plain["p99_ms"] / max(served["p99_ms"], 1e-9),
-                     "throughput_ratio": served["pts_per_s"] / plain["pts_per_s"]})
-    srv.close()
-    return {"requests": nreq, "slots": nslots, "plain_serial_s": serial, "loads": runs}
+                     "plain_reuse": reuse, "served_warm": served_w, "served_cold": served_c,
+                     "p50_speedup_warm_vs_plain": plain["p50_ms"] / max(served_w["p50_ms"], 1e-9),
+                     "p99_speedup_warm_vs_plain": plain["p99_ms"] / max(served_w["p99_ms"], 1e-9),
+                     "p50_speedup_warm_vs_plain_reuse": reuse["p50_ms"] / max(served_w["p50_ms"], 1e-9),
+                     "p99_speedup_warm_vs_plain_reuse": reuse["p99_ms"] / max(served_w["p99_ms"], 1e-9)})
+    # the same loads against the plain path that reuses plans: near its
+    # capacity, what the worker streams' overlap adds
+    runs_reuse = []
+    serial_r = float(s_reuse.sum())
+    for load in loads:
+        rate = load * nreq / serial_r
+        gaps = np.random.Generator(np.random.PCG64(seed + 1)).exponential(1.0 / rate, size=nreq)
+        arrive = np.cumsum(gaps) - gaps[0]
+        lr, wall_r = fifo(arrive, s_reuse)
+        reuse = summary(lr, wall_r)
+        served_w = served_run(warm, arrive)
+        runs_reuse.append({"offered_load": load, "arrival_rate_per_s": rate, "plain_reuse": reuse,
+                           "served_warm": served_w,
+                           "p50_speedup": reuse["p50_ms"] / max(served_w["p50_ms"], 1e-9),
+                           "p99_speedup": reuse["p99_ms"] / max(served_w["p99_ms"], 1e-9),
+                           "throughput_ratio": served_w["pts_per_s"] / reuse["pts_per_s"]})
+    warm.close()
+    return {"requests": nreq, "slots": nslots, "plain_serial_s": serial,
+            "loads_vs_plain_reuse": runs_reuse,
+            "plain_reuse_serial_s": float(s_reuse.sum()),
+            "plain_pts_per_s_serial": float(pts.sum() / serial),
+            "plain_reuse_pts_per_s_serial": float(pts.sum() / s_reuse.sum()),
+            "loads": runs}
 
 
 def batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt, reps=5):

@@ -111,6 +111,31 @@ __device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
 // barrier only: no instruction, no wait).
 __device__ __forceinline__ void keep_order() { asm volatile("" ::: "memory"); }
 
+// Wait states before a VALU instruction may read the result of a matrix
+// instruction.  The MAI dependency rules of the CDNA3 / CDNA4 instruction set
+// require, between an XDL instruction writing VGPRs and a VALU read or write
+// of those VGPRs, as many independent instructions or wait states as the XDL
+// instruction's passes plus 3.  v_mfma_f32_16x16x4_f32 takes 8 passes (32
+// cycles: SQ_VALU_MFMA_BUSY_CYCLES counts 32 per instruction on gfx950), so
+// 11.  The waits are issued explicitly, tied to the accumulators: after the
+// asm statement below the compiler sees the registers as written by it, not
+// by the matrix instruction, and adds no waits of its own, so the statement
+// itself must cover the whole requirement.  (Without explicit waits a stress
+// run found rare results read before the products had landed.)
+constexpr int kMfma16x16x4f32Passes = 8;
+constexpr int kXdlToValuWaits = kMfma16x16x4f32Passes + 3;
+// s_nop n waits n + 1 states, n <= 15
+template <int N>
+__device__ __forceinline__ void xdl_waits(v4f& a) {
+  static_assert(N >= 1 && N <= 16, "one s_nop covers 1 .. 16 wait states");
+  asm volatile("s_nop %1" : "+a"(a) : "i"(N - 1));
+}
+template <int N>
+__device__ __forceinline__ void xdl_waits(v4f& a, v4f& b) {
+  static_assert(N >= 1 && N <= 16, "one s_nop covers 1 .. 16 wait states");
+  asm volatile("s_nop %2" : "+a"(a), "+a"(b) : "i"(N - 1));
+}
+
 // Floats per z plane of a bin tile of T0 x T1 complex cells: 2 T0 T1 padded
 // to 8 mod 32, so that the 8 planes a wave touches at once start in distinct
 // LDS banks.
@@ -284,11 +309,10 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
 
   // add this wave's ring slots in mask fm (block-uniform) into the bin tile and clear them
   auto flush = [&](unsigned fm) {
-    // 16 wait states on top of the compiler's own between the matrix products
-    // and the reads of their results (tied to the accumulators, so the nop
-    // sits between them): with the compiler's count alone, rare results were
-    // read before the products had landed
-    asm volatile("s_nop 15" : "+a"(acc[0]), "+a"(acc[1]));
+    // the wait states before the products are read (a flush is rare: the
+    // largest single s_nop, 16 states, above the 11 required)
+    static_assert(16 >= kXdlToValuWaits, "flush waits below the MAI rule");
+    xdl_waits<16>(acc[0], acc[1]);
 #pragma unroll
     for (int u = 0; u < 2; u++) {
       const int t = 2 * wv + u;
@@ -623,9 +647,8 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], ((s & 1) ? kxb : kxa) * ky[s >> 1],
                                                      acc, 0, 0, 0);
         finish(rep, imp, qp);
-        // 8 wait states on top of the compiler's own before the results are
-        // read (as in the spreading kernel's flush)
-        asm volatile("s_nop 7" : "+a"(acc));
+        // the wait states before the results are read
+        xdl_waits<kXdlToValuWaits>(acc);
         // output rows 4 kq + i: plane kq + 4 (i >> 1), part i & 1
         rep = fmaf(kz4, acc[2], kz0 * acc[0]);
         imp = fmaf(kz4, acc[3], kz0 * acc[1]);
