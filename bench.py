@@ -334,6 +334,9 @@ def main():
     if shared and not args.no_sort_ablation:
         out["sort_ablation"] = sort_ablation(wl, N, coords, c_in, f_in, outs, cdt, stages)
 
+    if wl.name == "3d_clustered":
+        out["batched_8_vectors"] = batched_headline(wl, coords, cdt)
+
     if args.serve_requests > 0 and args.workload == "3d_clustered":
         out["serving"] = serve_bench(args.serve_requests, args.serve_load, args.serve_slots)
 
@@ -673,6 +676,52 @@ def serve_bench(nreq, loads, nslots, seed=5):
             "plain_pts_per_s_serial": float(pts.sum() / serial),
             "plain_reuse_pts_per_s_serial": float(pts.sum() / s_reuse.sum()),
             "loads": runs}
+
+
+def batched_headline(wl, coords, cdt, nvec=8, reps=3):
+    """NU pts/s of nvec strength (type 1) or coefficient (type 2) vectors on
+    the workload's points: one plan with ntransf = nvec (fused launches) against
+    nvec executes on one ntransf = 1 plan; the points are sorted once either
+    way (setpts not timed)."""
+    import torch
+    from paper_1808_06736_amd import binding as B
+    N, M = wl.N[:wl.dim], wl.M
+    res = {"vectors": nvec}
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        b = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            b = min(b, time.perf_counter() - t0)
+        return b
+
+    for t in (1, 2):
+        pb = B.Plan(t, N, wl.eps, dtype=cdt, ntransf=nvec)
+        pb.setpts(*coords)
+        p1 = B.Plan(t, N, wl.eps, dtype=cdt)
+        p1.setpts(*coords)
+        if t == 1:
+            cv = I.device_complex((nvec, M), 777, cdt)
+            fv = torch.empty((nvec,) + tuple(reversed(N)), dtype=cdt, device="cuda")
+            tb = best(lambda: pb.execute(cv, fv))
+            tl = best(lambda: [p1.execute(cv[k], fv[k]) for k in range(nvec)])
+        else:
+            fv = I.device_complex((nvec,) + tuple(reversed(N)), 778, cdt)
+            cv = torch.empty((nvec, M), dtype=cdt, device="cuda")
+            tb = best(lambda: pb.execute(cv, fv))
+            tl = best(lambda: [p1.execute(cv[k], fv[k]) for k in range(nvec)])
+        info = pb.info()
+        res[f"type{t}"] = {"batched_pts_per_s": M * nvec / tb, "plan_loop_pts_per_s": M * nvec / tl,
+                           "batched_over_loop": tl / tb, "chunk": int(info.ntransf_chunk),
+                           "method": int(info.spread_method if t == 1 else info.interp_method)}
+        pb.close()
+        p1.close()
+        del cv, fv
+    return res
 
 
 def batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt, reps=5):

@@ -126,3 +126,36 @@ def test_headline_step_one_plan_type1_and_adjoint():
           f"(type 2) rel l2 {e2[0]:.3e} [{e2[1]:.3e}, {e2[2]:.3e}] (methods "
           f"{info.spread_method}/{info.interp_method}, subproblems {info.nsubprob})")
     assert e1[0] <= 10 * wl.eps and e2[0] <= 10 * wl.eps
+
+
+def test_clustered_3d_batch_of_eight_on_matrix_cores():
+    """Eight strength vectors on one clustered point set (1e6 points, 64^3
+    modes, eps 1e-6; the headline's distribution at a size the oracle samples
+    quickly): the batched execute runs on the matrix cores, every vector
+    equals the same vector run alone on the same sorted points, and vectors 0
+    and 7 meet the oracle bar on sampled modes."""
+    N = (64, 64, 64)
+    M = 1_000_000
+    eps = 1e-6
+    coords = I.wrapped_gaussian_points(M, 3, 401, 0.3, np.float32)
+    c = I.complex_normal((8, M), 402, np.complex64)
+    t = torch()
+    from paper_1808_06736_amd import binding as B
+    pb = B.Plan(1, N, eps, dtype=t.complex64, ntransf=8)
+    pb.setpts(*[dev(a) for a in coords])
+    info = pb.info()
+    assert info.spread_method == 3
+    fb = host(pb.type1(dev(c)))
+    pb.close()
+    p1 = B.Plan(1, N, eps, dtype=t.complex64)
+    p1.setpts(*[dev(a) for a in coords])
+    for k in range(8):
+        one = host(p1.type1(dev(c[k])))
+        assert O.rel_l2(fb[k], one) < 1e-5, k
+    p1.close()
+    modes = [I.sample_modes(n, 8, seed=405 + m) for m, n in enumerate(N)]
+    idx = np.ix_(*[m + n // 2 for m, n in zip(reversed(modes), reversed(N))])
+    for k in (0, 7):
+        err, lo, hi = O.rel_l2_interval(fb[k][idx], O.type1(coords, c[k], +1, modes=modes), seed=k)
+        print(f"batch of 8, vector {k}: rel l2 {err:.3e} [{lo:.3e}, {hi:.3e}]")
+        assert err <= 10 * eps
