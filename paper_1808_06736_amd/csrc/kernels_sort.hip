@@ -9,19 +9,24 @@
 // keys, and the points are ordered by key.
 //
 // Large point sets: a least-significant-digit radix sort of the point records
-// by key, with digits of at most 12 bits (two passes for keys up to 24 bits).
-// A pass splits the points into tiles of consecutive points and runs
-//   rsort_count : each tile's count of every digit (the first pass folds each
-//                 coordinate into [0, 2pi), rescales it to t = x n / 2pi in
-//                 FP64 and forms the key, and checks the coordinates);
+// by key, with digits of at most 8 bits (three passes for the 24-bit keys of
+// the 3D benchmark grids, four above 24 bits):
+//   rsort_keys  : once, in input order: fold each coordinate into [0, 2pi),
+//                 rescale it to t = x n / 2pi in FP64, check it, build the
+//                 point's record and its key, and count the first pass's
+//                 digit per tile;
+// then per pass, over tiles of consecutive points:
+//   rsort_count : each tile's count of every digit of the pass (passes after
+//                 the first);
 //   scan        : exclusive scan of the counts in digit-major order = where
 //                 each tile's points of each digit start;
-//   rsort_pass  : every point to its place: the tile's points are ranked
-//                 stably by digit (each wave its own 64-point steps, lanes of
-//                 one digit found by ballots of the digit's bits).  The first
-//                 pass reads the caller's coordinates and builds the records;
-//                 a pass stores the next pass's digit beside each point, the
-//                 last one the sorted keys.
+//   rsort_pass  : every point, record and key, to its place: a tile is moved
+//                 in chunks, each chunk's points ranked stably by digit (each
+//                 wave its own 64-point steps, lanes of one digit found by
+//                 ballots of the digit's bits), put in digit order in LDS and
+//                 written out from there, so that a digit's points leave as
+//                 one contiguous run;
+// and at the end
 //   ends        : where the sorted keys move on to another bin gives that
 //                 bin's end; the bins' starts follow by a running maximum.
 // The sort is stable: points of one cell keep their input order.

@@ -410,6 +410,45 @@ def test_column_fft_grids(case):
         assert e1 <= 10 * eps and e2 <= 10 * eps
 
 
+@pytest.mark.parametrize("N,sigma,nf", [((31, 127, 16), 2.0, (64, 256, 32)),
+                                         ((101, 25, 25), 1.25, (128, 32, 32))],
+                         ids=["s2-odd", "s1.25-w10"])
+def test_column_fft_several_transforms_per_launch(N, sigma, nf):
+    """Three transforms on one plan whose launches take several at once (the
+    LDS-tile kernels fuse the batch as far as the LDS allows, so the column
+    passes run with a transform index per block and the correction and the
+    clear of the unkept columns with ntr > 1, then a tail launch), for type 1,
+    type 2 and the type 1 plan's adjoint: every transform meets the oracle bar."""
+    eps, M = 1e-5, 3000
+    coords = coord_np(I.uniform_points(M, 3, 931, np.float32), "f32")
+    c = I.complex_normal((3, M), 932, np.complex64)
+    f = I.complex_normal((3,) + tuple(reversed(N)), 933, np.complex64)
+    opts = {"spread_method": 1, "interp_method": 1}
+    if sigma != 2.0:
+        # w = 10: bins of 4 x 4 x 4 keep two tiles within the LDS budget
+        opts.update(upsampfac=sigma, bin=(4, 4, 4))
+    t = torch()
+    p1 = B.Plan(1, N, eps, dtype=t.complex64, ntransf=3, **opts)
+    p1.setpts(*[dev(a) for a in coords])
+    info = p1.info()
+    assert tuple(int(info.nf[m]) for m in range(3)) == nf and info.ntransf_chunk >= 2
+    o1 = host(p1.type1(dev(c)))
+    adj = t.empty((3, M), dtype=t.complex64, device="cuda")
+    p1.execute_adjoint(adj, dev(f))
+    adj = host(adj)
+    p1.close()
+    o2, info2 = run_type2(coords, f, N, eps, "f32", ntransf=3, **opts)
+    assert info2.ntransf_chunk >= 2
+    for k in range(3):
+        e1 = O.rel_l2(o1[k], O.type1(coords, c[k], +1, N=N))
+        r2 = O.type2(coords, f[k], -1)
+        e2 = O.rel_l2(o2[k], r2)
+        ea = O.rel_l2(adj[k], r2)
+        print(f"column FFTs, 3 transforms, {N} sigma {sigma} transform {k}: type 1 {e1:.2e}, "
+              f"type 2 {e2:.2e}, adjoint {ea:.2e}")
+        assert e1 <= 10 * eps and e2 <= 10 * eps and ea <= 10 * eps
+
+
 def test_column_fft_modes_in_fft_order():
     """The column passes that read or write the mode arrays themselves keep
     the caller's mode order: modeord 1 (FFT order) gives the modeord 0 result
