@@ -118,9 +118,12 @@ struct ColIO {
   // modes
   float2* f;                // this transform's mode array
   int fxy;                  // position of (kx, ky) in it
-  float pxy;                // p_kx p_ky (0 where (x, y) holds no mode)
+  double pxy;               // p_kx p_ky (0 where (x, y) holds no mode)
   const int* zoff;          // [L] N1 N2 .. position of kz, or -1
-  const float* zfac;        // [L] p_kz
+  const double* zfac;       // [L] p_kz
+  // the correction p_k = p_kx p_ky p_kz, formed in FP64 and rounded once (as
+  // the separate deconvolution and amplification kernels do)
+  __device__ __forceinline__ float factor(int j) const { return (float)(pxy * zfac[j]); }
   bool col_ok;              // (x, y) holds modes
   __device__ __forceinline__ bool kept(int j, int L) const {
     return j < keep_lo || j >= L - keep_hi;
@@ -132,7 +135,7 @@ struct ColIO {
     if constexpr (IN == kColMasked) return kept(j, L) ? gp.at(u) : make_float2(0.f, 0.f);
     const int zo = zoff[j];
     if (!col_ok || zo < 0) return make_float2(0.f, 0.f);
-    const float p = pxy * zfac[j];
+    const float p = factor(j);
     const float2 v = f[fxy + zo];
     return make_float2(v.x * p, v.y * p);
   }
@@ -149,7 +152,7 @@ struct ColIO {
     }
     const int zo = zoff[j];
     if (!col_ok || zo < 0) return;
-    const float p = pxy * zfac[j];
+    const float p = factor(j);
     f[fxy + zo] = make_float2(v.x * p, v.y * p);
   }
 };
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   io.keep_hi = a.keep_hi;
   io.f = nullptr;
   io.fxy = 0;
-  io.pxy = 0.f;
+  io.pxy = 0.0;
   io.zoff = nullptr;
   io.zfac = nullptr;
   io.col_ok = false;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
   bool x_ok = false;
   constexpr bool modes = IN == kColModes || OUT == kColModes;
   __shared__ int zoff[modes ? L : 1];
-  __shared__ float zfac[modes ? L : 1];
+  __shared__ double zfac[modes ? L : 1];
   if constexpr (modes) {
     const int64_t x = (int64_t)chunk * W + c;
     const int64_t N0 = cm.N[0], N2 = cm.N[2];
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
       const int64_t k = j < N2 - N2 / 2 ? j : (int64_t)j - L;
       const int64_t pos = cm.modeord == 0 ? k + N2 / 2 : (k >= 0 ? k : k + N2);
       zoff[j] = ok ? (int)(pos * cm.N[0] * cm.N[1]) : -1;
-      zfac[j] = ok ? (float)cm.pf[2][k < 0 ? -k : k] : 0.f;
+      zfac[j] = ok ? cm.pf[2][k < 0 ? -k : k] : 0.0;
     }
     io.zoff = zoff;
     io.zfac = zfac;
@@ -271,9 +274,7 @@ __global__ __launch_bounds__(kColThreads) void fft_cols_kernel(float2* __restric
       const int64_t px = cm.modeord == 0 ? kx + N0 / 2 : (kx >= 0 ? kx : kx + N0);
       const int64_t py = cm.modeord == 0 ? ky + N1 / 2 : (ky >= 0 ? ky : ky + N1);
       io.fxy = (int)(px + N0 * py);
-      io.pxy = io.col_ok
-                   ? (float)(cm.pf[0][kx < 0 ? -kx : kx] * cm.pf[1][ky < 0 ? -ky : ky])
-                   : 0.f;
+      io.pxy = io.col_ok ? cm.pf[0][kx < 0 ? -kx : kx] * cm.pf[1][ky < 0 ? -ky : ky] : 0.0;
     }
     col_stages<L, W, IN, OUT, 1, Rs...>(s, tw, sgn, io, c, g);
   }
