@@ -51,6 +51,12 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 
+def progress(msg):
+    """A line on stderr as each part of the run completes (the JSON result is
+    the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,12 +339,16 @@ def main():
         out["batched_vs_plain"] = batched_vs_plain(wl, coords, c_in, f_in, plans, outs, cdt)
     if shared and not args.no_sort_ablation:
         out["sort_ablation"] = sort_ablation(wl, N, coords, c_in, f_in, outs, cdt, stages)
+        progress("sort ablation done")
 
+    progress(f"timed steps done: {ms_per_step:.3f} ms per step")
     if wl.name == "3d_clustered":
         out["batched_8_vectors"] = batched_headline(wl, coords, cdt)
+        progress("batched 8-vector comparison done")
 
     if args.serve_requests > 0 and args.workload == "3d_clustered":
         out["serving"] = serve_bench(args.serve_requests, args.serve_load, args.serve_slots)
+        progress("serving measurement done")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(wl, coords_np, c_np, f_np, plans,
@@ -495,9 +505,10 @@ def serve_bench(nreq, loads, nslots, seed=5):
     data.  Paths:
     * plain: one request at a time in arrival order, each planned, sorted,
       executed and freed (the paper's one-call interface, Sec. 2);
-    * plain_reuse: one at a time, but plans kept per (type, N, eps, precision)
-      and reused (setpts + execute only), which separates what the served path
-      gains from plan caching from what it gains from overlap;
+    * plain_reuse: one at a time with the plan already made (setpts + execute
+      only: each plain request's time without its plan creation and
+      destruction), which separates what the served path gains from plan
+      caching from what it gains from overlap;
     * served_warm: the request loop with `nslots` worker streams and its plan
       cache filled by an untimed pass over the same requests;
     * served_cold: a fresh request loop (empty plan cache).
@@ -539,45 +550,37 @@ def serve_bench(nreq, loads, nslots, seed=5):
         return (f if wl.types[0] == 1 else c).reshape(-1)
 
     def plain_one(wl, xs, c, f):
+        """One plain request; returns (service time, time of setpts + execute)."""
+        t0 = time.perf_counter()
         p = B.Plan(wl.types[0], wl.N[:wl.dim], wl.eps, dtype=c.dtype)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         p.setpts(*xs)
         p.execute(c, f)
         torch.cuda.synchronize()
+        t2 = time.perf_counter()
         p.close()
+        return time.perf_counter() - t0, t2 - t1
 
-    plans = {}
-
-    def reuse_one(wl, xs, c, f):
-        key = (wl.types[0], wl.N[:wl.dim], wl.eps, c.dtype)
-        if key not in plans:
-            plans[key] = B.Plan(wl.types[0], wl.N[:wl.dim], wl.eps, dtype=c.dtype)
-        p = plans[key]
-        p.setpts(*xs)
-        p.execute(c, f)
-        torch.cuda.synchronize()
-
-    def service_times(fn):
-        t = []
-        for d in data:
-            t0 = time.perf_counter()
-            fn(*d)
-            t.append(time.perf_counter() - t0)
-        return np.array(t)
-
+    progress(f"serving: data of {nreq} requests ready")
     # warm-up: every shape once on both paths
-    for d in data:
+    for k, d in enumerate(data):
         plain_one(*d)
+        if (k + 1) % 100 == 0:
+            progress(f"serving: plain warm-up {k + 1}/{nreq}")
     warm = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
     for tk in [warm.submit(wl.types[0], xs, c, f, wl.eps) for wl, xs, c, f in data]:
         warm.wait(tk)
+    progress("serving: served warm-up done")
 
-    # plain service times (and the reference outputs), plain with plan reuse
-    s_plain = service_times(plain_one)
+    # plain service times and the reference outputs; the plan-reusing path's
+    # service time is the same request's setpts + execute (the plan made and
+    # freed outside it), since holding a plan for each of the mix's shapes at
+    # once would not fit the device
+    times = np.array([plain_one(*d) for d in data])
+    s_plain, s_reuse = times[:, 0], times[:, 1]
+    progress(f"serving: plain service times measured ({times[:, 0].sum():.2f} s serial)")
     ref = [output(d)[sample[k]].clone() for k, d in enumerate(data)]
-    service_times(reuse_one)      # fills the plan dict
-    s_reuse = service_times(reuse_one)
-    for p in plans.values():
-        p.close()
     serial = float(s_plain.sum())
     pts = np.array([float(wl.M) for wl, *_ in data])
 
@@ -647,6 +650,7 @@ def serve_bench(nreq, loads, nslots, seed=5):
         cold = B.Server(nslots=nslots, hbm_budget_bytes=64 << 30)
         served_c = served_run(cold, arrive)
         cold.close()
+        progress(f"serving: load {load} of the plain rate done")
         runs.append({"offered_load": load, "arrival_rate_per_s": rate, "plain": plain,
                      "plain_reuse": reuse, "served_warm": served_w, "served_cold": served_c,
                      "p50_speedup_warm_vs_plain": plain["p50_ms"] / max(served_w["p50_ms"], 1e-9),
@@ -664,6 +668,7 @@ def serve_bench(nreq, loads, nslots, seed=5):
         lr, wall_r = fifo(arrive, s_reuse)
         reuse = summary(lr, wall_r)
         served_w = served_run(warm, arrive)
+        progress(f"serving: load {load} of the plan-reusing rate done")
         runs_reuse.append({"offered_load": load, "arrival_rate_per_s": rate, "plain_reuse": reuse,
                            "served_warm": served_w,
                            "p50_speedup": reuse["p50_ms"] / max(served_w["p50_ms"], 1e-9),

@@ -368,11 +368,19 @@ int fft_make_padded(FFTPlan* p, int dim, const int64_t* L, const int64_t* N, int
                     hipStream_t s);
 int fft_exec_padded(FFTPlan* p, void* data, int input_padded);
 // Move an FFT plan's work to another stream.
+void fft_trim(FFTPlan* p);
+int fft_ensure_work(FFTPlan* p);
 int fft_set_stream(FFTPlan* p, hipStream_t s);
 
 // Move a plan (and its rocFFT execution info) to another stream.  The caller
 // makes sure no work of the plan is pending on the old stream.
 int plan_set_stream(esn_plan p, hipStream_t s);
+// Give back the memory a plan needs only while it works (fine grid, FFT work
+// buffers, sorted points and sort scratch); the plan keeps its parameters,
+// tables and FFT plans, needs a setpts before its next execute, and makes
+// the buffers again then.  For plans kept idle in a cache.  Returns the
+// plan's remaining device bytes.
+int64_t plan_trim(esn_plan p);
 // Device bytes a plan of this shape would hold with M points (an estimate used
 // for admission before the plan exists; rocFFT's work buffer is taken as one
 // fine grid).

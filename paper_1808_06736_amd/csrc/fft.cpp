@@ -53,7 +53,7 @@ static rocfft_plan make_one(int dim, const size_t* len, size_t batch, const size
 
 // Twiddle table of the column FFTs: exp(2 pi i e / ly), e < ly, then
 // exp(2 pi i e / lz), e < lz, in FP64.
-static int col_twiddles(FFTPlan* p) {
+static int col_twiddles(FFTPlan* p, hipStream_t s) {
   std::vector<double2> tw((size_t)(p->ly + p->lz));
   for (int i = 0; i < p->ly + p->lz; i++) {
     const int len = i < p->ly ? p->ly : p->lz;
@@ -61,12 +61,13 @@ static int col_twiddles(FFTPlan* p) {
     const double ang = 2.0 * M_PI * (double)e / (double)len;
     tw[(size_t)i] = make_double2(std::cos(ang), std::sin(ang));
   }
-  if (hipMalloc(&p->d_tw, tw.size() * sizeof(double2)) != hipSuccess) {
+  // stream-ordered memory on the plan's stream (no wait for the whole device)
+  if (hipMallocAsync((void**)&p->d_tw, tw.size() * sizeof(double2), s) != hipSuccess) {
     p->d_tw = nullptr;
     return ESN_ERR_ALLOC;
   }
-  if (hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) !=
-      hipSuccess)
+  if (hipMemcpyAsync(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
     return ESN_ERR_HIP;
   return ESN_OK;
 }
@@ -85,7 +86,7 @@ static int finish_plan(FFTPlan* p, hipStream_t s) {
   p->work_bytes = work;
   if (rocfft_execution_info_create(&p->info) != rocfft_status_success) return ESN_ERR_FFT_PLAN;
   if (work > 0) {
-    if (hipMalloc(&p->work, work) != hipSuccess) {
+    if (hipMallocAsync(&p->work, work, s) != hipSuccess) {
       p->work = nullptr;
       return ESN_ERR_ALLOC;
     }
@@ -178,7 +179,7 @@ int fft_make(FFTPlan* p, int dim, const int64_t* nf, const int64_t* nmodes, int 
       p->cz_keep.keep_lo = zlo;
       p->cz_keep.keep_hi = zlo + zhi < nf[2] ? zhi : nf[2] - zlo;
     }
-    const int rc = col_twiddles(p);
+    const int rc = col_twiddles(p, s);
     if (rc != ESN_OK) return rc;
   } else if (prune) {
     const size_t lx[1] = {(size_t)nf[0]};
@@ -238,7 +239,7 @@ int fft_make_padded(FFTPlan* p, int dim, const int64_t* L, const int64_t* N, int
   p->cz.plane_b0 = L[1];
   const size_t lx[1] = {(size_t)L[0]};
   p->plan = make_one(1, lx, (size_t)(L[1] * L[2]), nullptr, 0, prec, sign);
-  const int rc = col_twiddles(p);
+  const int rc = col_twiddles(p, s);
   if (rc != ESN_OK) return rc;
   return finish_plan(p, s);
 }
@@ -342,9 +343,28 @@ void fft_destroy(FFTPlan* p) {
   if (p->info) rocfft_execution_info_destroy(p->info);
   for (rocfft_plan q : {p->plan, p->yz[0], p->yz[1]})
     if (q) rocfft_plan_destroy(q);
-  if (p->work) (void)hipFree(p->work);
-  if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->work) (void)hipFreeAsync(p->work, p->stream);
+  if (p->d_tw) (void)hipFreeAsync(p->d_tw, p->stream);
   *p = FFTPlan();
+}
+
+// Give back the rocFFT work buffer (a plan kept idle); fft_ensure_work makes
+// it again before the next transform.
+void fft_trim(FFTPlan* p) {
+  if (p->work) (void)hipFreeAsync(p->work, p->stream);
+  p->work = nullptr;
+}
+
+int fft_ensure_work(FFTPlan* p) {
+  if (!p->info || p->work_bytes == 0 || p->work) return ESN_OK;
+  if (hipMallocAsync(&p->work, p->work_bytes, p->stream) != hipSuccess) {
+    p->work = nullptr;
+    return ESN_ERR_ALLOC;
+  }
+  if (rocfft_execution_info_set_work_buffer(p->info, p->work, p->work_bytes) !=
+      rocfft_status_success)
+    return ESN_ERR_FFT_PLAN;
+  return ESN_OK;
 }
 
 int fft_set_stream(FFTPlan* p, hipStream_t s) {

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "esn_internal.hpp"
@@ -55,9 +56,37 @@ int ceil_log2(int64_t n) {
 }
 
 // Device allocations of a plan, with their sizes kept for accounting.
+// Plan memory comes from the stream-ordered allocator on the plan's stream:
+// unlike hipMalloc / hipFree, allocating and freeing it does not wait for the
+// whole device, so plans made and destroyed by one worker of a request loop
+// do not stall the others.  A plan's first use of an allocation is on its own
+// stream, and plan creation ends with a synchronisation of that stream, so
+// the memory is ready for any stream the plan moves to.
+// Memory given back to the stream-ordered allocator stays in its pool up to
+// this much (per device) instead of returning to the system at the next
+// synchronisation, so that plans that make and free their working buffers at
+// every request (a request loop's cached plans) reuse pool memory.
+constexpr uint64_t kPoolKeepBytes = (uint64_t)16 << 30;
+
+void keep_pool_memory(int device) {
+  static std::mutex mu;
+  static std::vector<int> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(done.begin(), done.end(), device) != done.end()) return;
+  done.push_back(device);
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || !pool) {
+    (void)hipGetLastError();
+    return;
+  }
+  uint64_t keep = kPoolKeepBytes;
+  if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess)
+    (void)hipGetLastError();
+}
+
 int dalloc(esn_plan_s* p, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  if (hipMalloc(ptr, bytes) != hipSuccess) {
+  if (hipMallocAsync(ptr, bytes, p->stream) != hipSuccess) {
     *ptr = nullptr;
     (void)hipGetLastError();
     return ESN_ERR_ALLOC;
@@ -76,9 +105,33 @@ void dfree(esn_plan_s* p, void** ptr) {
         break;
       }
     }
-    (void)hipFree(*ptr);
+    (void)hipFreeAsync(*ptr, p->stream);
   }
   *ptr = nullptr;
+}
+
+// Small pinned host slots for the plans' read-backs (32 bytes each), carved
+// from pinned pages that stay for the process (hipHostFree would wait for
+// the device).
+std::mutex g_pin_mu;
+std::vector<int32_t*> g_pin_free;
+
+int32_t* pinned_slot_get() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (g_pin_free.empty()) {
+    void* page = nullptr;
+    if (hipHostMalloc(&page, 4096, hipHostMallocDefault) != hipSuccess) return nullptr;
+    for (int i = 0; i < 4096 / 32; i++) g_pin_free.push_back(static_cast<int32_t*>(page) + 8 * i);
+  }
+  int32_t* slot = g_pin_free.back();
+  g_pin_free.pop_back();
+  return slot;
+}
+
+void pinned_slot_put(int32_t* slot) {
+  if (!slot) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(slot);
 }
 
 #define ESN_HIP(call)                         \
@@ -136,6 +189,21 @@ void free_subs(esn_plan_s* p) {
   dfree(p, (void**)&p->d_sub_start);
   dfree(p, (void**)&p->d_sub_len);
   p->cap_sub = 0;
+}
+
+// The fine grid (chunk transforms) and the FFT work buffers, made again after
+// plan_trim gave them back.
+int ensure_exec_buffers(esn_plan_s* p) {
+  if (!p->spread_only && !p->d_grid &&
+      dalloc(p, &p->d_grid, (size_t)nf_total(p) * csize(p->prec) * p->chunk) != ESN_OK)
+    return ESN_ERR_ALLOC;
+  for (FFTPlan* f : {&p->fft, &p->fft_tail, &p->fft_adj, &p->fft_adj_tail}) {
+    const bool had = f->work != nullptr;
+    const int rc = fft_ensure_work(f);
+    if (rc != ESN_OK) return rc;
+    if (!had && f->work) p->device_bytes += (int64_t)f->work_bytes;
+  }
+  return ESN_OK;
 }
 
 
@@ -205,7 +273,7 @@ void destroy_all(esn_plan_s* p) {
   dfree(p, (void**)&p->d_tiles);
   dfree(p, (void**)&p->d_flags);
   dfree(p, &p->d_ktab);
-  if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+  pinned_slot_put(p->h_pinned);
   p->h_pinned = nullptr;
   fft_destroy(&p->fft);
   fft_destroy(&p->fft_tail);
@@ -217,7 +285,7 @@ void destroy_all(esn_plan_s* p) {
     for (auto& e : r.e)
       if (e) (void)hipEventDestroy(e);
   // anything still tracked (none is expected)
-  for (auto& a : p->allocs) (void)hipFree(a.first);
+  for (auto& a : p->allocs) (void)hipFreeAsync(a.first, p->stream);
   p->allocs.clear();
   p->device_bytes = 0;
 }
@@ -300,6 +368,7 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
     delete p;
     return ESN_ERR_HIP;
   }
+  keep_pool_memory(p->device);
   for (int m = 0; m < 3; m++) {
     p->N[m] = m < dim ? nmodes[m] : 1;
     p->nf[m] = par.nf[m];
@@ -450,13 +519,13 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
     if (esn_kernel_poly(w, par.beta, tab.data()) != ESN_OK) return fail(ESN_ERR_BAD_ARG);
     if (prec == ESN_DOUBLE) {
       if (dalloc(p, &p->d_ktab, tab.size() * sizeof(double)) != ESN_OK ||
-          hipMemcpy(p->d_ktab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipMemcpyAsync(p->d_ktab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
               hipSuccess)
         return fail(ESN_ERR_ALLOC);
     } else {
       const std::vector<float> tf(tab.begin(), tab.end());
       if (dalloc(p, &p->d_ktab, tf.size() * sizeof(float)) != ESN_OK ||
-          hipMemcpy(p->d_ktab, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice) !=
+          hipMemcpyAsync(p->d_ktab, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice, s) !=
               hipSuccess)
         return fail(ESN_ERR_ALLOC);
     }
@@ -519,8 +588,10 @@ int esn::make_plan(int type, int dim, const int64_t* nmodes, int isign, int ntra
         dalloc(p, (void**)&p->d_flags, 4 * 4))
       return fail(ESN_ERR_ALLOC);
   }
-  if (hipHostMalloc((void**)&p->h_pinned, 4 * 8, hipHostMallocDefault) != hipSuccess)
+  if (!(p->h_pinned = pinned_slot_get()))
     return fail(ESN_ERR_ALLOC);
+  // the plan's memory (stream-ordered) and tables are ready for any stream
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ESN_ERR_HIP);
   *out = p;
   return p->warn;
 }
@@ -774,6 +845,7 @@ static int execute_dir(esn_plan_s* p, int dir, void* c, void* f) {
   ESN_HIP(hipSetDevice(p->device));
   const bool adj = dir != p->type;
   if (adj) ESN_TRY(make_adjoint(p));
+  ESN_TRY(ensure_exec_buffers(p));
   const int chunk = adj ? p->adj_chunk : p->chunk;
   FFTPlan* fft_full = adj ? &p->fft_adj : &p->fft;
   FFTPlan* fft_last = adj ? &p->fft_adj_tail : &p->fft_tail;
@@ -1049,6 +1121,24 @@ extern "C" int esn_get_stats_history(esn_plan p, esn_stats* out, int max, int* c
 }
 
 namespace esn {
+
+int64_t plan_trim(esn_plan p) {
+  if (!p) return 0;
+  (void)hipStreamSynchronize(p->stream);
+  free_points(p);
+  free_subs(p);
+  dfree(p, (void**)&p->d_count);
+  dfree(p, (void**)&p->d_sstart);
+  dfree(p, (void**)&p->d_cell_scan_tmp);
+  dfree(p, &p->d_grid);
+  for (FFTPlan* f : {&p->fft, &p->fft_tail, &p->fft_adj, &p->fft_adj_tail}) {
+    if (f->work) p->device_bytes -= (int64_t)f->work_bytes;
+    fft_trim(f);
+  }
+  p->M = -1;
+  p->nsub = 0;
+  return p->device_bytes;
+}
 
 int plan_set_stream(esn_plan p, hipStream_t s) {
   if (!p) return ESN_ERR_BAD_ARG;

@@ -10,7 +10,9 @@
 // recorded at submit on the stream that wrote its inputs.  Plans
 // are cached by problem shape (type, dim, modes, sign, tolerance, precision);
 // a cached plan remembers the point set it last sorted, so a request that
-// names the same points id skips setpts.  Latency is measured from submit to
+// names the same points id skips setpts; a plan cached without a points id
+// keeps only its parameters, tables and FFT plans (its grid, FFT work and
+// point buffers are made again at its next request).  Latency is measured from submit to
 // the end of the request's work on its stream.
 #include <algorithm>
 #include <chrono>
@@ -221,6 +223,11 @@ void worker_loop(esn_server_s* sv, int slot) {
     if (st < 2) st = esn_execute(plan, q->r.c, q->r.f);
     if (hipStreamSynchronize(stream) != hipSuccess && st < 2) st = ESN_ERR_HIP;
     if (st < 2 && warn) st = warn;
+    // a plan kept for later requests gives back its working memory (grid, FFT
+    // work, sorted points) unless its sorted points may be asked for again,
+    // so that the cache holds many more plans within the budget; the buffers
+    // come back (stream-ordered, no device-wide wait) at its next request
+    if (plan && st < 2 && q->r.points_id == 0) (void)esn::plan_trim(plan);
     esn_info info{};
     if (plan) esn_get_info(plan, &info);
 
