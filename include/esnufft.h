@@ -39,7 +39,10 @@
  * esn_makeplan (NULL = the null stream).  Calls return once the work is
  * enqueued, except where stated; errors found on the host are returned
  * before anything is enqueued.  One plan must not be used from two host
- * threads at once.
+ * threads at once.  A plan's device memory comes from the stream-ordered
+ * allocator on that stream (allocation and freeing do not wait for the
+ * rest of the device; freed memory stays in the device's default pool up to
+ * 16 GiB), so the stream must stay valid until esn_destroy.
  *
  * Status codes: 0 = success, 1 = warning (computed, but eps is beyond what
  * the precision supports), >= 2 = error (nothing was computed).
