@@ -274,8 +274,12 @@ def main():
     inf = info[tdom]
     nf = [int(inf.nf[m]) for m in range(dim)]
     kind = "spread" if tdom == 1 else "interp"
-    bytes_, flops = algorithmic_work(inf.w, dim, M, ntr, nf, prec, kind)
-    dur_s = kern_t[tdom] * 1e-3
+    # per launch: a batched execute runs ceil(ntransf / chunk) launches of the
+    # dominant kernel (chunk vectors each); the stage time covers them all
+    chunk = max(1, int(inf.ntransf_chunk))
+    nlaunch = -(-ntr // chunk)
+    bytes_, flops = algorithmic_work(inf.w, dim, M, min(chunk, ntr), nf, prec, kind)
+    dur_s = kern_t[tdom] * 1e-3 / nlaunch
     peak_alu = FP32_PEAK_TFLOPS if prec == "f32" else FP64_PEAK_TFLOPS
     intensity = flops / bytes_
     ridge = peak_alu * 1e12 / (HBM_PEAK_GBS * 1e9)
@@ -302,7 +306,8 @@ def main():
     roof["traffic"] = measured_traffic(args.traffic, roof["kernel"], wl.name)
     roof["algorithmic_bytes"] = bytes_
     roof["algorithmic_flops"] = flops
-    roof["mean_launch_ms"] = kern_t[tdom]
+    roof["mean_launch_ms"] = kern_t[tdom] / nlaunch
+    roof["launches_per_execute"] = nlaunch
     roof["hbm_frac"] = bytes_ / dur_s / 1e9 / HBM_PEAK_GBS
 
     out = {
