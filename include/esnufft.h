@@ -160,8 +160,10 @@ int esn_makeplan(int type, int dim, const int64_t* nmodes, int isign, int ntrans
                  double eps, int prec, esn_plan* out, const esn_opts* opts,
                  void* stream);
 
-/* Give the plan M >= 0 points (coordinate arrays x[, y[, z]] of M values,
- * float if coord_prec == ESN_SINGLE else double; unused dims may be NULL).
+/* Give the plan M points, 0 <= M <= 2^31 - 2^16 (ESN_ERR_BAD_ARG above; the
+ * same limit holds for the sources and targets of esn_setpts3): coordinate
+ * arrays x[, y[, z]] of M values, float if coord_prec == ESN_SINGLE else
+ * double; unused dims may be NULL.
  * Folds each coordinate into [0, 2pi) and rescales it to fine-grid units in
  * FP64, bin-sorts the points (Sec. 5.1) and builds the subproblem list
  * (Sec. 5.2).  Synchronises the stream (it reads back the subproblem count

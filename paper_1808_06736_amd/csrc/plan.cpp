@@ -18,7 +18,10 @@ constexpr size_t kLdsBudgetCap = 64 * 1024;   // bytes of LDS one tile may use
 // the 2D matrix-core kernels run 256-thread blocks: two of them per CU share its
 // 160 KiB of LDS
 constexpr size_t kLdsBudget2dCap = 80 * 1024;
-constexpr int64_t kMaxPoints = 2147483647LL;  // int32 permutation indices
+// Points per set: permutation indices are int32, and the spreading and
+// interpolation kernels form record indices up to a few hundred past a
+// subproblem's start in 32-bit ints, so the limit keeps 2^16 of headroom.
+constexpr int64_t kMaxPoints = ((int64_t)1 << 31) - ((int64_t)1 << 16);
 
 size_t csize(int prec) { return prec == ESN_DOUBLE ? 2 * sizeof(double) : 2 * sizeof(float); }
 

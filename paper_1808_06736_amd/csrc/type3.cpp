@@ -31,7 +31,10 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int64_t kT3MaxGrid = (int64_t)1 << 31;   // cells of the type 3 grid
-constexpr int64_t kMaxPoints = 2147483647LL;        // int32 permutation indices
+// Points per set: permutation indices are int32, and the spreading and
+// interpolation kernels form record indices up to a few hundred past a
+// subproblem's start in 32-bit ints, so the limit keeps 2^16 of headroom.
+constexpr int64_t kMaxPoints = ((int64_t)1 << 31) - ((int64_t)1 << 16);
 
 #define ESN_HIP(call)                       \
   do {                                      \

@@ -168,6 +168,24 @@ def test_bad_points_are_errors():
     assert O.rel_l2(f, ref) < 1e-8
 
 
+def test_point_count_limit():
+    """M above 2^31 - 2^16 is refused before any coordinate is read (the
+    kernels keep record indices in 32-bit ints with that headroom); the
+    small arrays passed with it are never touched."""
+    limit = (1 << 31) - (1 << 16)
+    x = dev(np.linspace(0.0, 1.0, 4).astype(np.float32))
+    ptr = B.vp(x.data_ptr())
+    p = B.Plan(1, (16, 16, 16), 1e-6, dtype=torch().complex64)
+    for M in (limit + 1, (1 << 31) - 1, 1 << 31):
+        assert B.esn_setpts(p.handle, M, B.ESN_SINGLE, ptr, ptr, ptr) == B.ESN_ERR_BAD_ARG
+    p.setpts(x, x, x)                 # the plan still takes a valid point set
+    p.close()
+    q = B.Plan3(3, 1e-6, dtype=torch().complex64)
+    for M, N in ((limit + 1, 4), (4, limit + 1)):
+        assert B.esn_setpts3(q.handle, M, B.ESN_SINGLE, [ptr] * 3, N, [ptr] * 3) == B.ESN_ERR_BAD_ARG
+    q.close()
+
+
 def test_modeord_fft_order():
     N = (7, 6)
     coords = I.uniform_points(500, 2, 101)
