@@ -41,7 +41,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // ES kernel values of one point at its w window cells (as es_weights_f32),
 // using the hardware square root and base-2 exponential: bl = beta log2(e),
-// ker[k] = 2^(bl (sqrt(1 - z^2) - 1)).
+// ker[k] = 2^(bl (sqrt(1 - z^2) - 1)).  Only the two edge cells need the
+// clamp of 1 - z^2 at zero: with the offset off = sh - floor(w/2) - f in
+// (sh - floor(w/2) - 1, sh - floor(w/2)], sh in {0, 1}, the cells k = 1 ..
+// w - 2 have |off + k| <= floor((w - 1) / 2) < w / 2, so |z| <= 1 - 1/w.
 template <int W>
 __device__ __forceinline__ void es_weights_hw(int sh, float f, float bl, float* ker) {
   const float off = (float)(sh - W / 2) - f;
@@ -49,7 +52,8 @@ __device__ __forceinline__ void es_weights_hw(int sh, float f, float bl, float* 
 #pragma unroll
   for (int k = 0; k < W; k++) {
     const float z = (off + (float)k) * s;
-    const float a = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+    float a = fmaf(-z, z, 1.0f);
+    if (k == 0 || k == W - 1) a = fmaxf(a, 0.0f);
     ker[k] = __builtin_amdgcn_exp2f(fmaf(bl, __builtin_amdgcn_sqrtf(a), -bl));
   }
 }
@@ -144,7 +148,7 @@ __host__ __device__ inline int plane_floats(int T0, int T1) {
 }
 
 // Rows of staged points in the spreading kernel: 64 per batch, then zero rows
-// so that the steps may read up to 15 rows past the last run start (row 63)
+// so that the steps, which read 16 points ahead, may reach row 64 + 15
 // without a bound check.
 constexpr int kSpreadStage = 80;
 
@@ -404,43 +408,47 @@ spread_mfma_kernel(const GeomArgs g, const float2* __restrict__ c, float* __rest
         flush(fm);
         pend = zr;
       }
-      // Two 4-point steps per iteration.  The operands of a step are read from
-      // LDS into the registers of the step 8 points earlier right after that
-      // step has used them, so the other step's work covers the read latency
-      // (scheduling barriers keep the reads where they are written).
-      // Reads may run past the run (other runs' points, or the zero rows at
-      // the end of the staging; every row read is finite) and past a step's
-      // run end the B operand is masked.
+      // Four 4-point steps per iteration.  The operands of step i are read
+      // from LDS into its registers 16 points ahead, right after the step has
+      // used them, so three other steps' work covers the read latency
+      // (scheduling barriers keep the reads where they are written, and the
+      // first reads are issued in the loop's order so that each step waits
+      // only for its own).  Full iterations need no mask; the last 1 .. 15
+      // points of a run take masked steps.  Reads may run past the run (other
+      // runs' points, or the zero rows at the end of the staging; the
+      // furthest is row q1 - 1 + 16 <= 79, and every row read is finite).
       const float* px = skx + ox;   // + 8 q: x weight of this lane's row
       const float* pz = skz + oz;   // + 8 q: its two ring-slot weights
       const float* pb = sb + ob;    // + 16 q: its B column
-      float axA = px[8 * q0], bvA = pb[16 * q0];
-      float2 kzA = *reinterpret_cast<const float2*>(pz + 8 * q0);
-      // (the first step's reads are issued first, so that waiting for them
-      // leaves the second step's in flight)
-      __builtin_amdgcn_sched_barrier(0);
-      float axB = px[8 * q0 + 32], bvB = pb[16 * q0 + 64];
-      float2 kzB = *reinterpret_cast<const float2*>(pz + 8 * q0 + 32);
-      for (int q = q0; q < q1; q += 8) {
-        {
-          const float bv = kg < q1 - q ? bvA : 0.f;
-          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axA * kzA.x, bv, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axA * kzA.y, bv, acc[1], 0, 0, 0);
-        }
-        int qa = q + 8;
-        axA = px[8 * qa];
-        kzA = *reinterpret_cast<const float2*>(pz + 8 * qa);
-        bvA = pb[16 * qa];
+      float ax[4], bv[4];
+      float2 kz[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        ax[i] = px[8 * q0 + 32 * i];
+        kz[i] = *reinterpret_cast<const float2*>(pz + 8 * q0 + 32 * i);
+        bv[i] = pb[16 * q0 + 64 * i];
         __builtin_amdgcn_sched_barrier(0);
-        if (q + 4 < q1) {
-          const float bv = kg < q1 - q - 4 ? bvB : 0.f;
-          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(axB * kzB.x, bv, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(axB * kzB.y, bv, acc[1], 0, 0, 0);
+      }
+      int q = q0;
+      for (; q + 16 <= q1; q += 16) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[i] * kz[i].x, bv[i], acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[i] * kz[i].y, bv[i], acc[1], 0, 0, 0);
+          const int qa = q + 16;
+          ax[i] = px[8 * qa + 32 * i];
+          kz[i] = *reinterpret_cast<const float2*>(pz + 8 * qa + 32 * i);
+          bv[i] = pb[16 * qa + 64 * i];
+          __builtin_amdgcn_sched_barrier(0);
         }
-        axB = px[8 * qa + 32];
-        kzB = *reinterpret_cast<const float2*>(pz + 8 * qa + 32);
-        bvB = pb[16 * qa + 64];
-        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        if (q + 4 * i < q1) {
+          const float b = kg < q1 - q - 4 * i ? bv[i] : 0.f;
+          acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[i] * kz[i].x, b, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ax[i] * kz[i].y, b, acc[1], 0, 0, 0);
+        }
       }
     }
   }
