@@ -624,20 +624,33 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
       int qp = qs - qstride;   // the pending step (none before the first)
       auto finish = [&](float re, float im, int qb) {
         // the lower half of the wave sums re over lane groups (0, 2) and
-        // (1, 3), the upper half im: each lane sends the part it does not
-        // keep to the lane 32 away
-        const bool lo = kq < 2;
-        const float u = (lo ? re : im) + __shfl_xor(lo ? im : re, 32);
-        // every row of 16 lanes then adds its neighbour row
-        const float v = u + __shfl_xor(u, 16);
+        // (1, 3), the upper half im: one swap of re's upper 32 lanes with
+        // im's lower 32 (v_permlane32_swap) leaves lane l < 32 with re(l) and
+        // re(l + 32), lane l >= 32 with im(l - 32) and im(l)
+        const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(re), __float_as_uint(im),
+                                                        false, false);
+        const float u = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+        // every row of 16 lanes then adds its neighbour row (odd rows swapped
+        // with even rows, v_permlane16_swap)
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(u), __float_as_uint(u),
+                                                        false, false);
+        const float v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
         const int pt = qb + n;
         // row 0 stores re, row 2 im
         if ((kq & 1) == 0 && pt >= q0 && pt < q1)
           reinterpret_cast<float*>(sout)[2 * pt + (kq >> 1)] = v;
       };
       for (int q = qs; q < q1; q += qstride) {
-        const float kxa = kxa_n, kxb = kxb_n, kz0 = kz0_n, kz4 = kz4_n;
+        // the step's B operands are formed before the next step's weights are
+        // read into the same registers
         const float ky[8] = {kya_n.x, kya_n.y, kya_n.z, kya_n.w, kyb_n.x, kyb_n.y, kyb_n.z, kyb_n.w};
+        float bop[16];
+#pragma unroll
+        for (int s = 0; s < 16; s++) bop[s] = ((s & 1) ? kxb_n : kxa_n) * ky[s >> 1];
+        const float kz0 = kz0_n, kz4 = kz4_n;
+        // (scheduling barriers keep the products, the next step's reads and
+        // the matrix work in this order, so the reads have the whole step)
+        __builtin_amdgcn_sched_barrier(0);
         {
           int qn = min(q + qstride, 64);
           opaque(qn);
@@ -649,11 +662,11 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
           kz4_n = wx[8 * qn + 1028];
           keep_order();
         }
+        __builtin_amdgcn_sched_barrier(0);
         v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 16; s++)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], ((s & 1) ? kxb : kxa) * ky[s >> 1],
-                                                     acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gop[s], bop[s], acc, 0, 0, 0);
         finish(rep, imp, qp);
         // the wait states before the results are read
         xdl_waits<kXdlToValuWaits>(acc);
