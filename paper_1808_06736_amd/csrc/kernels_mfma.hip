@@ -157,12 +157,20 @@ constexpr int kSpreadStage = 80;
 // row 79; rows past the batch only feed output columns that are not stored.
 constexpr int kInterpRows = 80;
 
+// Floats of the interpolation kernel's staging area: the staged weights, or,
+// while the bin's grid tile is read, a table of two ints per tile row.
+__host__ __device__ inline int interp_stage_floats(int T1, int T2) {
+  const int w = (2 * 64 + kInterpRows) * 8;
+  return 2 * T1 * T2 > w ? 2 * T1 * T2 : w;
+}
+
 // LDS layouts.  Both start with the bin tile (bin + 6 cells per dim, planes of
 // plane_floats) and end with the wrapped grid offsets of the tile's z planes
 // (int64), per-point ints and the offsets of the tile's x and y lines.
-// Spreading stages [67][8] x and z weights and [67][16] B operands;
-// interpolation [64][8] x and y weights, [80][8] z weights and a float2 result
-// per point.
+// Spreading stages [80][8] x and z weights and [80][16] B operands;
+// interpolation [64][8] x and y weights and [80][8] z weights (an area that
+// first holds the table of tile rows, sized for both) and a float2 result per
+// point.
 static inline size_t mfma_tail_bytes(const int* b, int nint) {
   const size_t T0 = b[0] + 6, T1 = b[1] + 6, T2 = b[2] + 6;
   return T2 * sizeof(int64_t) + (size_t)nint * 64 * sizeof(int) + (T0 + T1) * sizeof(int);
@@ -180,7 +188,7 @@ size_t mfma_spread_lds_bytes(int w, const int* b) {
 }
 
 size_t mfma_interp_lds_bytes(const int* b) {
-  return mfma_tile_bytes(b) + (2 * 64 + kInterpRows) * 8 * sizeof(float) +
+  return mfma_tile_bytes(b) + (size_t)interp_stage_floats(b[1] + 6, b[2] + 6) * sizeof(float) +
          64 * sizeof(float2) + mfma_tail_bytes(b, 2);
 }
 
@@ -491,13 +499,13 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   const int b0 = g.b[0], b1 = g.b[1], b2 = g.b[2];
   // 8-wide footprints from even window cells of the bin (even bin sizes)
   const int T0 = b0 + 6, T1 = b1 + 6, T2 = b2 + 6;
-  const int tc = T0 * T1 * T2;
   const int ps = plane_floats(T0, T1);               // floats per tile plane
   float* gtf = reinterpret_cast<float*>(smem_raw);                 // [T2][ps]: [T1][T0][2]
   float* skx = gtf + T2 * ps;                                      // [64][8] x slots
   float* sky = skx + 64 * 8;                                       // [64][8] y slots
   float* skz = sky + 64 * 8;                                       // [80][8] z slots
-  float2* sout = reinterpret_cast<float2*>(skz + kInterpRows * 8); // [64] results
+  // [64] results, after the staging area (the weights, or the row table)
+  float2* sout = reinterpret_cast<float2*>(skx + interp_stage_floats(T1, T2));
   int64_t* gz = reinterpret_cast<int64_t*>(sout + 64);             // [T2]
   int* sorg = reinterpret_cast<int*>(gz + T2);                     // [64] footprint origin
   int* sperm = sorg + 64;                                          // [64]
@@ -527,23 +535,35 @@ interp_mfma_kernel(const GeomArgs g, const float2* __restrict__ grid, float2* __
   tile_offsets(tid, 128, T0, T1, T2, bx0 - H, by0 - H, bz0 - H, n0, n1, n2, gx, gy, gz);
   __syncthreads();
   {
-    // the bin's grid tile, 4 cells per thread in flight at a time
+    // the bin's grid tile, by tile rows (y, z): lanes 16 j .. 16 j + 15 of the
+    // block read x cells x0 .. x0 + 15 of rows j, j + 8, ..., four rows in
+    // flight per thread.  Each row's grid offset (fine grids hold under 2^31
+    // cells) and float offset in the tile come from a table built in the
+    // staging area, which the first batch overwrites only after a barrier.
+    const int nrow = T1 * T2;
+    int* rowg = reinterpret_cast<int*>(skx);   // [nrow] gz[z] + gy[y]
+    int* rowt = rowg + nrow;                    // [nrow] z ps + 2 y T0
+    for (int r = tid; r < nrow; r += 128) {
+      const int iy = r % T1, iz = r / T1;
+      rowg[r] = (int)(gz[iz] + gy[iy]);
+      rowt[r] = iz * ps + 2 * iy * T0;
+    }
+    __syncthreads();
     constexpr int U = 4;
-    TileWalk tw(tid, 128, T0, T1);
-    for (int i0 = 0; i0 < tc; i0 += 128 * U) {
-      float2 v[U];
-      int o[U];
+    const int lx = tid & 15;
+    for (int x0 = 0; x0 < T0; x0 += 16) {
+      const int ix = x0 + lx;
+      const int gxi = gx[min(ix, T0 - 1)];
+      for (int rb = tid >> 4; rb < nrow; rb += 8 * U) {
+        float2 v[U];
+        // (rows past the last are read at the last row and not stored)
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        // past the tile's last cell the walk runs on in z; the load then
-        // stays on the last plane and its value is not stored
-        o[u] = tw.ofs(ps);
-        v[u] = grid[gz[min(tw.iz, T2 - 1)] + gy[tw.iy] + gx[tw.ix]];
-        tw.next();
+        for (int u = 0; u < U; u++) v[u] = grid[rowg[min(rb + 8 * u, nrow - 1)] + gxi];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          if (ix < T0 && rb + 8 * u < nrow)
+            *reinterpret_cast<float2*>(gtf + rowt[rb + 8 * u] + 2 * ix) = v[u];
       }
-#pragma unroll
-      for (int u = 0; u < U; u++)
-        if (i0 + 128 * u + tid < tc) *reinterpret_cast<float2*>(gtf + o[u]) = v[u];
     }
   }
 
